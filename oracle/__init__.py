@@ -1,0 +1,201 @@
+"""CPU float64 oracle of the cost-model hot path (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+use this package. It is a ctypes wrapper over ``oracle.c`` (plain C, float64,
+no BLAS), built with gcc on first use, plus the synthetic runtime model that
+stands in for measured runtimes. It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NFEAT = 32
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math,
+    no FMA contraction, OpenMP over kernels in the rank routine)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+               _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64 = C.c_int64
+        lib.oracle_featurize.argtypes = [P, P, i64, i64, P, P]
+        lib.oracle_featurize.restype = None
+        lib.oracle_zscore_fit.argtypes = [P, i64, P, P]
+        lib.oracle_zscore_fit.restype = None
+        lib.oracle_normalize.argtypes = [P, i64, P, P, P]
+        lib.oracle_normalize.restype = None
+        lib.oracle_forward.argtypes = [P, C.c_int, P, C.c_int, P, i64, P]
+        lib.oracle_forward.restype = C.c_int
+        lib.oracle_argmin.argtypes = [P, P, P, i64, P]
+        lib.oracle_argmin.restype = None
+        lib.oracle_topn.argtypes = [P, P, P, i64, C.c_int, P]
+        lib.oracle_topn.restype = None
+        lib.oracle_mse.argtypes = [P, P, i64]
+        lib.oracle_mse.restype = C.c_double
+        lib.oracle_loss_grad.argtypes = [P, C.c_int, P, C.c_int, P, P, i64, P, P]
+        lib.oracle_loss_grad.restype = C.c_int
+        lib.oracle_l2norm.argtypes = [P, i64]
+        lib.oracle_l2norm.restype = C.c_double
+        lib.oracle_adam.argtypes = [P, P, P, P, i64, i64, C.c_double, C.c_double, C.c_double,
+                                    C.c_double]
+        lib.oracle_adam.restype = None
+        lib.oracle_rank.argtypes = [P, P, P, i64, i64, P, C.c_int, P, P, P, P, P, C.c_int]
+        lib.oracle_rank.restype = C.c_int
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+ACT = {"relu": 0, "identity": 1}
+
+
+def featurize(kdesc, vdesc):
+    kd, vd = _c(kdesc, np.int64), _c(vdesc, np.int64)
+    n = vd.shape[0]
+    feat = np.zeros((n, NFEAT), dtype=np.int64)
+    inv = np.zeros(n, dtype=np.uint8)
+    _load().oracle_featurize(_p(kd), _p(vd), kd.shape[0], n, _p(feat), _p(inv))
+    return feat, inv
+
+
+def zscore_fit(feat):
+    f = _c(feat, np.int64)
+    mu = np.zeros(NFEAT)
+    sd = np.zeros(NFEAT)
+    _load().oracle_zscore_fit(_p(f), f.shape[0], _p(mu), _p(sd))
+    return mu, sd
+
+
+def normalize(feat, mu, sigma):
+    f = _c(feat, np.int64)
+    x = np.zeros((f.shape[0], NFEAT))
+    _load().oracle_normalize(_p(f), f.shape[0], _p(_c(mu, np.float64)),
+                             _p(_c(sigma, np.float64)), _p(x))
+    return x
+
+
+def _widths(widths):
+    return _c(widths, np.int32)
+
+
+def forward(widths, params, x, act="relu"):
+    w = _widths(widths)
+    p = _c(params, np.float64)
+    xx = _c(x, np.float64)
+    y = np.zeros(xx.shape[0])
+    rc = _load().oracle_forward(_p(w), w.size, _p(p), ACT[act], _p(xx), xx.shape[0], _p(y))
+    if rc:
+        raise ValueError("oracle_forward: bad widths (%d)" % rc)
+    return y
+
+
+def argmin(pred, offsets, invalid=None):
+    pr = _c(pred, np.float64)
+    off = _c(offsets, np.int64)
+    inv = None if invalid is None else _c(invalid, np.uint8)
+    best = np.zeros(off.size - 1, dtype=np.int64)
+    _load().oracle_argmin(_p(pr), _p(inv), _p(off), off.size - 1, _p(best))
+    return best
+
+
+def topn(pred, offsets, N, invalid=None):
+    pr = _c(pred, np.float64)
+    off = _c(offsets, np.int64)
+    inv = None if invalid is None else _c(invalid, np.uint8)
+    out = np.zeros((off.size - 1, N), dtype=np.int64)
+    _load().oracle_topn(_p(pr), _p(inv), _p(off), off.size - 1, int(N), _p(out))
+    return out
+
+
+def mse(pred, y):
+    a, b = _c(pred, np.float64), _c(y, np.float64)
+    return _load().oracle_mse(_p(a), _p(b), a.size)
+
+
+def rmse(pred, y):
+    """Root mean square error between predicted and true runtimes."""
+    return float(np.sqrt(mse(pred, y)))
+
+
+def nrmse(pred, y, y_min=None, y_max=None):
+    """RMSE divided by the range of the true values (the paper's
+    normalization; the range may be given explicitly)."""
+    y = np.asarray(y, dtype=np.float64)
+    lo = float(np.min(y)) if y_min is None else float(y_min)
+    hi = float(np.max(y)) if y_max is None else float(y_max)
+    return rmse(pred, y) / (hi - lo)
+
+
+def loss_grad(widths, params, x, y, act="relu"):
+    w = _widths(widths)
+    p = _c(params, np.float64)
+    xx, yy = _c(x, np.float64), _c(y, np.float64)
+    g = np.zeros_like(p)
+    loss = C.c_double(0.0)
+    rc = _load().oracle_loss_grad(_p(w), w.size, _p(p), ACT[act], _p(xx), _p(yy), xx.shape[0],
+                                  _p(g), C.byref(loss))
+    if rc:
+        raise ValueError("oracle_loss_grad failed (%d)" % rc)
+    return loss.value, g
+
+
+def l2norm(g):
+    gg = _c(g, np.float64)
+    return _load().oracle_l2norm(_p(gg), gg.size)
+
+
+def adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays w, m, v."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    gg = _c(g, np.float64)
+    _load().oracle_adam(_p(w), _p(m), _p(v), _p(gg), w.size, int(t), lr, b1, b2, eps)
+
+
+def rank(kdesc, vdesc, offsets, widths, params, mu, sigma, n_threads=0, want_pred=True):
+    kd, vd, off = _c(kdesc, np.int64), _c(vdesc, np.int64), _c(offsets, np.int64)
+    w = _widths(widths)
+    p = _c(params, np.float64)
+    best = np.zeros(off.size - 1, dtype=np.int64)
+    pred = np.zeros(vd.shape[0]) if want_pred else None
+    rc = _load().oracle_rank(_p(kd), _p(vd), _p(off), off.size - 1, vd.shape[0], _p(w), w.size,
+                             _p(p), _p(_c(mu, np.float64)), _p(_c(sigma, np.float64)),
+                             _p(best), _p(pred), int(n_threads))
+    if rc:
+        raise ValueError("oracle_rank failed (%d)" % rc)
+    return best, pred
+
+
+def max_threads():
+    return _load().oracle_max_threads()
