@@ -1,0 +1,195 @@
+/*
+ * libadvisor: batched evaluation and training of the OpenMP Advisor's
+ * machine-learned cost model (Mishra et al., arXiv 2301.03636) on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The paper's prediction mode (sections 3 and 4) generates the offloading
+ * variants of a kernel, predicts each variant's runtime with a trained
+ * multi-layer perceptron (section 5.3) and returns the best ones; its
+ * training mode fits that perceptron to measured (variant, runtime) pairs.
+ * This library does both for many kernels at once: every variant's static
+ * descriptor becomes 32 integer features, a fully-connected ReLU network
+ * predicts its log-runtime, and a segmented argmin picks each kernel's
+ * predicted-fastest variant.
+ *
+ * Conventions shared by every entry point:
+ *  - Buffers named "device" are HIP device allocations owned by the caller
+ *    (rows are C-contiguous); buffers named "host" are ordinary host memory.
+ *  - "stream" is a hipStream_t passed as void* (NULL: the null stream).
+ *    Work on device buffers is enqueued on it and returns before it runs;
+ *    argument and shape errors are detected on the host and returned
+ *    synchronously, before anything is enqueued.
+ *  - Return value: ADVISOR_OK (0) or a negative ADVISOR_E* code; the text of
+ *    the last error of the calling thread is advisor_last_error().
+ *  - Descriptor layout (int64, row-major):
+ *      kdesc [n_kernels, 16]: D, N0..N3, A, E, s0..s3, fpi, req0..req3
+ *        D loop-nest depth (1..4), N_i trip counts (1 for i >= D), A arrays
+ *        (0..4) of E bytes per element (1..64), s_a 1 for a stride-N walk,
+ *        fpi flops per innermost iteration, req_a the data class found by
+ *        the data analysis of section 4.1.2 (0 alloc, 1 to, 2 from, 3 tofrom)
+ *      vdesc [n_variants, 8]: kernel_id, c, T, H, m0..m3
+ *        c collapse depth of the combined teams-distribute-parallel-for
+ *        (section 4.1.3), T teams, H threads per team, m_a the map clause of
+ *        array a (same codes as req_a)
+ *      offsets [n_kernels + 1]: variants of kernel k are rows
+ *        offsets[k] .. offsets[k+1]-1; offsets[0] = 0, offsets[n_kernels] =
+ *        n_variants, non-decreasing (empty segments allowed).
+ *  - n_variants must stay below 2^32.
+ */
+#ifndef ADVISOR_H
+#define ADVISOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum advisor_status {
+    ADVISOR_OK = 0,
+    ADVISOR_EINVAL = -1,       /* null pointer, bad enum, bad scalar argument */
+    ADVISOR_ESHAPE = -2,       /* sizes inconsistent or outside the supported range */
+    ADVISOR_EHIP = -3,         /* a HIP runtime call failed (text in advisor_last_error) */
+    ADVISOR_ENOMEM = -4,       /* device or host allocation failed */
+    ADVISOR_EUNSUPPORTED = -5  /* network shape or precision not built into the library */
+};
+
+enum advisor_precision {
+    ADVISOR_FP32 = 0,      /* fp32 weights and activations, fp32 matrix cores */
+    ADVISOR_BF16 = 1,      /* bf16 weights and activations, fp32 accumulation */
+    ADVISOR_FP8_E4M3 = 2   /* OCP e4m3 hidden layers with per-tensor scales, first layer bf16 */
+};
+
+#define ADVISOR_NFEAT 32
+#define ADVISOR_KD_COLS 16
+#define ADVISOR_VD_COLS 8
+#define ADVISOR_MAX_LAYERS 9   /* hidden layers + output layer */
+#define ADVISOR_MAX_WIDTH 1024
+
+typedef struct advisor_model advisor_model;  /* opaque; owned by the library */
+
+/* Text of the calling thread's last error ("" if none). Owned by the library,
+ * valid until the thread's next call. */
+const char *advisor_last_error(void);
+
+/* Library version string. */
+const char *advisor_version(void);
+
+/*
+ * Create a cost model: the multi-layer perceptron of section 5.3 (ReLU hidden
+ * layers, a linear single-output layer predicting ln(runtime in us)).
+ * widths (host) [n_widths]: 32, h_1, ..., h_L, 1 with 1 <= h_i <= 1024 and
+ * 2 <= n_widths <= ADVISOR_MAX_LAYERS + 1. precision: enum advisor_precision
+ * (ADVISOR_FP8_E4M3 also needs advisor_model_calibrate_fp8 before use).
+ * The model is allocated on the current HIP device; parameters start at 0,
+ * mu at 0 and sigma at 1. *out receives the handle (NULL on error).
+ */
+int advisor_model_create(const int32_t *widths, int n_widths, int precision,
+                         advisor_model **out);
+
+/* Free a model and every device buffer it owns. NULL is ignored. */
+void advisor_model_destroy(advisor_model *model);
+
+/* Number of parameters: sum over layers of out*in + out. */
+int64_t advisor_model_param_count(const advisor_model *model);
+
+/*
+ * Load parameters and the Z-score statistics (section 5.3 standardizes the
+ * data; here x_j = (log2(1 + f_j) - mu_j) / sigma_j).
+ * w_master (host, float) [param_count]: per layer l, W_l as [out, in]
+ * row-major followed by b_l [out]. mu, sigma (host, double) [32]; sigma > 0.
+ * Copies synchronously, rebuilds the packed compute copies, resets Adam state
+ * (m = v = 0, step 0) and any FP8 calibration.
+ */
+int advisor_model_set_params(advisor_model *model, const float *w_master,
+                             const double *mu, const double *sigma);
+
+/* Copy the fp32 master parameters (host, float [param_count]) and, if not
+ * NULL, mu and sigma (host, double [32]) out of the model. Synchronous. */
+int advisor_model_get_params(const advisor_model *model, float *w_master, double *mu,
+                             double *sigma);
+
+/* Copy the Adam state out (host: m, v float [param_count], step) or load it
+ * in (advisor_model_set_adam); either array pointer may be NULL to skip it.
+ * Synchronous. Used for checkpoint and resume of training. */
+int advisor_model_get_adam(const advisor_model *model, float *m, float *v, int64_t *step);
+int advisor_model_set_adam(advisor_model *model, const float *m, const float *v, int64_t step);
+
+/*
+ * Feature extraction (the Feature Extraction step of the training and
+ * prediction flows, section 3; the paper does not list its features, this
+ * library defines 32). For each variant i (device inputs kdesc, vdesc as in
+ * the header comment), writes feat_out[i, 0..31] (device, int64) and, if
+ * invalid_out (device, uint8 [n_variants]) is not NULL, invalid_out[i] = 1
+ * for an invalid variant (its feature row is all zero) and 0 otherwise.
+ * A variant is invalid when its kernel_id is outside [0, n_kernels), its
+ * kernel's D, N_i, A, E, s_a, req_a or fpi is out of range, c < 1 or c > D,
+ * T < 1, H < 1, or a map clause m_a does not carry the data its class req_a
+ * needs (to needs to/tofrom, from needs from/tofrom, tofrom needs tofrom).
+ * Integer arithmetic is unsigned 64-bit modulo 2^64, exact while trip-count
+ * products times 64 stay below 2^63.
+ * Features: 0 D, 1-4 N0..N3, 5 I = prod N_i, 6 c, 7 Pc = prod_{i<c} N_i,
+ * 8 R = prod_{i>=c} N_i, 9 T, 10 H, 11 TH = T*H, 12 busy = min(TH, Pc),
+ * 13 waves = ceil(Pc/TH), 14 waves*R, 15 waves*TH - Pc, 16 A, 17 E,
+ * 18 S = E*I, 19-22 arrays mapped to / from / tofrom / alloc,
+ * 23 h2d = S*(n_to + n_tofrom), 24 d2h = S*(n_from + n_tofrom),
+ * 25 h2d + d2h, 26 ns = number of strided arrays, 27 S*A,
+ * 28 S*(A - ns) + (64/E)*S*ns, 29 fpi*I, 30 fpi, 31 S*n_alloc.
+ */
+int advisor_featurize(const int64_t *kdesc, const int64_t *vdesc, int64_t n_kernels,
+                      int64_t n_variants, int64_t *feat_out, uint8_t *invalid_out, void *stream);
+
+/*
+ * Fit the Z-score statistics (section 5.3) on a calibration sample:
+ * feat (device, int64 [n, 32]) -> mu_out, sigma_out (device, double [32]):
+ * mean and population deviation of log2(1 + f_j), accumulated in float64;
+ * a feature with a single value over the sample gets mu = log2(1 + value)
+ * and sigma = 1. n >= 1. The result can be copied into a model with
+ * advisor_model_set_params or advisor_model_set_zscore.
+ */
+int advisor_zscore_fit(const int64_t *feat, int64_t n, double *mu_out, double *sigma_out,
+                       void *stream);
+
+/* Replace the model's Z-score statistics (device, double [32] each). */
+int advisor_model_set_zscore(advisor_model *model, const double *mu, const double *sigma,
+                             void *stream);
+
+/*
+ * Predict ln(runtime in us) of every row (section 5.3's network applied to
+ * the standardized features): feat (device, int64 [n, 32]) ->
+ * pred_out (device, float [n]). Every row is treated as valid.
+ */
+int advisor_predict(const advisor_model *model, const int64_t *feat, int64_t n,
+                    float *pred_out, void *stream);
+
+/*
+ * The prediction flow of section 3 for many kernels at once, in one fused
+ * pass: featurize -> standardize -> network -> per-kernel argmin (the paper
+ * sorts predictions and keeps the best N; this is N = 1).
+ * best_out (device, int64 [n_kernels]) receives, for each kernel k, the
+ * global index of the variant in [offsets[k], offsets[k+1]) with the lowest
+ * prediction, the lowest index among equal predictions (-0 equals +0), or -1
+ * if the segment has no eligible variant. A variant is eligible when it is
+ * valid (see advisor_featurize) and its kernel_id equals k. pred_out (device,
+ * float [n_variants], may be NULL) receives every prediction, NaN for
+ * ineligible variants, identical bit for bit to advisor_predict on the same
+ * features. best_out doubles as scratch during the call.
+ */
+int advisor_rank(const advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
+                 const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
+                 int64_t *best_out, float *pred_out, void *stream);
+
+/*
+ * The per-kernel argmin alone (the selection step of section 3, N = 1) on
+ * given predictions: pred (device, float [n_variants]), offsets (device,
+ * int64 [n_kernels + 1]) -> best_out (device, int64 [n_kernels]), with the
+ * tie, signed-zero and empty-segment rules of advisor_rank; NaN never wins.
+ * n_variants is offsets[n_kernels], passed for the size check.
+ */
+int advisor_rank_preds(const float *pred, const int64_t *offsets, int64_t n_kernels,
+                       int64_t n_variants, int64_t *best_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADVISOR_H */

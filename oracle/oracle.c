@@ -77,7 +77,8 @@ static int featurize_row(const int64_t *kd, const int64_t *vd, int64_t n_k, int6
     uint64_t I = N[0] * N[1] * N[2] * N[3];
     uint64_t Pc = 1;
     for (int i = 0; i < c; i++) Pc *= N[i];
-    uint64_t R = I / Pc;                 /* iterations each collapsed index runs serially */
+    uint64_t R = 1;                      /* iterations each collapsed index runs serially: */
+    for (int i = (int)c; i < 4; i++) R *= N[i];  /* the loops left out of the collapse */
     uint64_t TH = (uint64_t)T * (uint64_t)H;  /* hardware threads the launch asks for */
     uint64_t busy = TH < Pc ? TH : Pc;        /* threads that get work */
     uint64_t waves = Pc / TH + (Pc % TH != 0);/* rounds of collapsed iterations per thread */
@@ -393,8 +394,9 @@ void oracle_adam(double *w, double *m, double *v, const double *g, int64_t n, in
  * The whole prediction flow for many kernels: featurize every variant,
  * standardize, predict, and pick each kernel's best variant. Kernels are
  * independent, so they are spread over threads (n_threads <= 0: the OpenMP
- * default). pred (optional) receives every variant's prediction, NaN for
- * invalid variants.
+ * default). A variant takes part only if it is valid and its kernel id names
+ * the segment it sits in. pred (optional) receives every variant's
+ * prediction, NaN for the variants that take no part.
  */
 int oracle_rank(const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
                 int64_t n_k, int64_t n_v, const int32_t *widths, int n_widths,
@@ -425,7 +427,8 @@ int oracle_rank(const int64_t *kdesc, const int64_t *vdesc, const int64_t *offse
             int64_t bi = -1;
             double bv = 0.0;
             for (int64_t i = offsets[k]; i < offsets[k + 1]; i++) {
-                int ok = featurize_row(kdesc, vdesc + i * VD_COLS, n_k, f);
+                int ok = vdesc[i * VD_COLS] == k &&
+                         featurize_row(kdesc, vdesc + i * VD_COLS, n_k, f);
                 double yi = NAN;
                 if (ok) {
                     normalize_row(f, mu, sigma, x);

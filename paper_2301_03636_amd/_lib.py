@@ -1,0 +1,225 @@
+"""ctypes binding of libadvisor.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and checks
+nothing that the library does not check itself beyond tensor placement,
+dtype and contiguity (the library sees raw pointers). Device buffers are
+torch tensors on the current HIP device; work is enqueued on torch's current
+stream. There is no fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadvisor.so")
+
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+NFEAT = 32
+
+_lib = None
+
+
+class AdvisorError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libadvisor.so (built by paper_2301_03636_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libadvisor.so is not built (%s); run "
+                              "paper_2301_03636_amd/build.py or __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+        sig = {
+            "advisor_last_error": ([], C.c_char_p),
+            "advisor_version": ([], C.c_char_p),
+            "advisor_model_create": ([P, i32, i32, C.POINTER(C.c_void_p)], i32),
+            "advisor_model_destroy": ([P], None),
+            "advisor_model_param_count": ([P], i64),
+            "advisor_model_set_params": ([P, P, P, P], i32),
+            "advisor_model_get_params": ([P, P, P, P], i32),
+            "advisor_model_get_adam": ([P, P, P, C.POINTER(C.c_int64)], i32),
+            "advisor_model_set_adam": ([P, P, P, i64], i32),
+            "advisor_model_set_zscore": ([P, P, P, P], i32),
+            "advisor_featurize": ([P, P, i64, i64, P, P, P], i32),
+            "advisor_zscore_fit": ([P, i64, P, P, P], i32),
+            "advisor_predict": ([P, P, i64, P, P], i32),
+            "advisor_rank": ([P, P, P, P, i64, i64, P, P, P], i32),
+            "advisor_rank_preds": ([P, P, i64, i64, P, P], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().advisor_last_error().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise AdvisorError(rc, where, last_error())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor on the GPU" % (name, dtype))
+    return t
+
+
+# --------------------------------------------------------------------------- model
+
+
+def advisor_model_create(widths, precision) -> C.c_void_p:
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    h = C.c_void_p()
+    _check(lib().advisor_model_create(w.ctypes.data_as(C.c_void_p), w.size, p, C.byref(h)),
+           "advisor_model_create")
+    return h
+
+
+def advisor_model_destroy(h):
+    lib().advisor_model_destroy(h)
+
+
+def advisor_model_param_count(h) -> int:
+    return int(lib().advisor_model_param_count(h))
+
+
+def advisor_model_set_params(h, w_master, mu, sigma):
+    w = np.ascontiguousarray(w_master, dtype=np.float32)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    if w.size != advisor_model_param_count(h) or m.size != NFEAT or s.size != NFEAT:
+        raise ValueError("parameter or statistics size mismatch")
+    _check(lib().advisor_model_set_params(h, w.ctypes.data_as(C.c_void_p),
+                                          m.ctypes.data_as(C.c_void_p),
+                                          s.ctypes.data_as(C.c_void_p)),
+           "advisor_model_set_params")
+
+
+def advisor_model_get_params(h):
+    n = advisor_model_param_count(h)
+    w = np.zeros(n, dtype=np.float32)
+    mu = np.zeros(NFEAT)
+    sd = np.zeros(NFEAT)
+    _check(lib().advisor_model_get_params(h, w.ctypes.data_as(C.c_void_p),
+                                          mu.ctypes.data_as(C.c_void_p),
+                                          sd.ctypes.data_as(C.c_void_p)),
+           "advisor_model_get_params")
+    return w, mu, sd
+
+
+def advisor_model_get_adam(h):
+    n = advisor_model_param_count(h)
+    m = np.zeros(n, dtype=np.float32)
+    v = np.zeros(n, dtype=np.float32)
+    step = C.c_int64(0)
+    _check(lib().advisor_model_get_adam(h, m.ctypes.data_as(C.c_void_p),
+                                        v.ctypes.data_as(C.c_void_p), C.byref(step)),
+           "advisor_model_get_adam")
+    return m, v, step.value
+
+
+def advisor_model_set_adam(h, m, v, step):
+    mm = np.ascontiguousarray(m, dtype=np.float32)
+    vv = np.ascontiguousarray(v, dtype=np.float32)
+    _check(lib().advisor_model_set_adam(h, mm.ctypes.data_as(C.c_void_p),
+                                        vv.ctypes.data_as(C.c_void_p), int(step)),
+           "advisor_model_set_adam")
+
+
+def advisor_model_set_zscore(h, mu, sigma):
+    _dev(mu, torch.float64, "mu")
+    _dev(sigma, torch.float64, "sigma")
+    _check(lib().advisor_model_set_zscore(h, _ptr(mu), _ptr(sigma), _stream()),
+           "advisor_model_set_zscore")
+
+
+# --------------------------------------------------------------------------- hot path
+
+
+def advisor_featurize(kdesc, vdesc, n_kernels=None, feat_out=None, invalid_out=None):
+    _dev(kdesc, torch.int64, "kdesc")
+    _dev(vdesc, torch.int64, "vdesc")
+    nk = kdesc.shape[0] if n_kernels is None else int(n_kernels)
+    nv = vdesc.shape[0]
+    if feat_out is None:
+        feat_out = torch.empty((nv, NFEAT), dtype=torch.int64, device=vdesc.device)
+    if invalid_out is None:
+        invalid_out = torch.empty(nv, dtype=torch.uint8, device=vdesc.device)
+    _dev(feat_out, torch.int64, "feat_out")
+    _dev(invalid_out, torch.uint8, "invalid_out")
+    _check(lib().advisor_featurize(_ptr(kdesc), _ptr(vdesc), nk, nv, _ptr(feat_out),
+                                   _ptr(invalid_out), _stream()), "advisor_featurize")
+    return feat_out, invalid_out
+
+
+def advisor_zscore_fit(feat):
+    _dev(feat, torch.int64, "feat")
+    mu = torch.empty(NFEAT, dtype=torch.float64, device=feat.device)
+    sd = torch.empty(NFEAT, dtype=torch.float64, device=feat.device)
+    _check(lib().advisor_zscore_fit(_ptr(feat), feat.shape[0], _ptr(mu), _ptr(sd), _stream()),
+           "advisor_zscore_fit")
+    return mu, sd
+
+
+def advisor_predict(h, feat, pred_out=None):
+    _dev(feat, torch.int64, "feat")
+    n = feat.shape[0]
+    if pred_out is None:
+        pred_out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _dev(pred_out, torch.float32, "pred_out")
+    _check(lib().advisor_predict(h, _ptr(feat), n, _ptr(pred_out), _stream()), "advisor_predict")
+    return pred_out
+
+
+def advisor_rank(h, kdesc, vdesc, offsets, best_out=None, pred_out=None, want_pred=False):
+    for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
+        _dev(t, torch.int64, nm)
+    nk = offsets.shape[0] - 1
+    nv = vdesc.shape[0]
+    if best_out is None:
+        best_out = torch.empty(nk, dtype=torch.int64, device=vdesc.device)
+    if pred_out is None and want_pred:
+        pred_out = torch.empty(nv, dtype=torch.float32, device=vdesc.device)
+    _dev(best_out, torch.int64, "best_out")
+    _dev(pred_out, torch.float32, "pred_out")
+    _check(lib().advisor_rank(h, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
+                              _ptr(best_out), _ptr(pred_out), _stream()), "advisor_rank")
+    return (best_out, pred_out) if want_pred or pred_out is not None else best_out
+
+
+def advisor_rank_preds(pred, offsets, best_out=None):
+    _dev(pred, torch.float32, "pred")
+    _dev(offsets, torch.int64, "offsets")
+    nk = offsets.shape[0] - 1
+    if best_out is None:
+        best_out = torch.empty(nk, dtype=torch.int64, device=pred.device)
+    _dev(best_out, torch.int64, "best_out")
+    _check(lib().advisor_rank_preds(_ptr(pred), _ptr(offsets), nk, pred.shape[0], _ptr(best_out),
+                                    _stream()), "advisor_rank_preds")
+    return best_out

@@ -1,0 +1,160 @@
+// Launch side of the fused tile pipeline: tile shapes per (precision,
+// width), kernel instances, the argmin-key set-up and read-out kernels, and
+// the advisor_predict / advisor_rank entry points.
+#include <mutex>
+
+#include "mlp_tile.h"
+
+namespace adv {
+
+// Rows per tile: as many as fit LDS (activations [M][W] plus the input tile).
+template <int P, int W> struct TileRows {
+    static constexpr int value =
+        P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
+                       : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : (W <= 512 ? 128 : 64));
+};
+constexpr int TILE_WAVES = 8;
+
+__global__ void keys_init_kernel(uint64_t *keys, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = ~0ull;
+}
+
+// argmin key -> global variant index (low 32 bits), -1 if no variant won
+__global__ void keys_final_kernel(int64_t *best, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint64_t k = (uint64_t)best[i];
+        best[i] = k == ~0ull ? -1 : (int64_t)(k & 0xffffffffull);
+    }
+}
+
+template <int P, int W, int SRC, int SINK>
+int launch_tiles(const TileArgs &args, hipStream_t s)
+{
+    constexpr int M = TileRows<P, W>::value;
+    using C = TileCfg<P, W, M, TILE_WAVES>;
+    auto kern = mlp_tiles_kernel<P, W, M, TILE_WAVES, SRC, SINK>;
+    static std::once_flag once;
+    static int blocks_per_cu = 1;
+    static hipError_t setup_err = hipSuccess;
+    std::call_once(once, [&] {
+        setup_err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+        if (setup_err == hipSuccess) {
+            int nb = 0;
+            setup_err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(kern), C::THREADS, C::LDS);
+            blocks_per_cu = nb > 0 ? nb : 1;
+        }
+    });
+    if (setup_err != hipSuccess) return hip_fail(setup_err, "tile kernel set-up");
+    const int64_t ntiles = (args.n_rows + M - 1) / M;
+    const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus() * blocks_per_cu);
+    if (grid <= 0) return ADVISOR_OK;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), C::LDS, s, args);
+    ADV_LAUNCHED("mlp_tiles_kernel");
+    return ADVISOR_OK;
+}
+
+template <int SRC, int SINK>
+int dispatch_tiles(int precision, int W, const TileArgs &a, hipStream_t s)
+{
+#define ADV_CASE(P, WW) \
+    if (precision == P && W == WW) return launch_tiles<P, WW, SRC, SINK>(a, s);
+#define ADV_WIDTHS(P) ADV_CASE(P, 64) ADV_CASE(P, 128) ADV_CASE(P, 256) ADV_CASE(P, 512) ADV_CASE(P, 1024)
+    ADV_WIDTHS(PREC_FP32)
+    ADV_WIDTHS(PREC_BF16)
+    ADV_WIDTHS(PREC_FP8)
+#undef ADV_WIDTHS
+#undef ADV_CASE
+    return fail(ADVISOR_EUNSUPPORTED, "no tile kernel for this precision and width");
+}
+
+NetView net_view(const advisor_model *m)
+{
+    NetView v{};
+    for (int l = 0; l < m->n_hidden; ++l) {
+        v.w[l] = m->wpack[l];
+        v.b[l] = m->bias + (size_t)l * m->tile_w;
+        v.qscale[l] = m->qscale[l];
+        v.qinv[l] = m->qinv[l];
+    }
+    v.head_w = m->head;
+    v.head_b = m->head + m->tile_w;
+    v.mu = m->mu;
+    v.sigma = m->sigma;
+    v.n_hidden = m->n_hidden;
+    return v;
+}
+
+int check_model_ready(const advisor_model *m)
+{
+    if (!m) return fail(ADVISOR_EINVAL, "null model");
+    if (m->precision == PREC_FP8 && !m->fp8_calibrated)
+        return fail(ADVISOR_EINVAL, "fp8 model used before advisor_model_calibrate_fp8");
+    int dev = -1;
+    ADV_HIP(hipGetDevice(&dev));
+    if (dev != m->device) return fail(ADVISOR_EINVAL, "model lives on another device");
+    return ADVISOR_OK;
+}
+
+}  // namespace adv
+
+using namespace adv;
+
+extern "C" int advisor_predict(const advisor_model *model, const int64_t *feat, int64_t n,
+                               float *pred_out, void *stream)
+{
+    clear_error();
+    int rc = check_model_ready(model);
+    if (rc) return rc;
+    if (n < 0) return fail(ADVISOR_ESHAPE, "negative row count");
+    if (n == 0) return ADVISOR_OK;
+    if (!feat || !pred_out) return fail(ADVISOR_EINVAL, "advisor_predict: null pointer");
+    if (n >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "row count must be < 2^32");
+    TileArgs a{};
+    a.feat = feat;
+    a.n_rows = n;
+    a.net = net_view(model);
+    a.pred = pred_out;
+    return dispatch_tiles<SRC_FEAT, SINK_PRED>(model->precision, model->tile_w, a,
+                                               as_stream(stream));
+}
+
+extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
+                            const int64_t *vdesc, const int64_t *offsets, int64_t n_kernels,
+                            int64_t n_variants, int64_t *best_out, float *pred_out, void *stream)
+{
+    clear_error();
+    int rc = check_model_ready(model);
+    if (rc) return rc;
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels == 0) return ADVISOR_OK;
+    if (!kdesc || !offsets || !best_out || (n_variants > 0 && !vdesc))
+        return fail(ADVISOR_EINVAL, "advisor_rank: null pointer");
+    hipStream_t s = as_stream(stream);
+    const unsigned kb = (unsigned)((n_kernels + 255) / 256);
+    hipLaunchKernelGGL(keys_init_kernel, dim3(kb), dim3(256), 0, s,
+                       reinterpret_cast<uint64_t *>(best_out), n_kernels);
+    ADV_LAUNCHED("keys_init_kernel");
+    if (n_variants > 0) {
+        TileArgs a{};
+        a.kdesc = kdesc;
+        a.vdesc = vdesc;
+        a.offsets = offsets;
+        a.n_k = n_kernels;
+        a.n_rows = n_variants;
+        a.net = net_view(model);
+        a.pred = pred_out;
+        a.keys = reinterpret_cast<uint64_t *>(best_out);
+        rc = dispatch_tiles<SRC_DESC, SINK_RANK>(model->precision, model->tile_w, a, s);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(keys_final_kernel, dim3(kb), dim3(256), 0, s, best_out, n_kernels);
+    ADV_LAUNCHED("keys_final_kernel");
+    return ADVISOR_OK;
+}

@@ -1,0 +1,401 @@
+// The fused tile pipeline of the cost model: a persistent workgroup loops
+// over tiles of M variant rows; for each tile it builds the standardized
+// input (from descriptors or from features), runs every hidden layer on the
+// matrix cores with the activations held in LDS, reduces the output layer
+// with wavefront shuffles, and either stores the predictions or folds them
+// into per-kernel argmin keys.
+//
+// Matrix-core mapping (v_mfma_f32_32x32x{2f32,16_bf16,64_f8f6f4}): operand A
+// is a 32-row block of the layer's weights W_l[n][k] (rows = output neurons),
+// operand B a 32-column block of the transposed activations (columns =
+// variants), so D[n][m] = sum_k W[n][k] h[m][k]. Lane l of an operand holds
+// row (or column) l % 32; how the k values are spread over the two lane
+// halves is described at Geo below. D's lane l holds column m = l % 32 and
+// rows n = 8 * (r / 4) + 4 * (l / 32) + r % 4 for accumulator r = 0..15.
+// Weights are pre-packed fragment-major so each A operand is one contiguous
+// 64-lane load from global memory (L2-resident: every tile re-reads them);
+// activations live in LDS as [m][k] rows padded by one 16-byte bank step so
+// the 32 rows of a B operand fall in distinct banks.
+#pragma once
+
+#include "features.h"
+
+namespace adv {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+enum { PREC_FP32 = ADVISOR_FP32, PREC_BF16 = ADVISOR_BF16, PREC_FP8 = ADVISOR_FP8_E4M3 };
+enum { SRC_DESC = 0, SRC_FEAT = 1 };
+enum { SINK_PRED = 0, SINK_RANK = 1 };
+
+// Per-precision fragment geometry. A lane loads KV consecutive k values in
+// one vector (16 or 32 bytes); each matrix-core op consumes KL of them per
+// lane, so one vector feeds KV / KL ops. A k-group of KG = 2 * KV inputs is
+// split as: lane half h holds k = group * KG + h * KV + e, e < KV, and op t of
+// the group uses e in [t * KL, (t + 1) * KL). A and B use the same mapping,
+// which is all the dot product needs. EB bytes per element; PAD is the LDS
+// row padding (one 16-byte bank step).
+template <int P> struct Geo;
+template <> struct Geo<PREC_FP32> {
+    using Vec = v4f;
+    static constexpr int KV = 4, KL = 1, KG = 8, EB = 4, PAD = 16;
+};
+template <> struct Geo<PREC_BF16> {
+    using Vec = v8bf;
+    static constexpr int KV = 8, KL = 8, KG = 16, EB = 2, PAD = 16;
+};
+template <> struct Geo<PREC_FP8> {
+    using Vec = v8i;
+    static constexpr int KV = 32, KL = 32, KG = 64, EB = 1, PAD = 16;
+};
+
+__device__ __forceinline__ v16f mma(float a, float b, v16f c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v16f mma(v8bf a, v8bf b, v16f c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v16f mma(v8i a, v8i b, v16f c)
+{
+    // OCP e4m3 for both operands, no block scales
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+}
+
+// Precision of the first layer (K = 32 input features): fp32 for the fp32
+// model, bf16 otherwise (the fp8 k-step of 64 does not fit 32 inputs).
+template <int P> struct FirstP { static constexpr int value = P == PREC_FP32 ? PREC_FP32 : PREC_BF16; };
+
+// Packed weight index of element (n, k) of a layer with Kp (padded) inputs:
+// fragment-major, [n-block][k-group][lane][KV].
+template <int P>
+__host__ __device__ __forceinline__ int64_t pack_index(int n, int k, int Kp)
+{
+    constexpr int KV = Geo<P>::KV, KG = Geo<P>::KG;
+    const int nb = n >> 5, kg = k / KG, kk = k % KG;
+    const int lane = (n & 31) + 32 * (kk / KV);
+    return (((int64_t)nb * (Kp / KG) + kg) * 64 + lane) * KV + (kk % KV);
+}
+
+// OCP e4m3 (1-4-3, bias 7, max 448, no infinities) from fp32 with
+// round-to-nearest-even and saturation to +-448; NaN maps to 0x7f.
+__device__ __forceinline__ uint32_t f32_to_e4m3(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    u &= 0x7fffffffu;
+    if (u > 0x7f800000u) return 0x7fu;              // NaN
+    if (u >= 0x43e00000u) return sign | 0x7eu;      // >= 448 (and inf): saturate
+    if (u < 0x3c800000u) {                          // below 2^-6: subnormal range
+        // value = m * 2^-9 with m in [0, 8): round x * 2^9 to nearest even
+        const float y = __uint_as_float(u) * 512.0f;
+        const float r = __builtin_rintf(y);        // RNE, exact in fp32
+        return sign | (uint32_t)r;                 // r = 8 encodes 2^-6 (exponent 1)
+    }
+    // normal: keep 3 mantissa bits, RNE on the 20 dropped bits
+    const uint32_t lsb = (u >> 20) & 1u;
+    u += 0x7ffffu + lsb;
+    const uint32_t e = (u >> 23) - 127 + 7;
+    const uint32_t mant = (u >> 20) & 7u;
+    const uint32_t code = (e << 3) | mant;
+    return sign | (code > 0x7eu ? 0x7eu : code);
+}
+
+struct TileArgs {
+    // input
+    const int64_t *kdesc;
+    const int64_t *vdesc;
+    const int64_t *feat;
+    const int64_t *offsets;
+    int64_t n_k;
+    int64_t n_rows;
+    // network
+    NetView net;
+    // output
+    float *pred;          // [n_rows] or null
+    uint64_t *keys;       // [n_k] argmin keys (rank)
+};
+
+template <int P, int W, int M, int NWAVES>
+struct TileCfg {
+    using G = Geo<P>;
+    using G0 = Geo<FirstP<P>::value>;
+    static constexpr int NB = W / 32;                      // n-blocks of a layer
+    static constexpr int MB = M / 32;                      // m-blocks of a tile
+    static constexpr int WN = NB < NWAVES ? NB : NWAVES;   // waves along n
+    static constexpr int WM = NWAVES / WN;                 // waves along m
+    static constexpr int NBW = NB / WN;                    // n-blocks per wave
+    static constexpr int MBW = MB / WM;                    // m-blocks per wave
+    static_assert(NB % WN == 0 && MB % WM == 0 && NWAVES % WN == 0, "tile split");
+    static constexpr int XS = 32 * G0::EB + G0::PAD;       // input row stride (bytes)
+    static constexpr int AS = W * G::EB + G::PAD;          // activation row stride (bytes)
+    static constexpr int THREADS = NWAVES * 64;
+    static constexpr int PARTS = THREADS / M;              // threads per row in the input stage
+    static_assert(PARTS >= 1 && NFEAT % PARTS == 0, "input split");
+    static constexpr int FPP = NFEAT / PARTS;              // features per thread
+    static constexpr size_t LDS = (size_t)M * XS + (size_t)M * AS + (size_t)WN * M * 4 + M * 8;
+};
+
+// 16-byte-aligned LDS vector load (an fp8 vector is two 16-byte halves).
+template <int P>
+__device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
+{
+    using V = typename Geo<P>::Vec;
+    if constexpr (sizeof(V) == 32) {
+        typedef int v4i_ __attribute__((ext_vector_type(4)));
+        const v4i_ lo = *reinterpret_cast<const v4i_ *>(p);
+        const v4i_ hi = *reinterpret_cast<const v4i_ *>(p + 16);
+        v8i r;
+        r[0] = lo[0]; r[1] = lo[1]; r[2] = lo[2]; r[3] = lo[3];
+        r[4] = hi[0]; r[5] = hi[1]; r[6] = hi[2]; r[7] = hi[3];
+        return r;
+    } else {
+        return *reinterpret_cast<const V *>(p);
+    }
+}
+
+// acc[i][j] += W (A vectors streamed from global/L2) x act^T (B vectors from
+// LDS) over the K inputs of one layer.
+template <int PL, int K, int NBW, int MBW>
+__device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restrict__ wl,
+                                          const unsigned char *lds_in, int stride, int nb0,
+                                          int mb0, int lane, v16f (&acc)[NBW][MBW])
+{
+    using G = Geo<PL>;
+    using V = typename G::Vec;
+    constexpr int KGROUPS = K / G::KG;
+    const int half = lane >> 5, col = lane & 31;
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+        for (int j = 0; j < MBW; ++j) acc[i][j] = v16f{0};
+    const unsigned char *bbase = lds_in + (size_t)(mb0 * 32 + col) * stride + half * G::KV * G::EB;
+#pragma unroll 2
+    for (int kg = 0; kg < KGROUPS; ++kg) {
+        V a[NBW], b[MBW];
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) a[i] = wl[((int64_t)(nb0 + i) * KGROUPS + kg) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < MBW; ++j)
+            b[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride + kg * G::KG * G::EB);
+#pragma unroll
+        for (int i = 0; i < NBW; ++i)
+#pragma unroll
+            for (int j = 0; j < MBW; ++j) {
+                if constexpr (PL == PREC_FP32) {
+#pragma unroll
+                    for (int t = 0; t < G::KV; ++t) acc[i][j] = mma(a[i][t], b[j][t], acc[i][j]);
+                } else {
+                    acc[i][j] = mma(a[i], b[j], acc[i][j]);
+                }
+            }
+    }
+}
+
+// Bias + ReLU, then store four consecutive neurons of one variant into the
+// next layer's activation rows (optionally scaled for fp8).
+template <int P>
+__device__ __forceinline__ void store4(unsigned char *row, int n, v4f v, float qinv)
+{
+    using G = Geo<P>;
+    if constexpr (P == PREC_FP32) {
+        *reinterpret_cast<v4f *>(row + n * 4) = v;
+    } else if constexpr (P == PREC_BF16) {
+        v4bf o;
+        o[0] = (__bf16)v[0];
+        o[1] = (__bf16)v[1];
+        o[2] = (__bf16)v[2];
+        o[3] = (__bf16)v[3];
+        *reinterpret_cast<v4bf *>(row + n * 2) = o;
+    } else {
+        const uint32_t q = f32_to_e4m3(v[0] * qinv) | (f32_to_e4m3(v[1] * qinv) << 8) |
+                           (f32_to_e4m3(v[2] * qinv) << 16) | (f32_to_e4m3(v[3] * qinv) << 24);
+        *reinterpret_cast<uint32_t *>(row + n) = q;
+    }
+    (void)sizeof(G);
+}
+
+template <int P, int W, int M, int NWAVES, int SRC, int SINK>
+__global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
+{
+    using C = TileCfg<P, W, M, NWAVES>;
+    using G = typename C::G;
+    constexpr int P0 = FirstP<P>::value;
+    using G0 = Geo<P0>;
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *xin = lds;                                   // [M][XS]
+    unsigned char *act = xin + (size_t)M * C::XS;               // [M][AS]
+    float *hpart = reinterpret_cast<float *>(act + (size_t)M * C::AS);  // [WN][M]
+    int *meta_ok = reinterpret_cast<int *>(hpart + C::WN * M);  // [M]
+    int *meta_kid = meta_ok + M;                                // [M]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wn = wave % C::WN, wm = wave / C::WN;
+    const int nb0 = wn * C::NBW, mb0 = wm * C::MBW;
+    const int half = lane >> 5, col = lane & 31;
+    const NetView &net = args.net;
+    const int64_t n = args.n_rows;
+    const int64_t ntiles = (n + M - 1) / M;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * M;
+        __syncthreads();  // previous tile's readers of xin / meta / hpart are done
+        // ---- input stage: PARTS threads per row, FPP features each
+        {
+            const int r = tid / C::PARTS, part = tid % C::PARTS;
+            const int64_t row = row0 + r;
+            bool ok = row < n;
+            int64_t kid = -1;
+            double xv[C::FPP];
+            if constexpr (SRC == SRC_DESC) {
+                Feat f;
+                if (ok) {
+                    ok = featurize_one(args.kdesc, args.vdesc + row * VD, args.n_k, f);
+                    kid = args.vdesc[row * VD];
+                    if (SINK == SINK_RANK && ok)  // the variant must sit in its kernel's segment
+                        ok = args.offsets[kid] <= row && row < args.offsets[kid + 1];
+                }
+#pragma unroll
+                for (int q = 0; q < C::FPP; ++q) {
+                    const int j = part * C::FPP + q;
+                    xv[q] = ok ? zscore((int64_t)f.f[j], net.mu[j], net.sigma[j]) : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < C::FPP; ++q) {
+                    const int j = part * C::FPP + q;
+                    xv[q] = ok ? zscore(args.feat[row * NFEAT + j], net.mu[j], net.sigma[j]) : 0.0;
+                }
+            }
+            unsigned char *xr = xin + (size_t)r * C::XS + part * C::FPP * G0::EB;
+#pragma unroll
+            for (int q = 0; q < C::FPP; ++q) {
+                const float x = (float)xv[q];
+                if constexpr (P0 == PREC_FP32)
+                    reinterpret_cast<float *>(xr)[q] = x;
+                else
+                    reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
+            }
+            if (part == 0) {
+                meta_ok[r] = ok ? 1 : 0;
+                meta_kid[r] = (int)kid;
+            }
+        }
+        __syncthreads();
+
+        v16f acc[C::NBW][C::MBW];
+        // ---- layer 0 (32 inputs), then hidden layers 1..n_hidden-1
+        for (int l = 0; l < net.n_hidden; ++l) {
+            if (l == 0) {
+                layer_mma<P0, 32, C::NBW, C::MBW>(
+                    reinterpret_cast<const typename G0::Vec *>(net.w[0]), xin, C::XS, nb0, mb0,
+                    lane, acc);
+            } else {
+                layer_mma<P, W, C::NBW, C::MBW>(
+                    reinterpret_cast<const typename G::Vec *>(net.w[l]), act, C::AS, nb0, mb0,
+                    lane, acc);
+                __syncthreads();  // every wave finished reading act before it is overwritten
+            }
+            const float *bias = net.b[l];
+            const float qs = (P == PREC_FP8 && l > 0) ? net.qscale[l] : 1.0f;
+            if (l + 1 < net.n_hidden) {
+                const float qinv = net.qinv[l];
+#pragma unroll
+                for (int i = 0; i < C::NBW; ++i) {
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                        const v4f bb = *reinterpret_cast<const v4f *>(bias + nn);
+#pragma unroll
+                        for (int j = 0; j < C::MBW; ++j) {
+                            v4f v;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float z = acc[i][j][4 * g + e] * qs + bb[e];
+                                v[e] = z > 0.0f ? z : 0.0f;
+                            }
+                            const int m = (mb0 + j) * 32 + col;
+                            store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
+                        }
+                    }
+                }
+                __syncthreads();  // next layer reads the complete activations
+            } else {
+                // output layer: per-lane partial dot products of the ReLU'd
+                // last hidden layer with the head weights (fp32)
+                const float *hw = net.head_w;
+#pragma unroll
+                for (int j = 0; j < C::MBW; ++j) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < C::NBW; ++i) {
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                            const v4f bb = *reinterpret_cast<const v4f *>(bias + nn);
+                            const v4f ww = *reinterpret_cast<const v4f *>(hw + nn);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float z = acc[i][j][4 * g + e] * qs + bb[e];
+                                s += (z > 0.0f ? z : 0.0f) * ww[e];
+                            }
+                        }
+                    }
+                    s += __shfl_xor(s, 32, 64);  // the two lane halves hold different neurons
+                    if (half == 0) hpart[wn * M + (mb0 + j) * 32 + col] = s;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- output stage: one thread per row (whole waves, for the shuffles)
+        if (wave < (M + 63) / 64) {
+            const bool inrow = tid < M;
+            const int64_t row = row0 + tid;
+            float p = net.head_b[0];
+            if (inrow) {
+#pragma unroll
+                for (int q = 0; q < C::WN; ++q) p += hpart[q * M + tid];
+            }
+            const bool ok = inrow && meta_ok[tid] != 0;
+            if constexpr (SINK == SINK_PRED) {
+                if (inrow && row < n) args.pred[row] = p;
+            } else {
+                if (inrow && row < n && args.pred) args.pred[row] = ok ? p : __builtin_nanf("");
+                const bool take = ok && !__builtin_isnan(p);
+                uint64_t key = ~0ull;
+                if (take) {
+                    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
+                    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+                    key = ((uint64_t)u << 32) | (uint32_t)row;
+                }
+                // segmented min over runs of equal kernel id within the wave
+                // (inclusive scan with segment-head flags), then one atomic
+                // per run from its last lane
+                const int kid = take ? meta_kid[tid] : -1;
+                const int prev = __shfl_up(kid, 1, 64);
+                int head = (lane == 0) || (prev != kid);
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint64_t kup = __shfl_up(key, off, 64);
+                    const int hup = __shfl_up(head, off, 64);
+                    if (lane >= off && !head) {
+                        key = kup < key ? kup : key;
+                        head = hup;
+                    }
+                }
+                const int next = __shfl_down(kid, 1, 64);
+                const bool last = (lane == 63) || (next != kid);
+                if (last && kid >= 0 && key != ~0ull)
+                    atomicMin(reinterpret_cast<unsigned long long *>(args.keys + kid),
+                              (unsigned long long)key);
+            }
+        }
+    }
+}
+
+}  // namespace adv

@@ -1,0 +1,241 @@
+// Integer and selection kernels: standalone feature extraction, the Z-score
+// fit, and the per-kernel argmin on given predictions. All of them are
+// bandwidth-bound and use no matrix cores.
+#include <algorithm>
+
+#include "features.h"
+
+namespace adv {
+
+// ---------------------------------------------------------------------------
+// Feature extraction: one thread per variant. A workgroup stages its 256
+// feature rows (64 KiB) in LDS so the int64 stores leave as contiguous
+// 16-byte chunks per lane (fully coalesced) instead of 256-byte strided rows.
+constexpr int FZ_THREADS = 256;
+
+__global__ __launch_bounds__(FZ_THREADS) void featurize_kernel(
+    const int64_t *__restrict__ kdesc, const int64_t *__restrict__ vdesc, int64_t n_k,
+    int64_t n_v, int64_t *__restrict__ feat, uint8_t *__restrict__ invalid)
+{
+    __shared__ int64_t stage[FZ_THREADS * NFEAT];
+    const int64_t row0 = (int64_t)blockIdx.x * FZ_THREADS;
+    const int t = threadIdx.x;
+    const int64_t row = row0 + t;
+    if (row < n_v) {
+        Feat f;
+        bool ok = featurize_one(kdesc, vdesc + row * VD, n_k, f);
+        if (invalid) invalid[row] = ok ? 0 : 1;
+        // rotate the column by the row so neighbouring threads hit distinct banks
+#pragma unroll
+        for (int j = 0; j < NFEAT; ++j) stage[t * NFEAT + ((j + t) & (NFEAT - 1))] = (int64_t)f.f[j];
+    }
+    __syncthreads();
+    const int64_t rows = min((int64_t)FZ_THREADS, n_v - row0);
+    // 2 int64 per lane per store: chunk c covers row c/16, columns 2*(c%16)..+1
+    longlong2 *out = reinterpret_cast<longlong2 *>(feat + row0 * NFEAT);
+    const int chunks = (int)rows * (NFEAT / 2);
+    for (int c = t; c < chunks; c += FZ_THREADS) {
+        const int r = c >> 4, j = (c & 15) * 2;
+        longlong2 v;
+        v.x = stage[r * NFEAT + ((j + r) & (NFEAT - 1))];
+        v.y = stage[r * NFEAT + ((j + 1 + r) & (NFEAT - 1))];
+        out[c] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Z-score fit in float64 with a fixed reduction order (deterministic): each
+// workgroup owns a contiguous block of rows; 8 row-lanes x 32 features per
+// workgroup; per-workgroup partials are combined in workgroup order.
+constexpr int ZS_THREADS = 256;
+constexpr int ZS_ROWLANES = ZS_THREADS / NFEAT;
+
+__global__ __launch_bounds__(ZS_THREADS) void zscore_partial_kernel(
+    const int64_t *__restrict__ feat, int64_t n, int64_t rows_per_block,
+    const double *__restrict__ mean, double *__restrict__ part_sum,
+    int64_t *__restrict__ part_min, int64_t *__restrict__ part_max)
+{
+    __shared__ double s_sum[ZS_THREADS];
+    __shared__ int64_t s_min[ZS_THREADS], s_max[ZS_THREADS];
+    const int j = threadIdx.x & (NFEAT - 1), lane_row = threadIdx.x / NFEAT;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    double s = 0.0;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int64_t r = r0 + lane_row; r < r1; r += ZS_ROWLANES) {
+        const int64_t f = feat[r * NFEAT + j];
+        const double l = log2((double)f + 1.0);
+        if (mean) {
+            const double d = l - mean[j];
+            s += d * d;
+        } else {
+            s += l;
+        }
+        lo = f < lo ? f : lo;
+        hi = f > hi ? f : hi;
+    }
+    s_sum[threadIdx.x] = s;
+    s_min[threadIdx.x] = lo;
+    s_max[threadIdx.x] = hi;
+    __syncthreads();
+    if (threadIdx.x < NFEAT) {
+        double a = 0.0;
+        int64_t mn = INT64_MAX, mx = INT64_MIN;
+        for (int q = 0; q < ZS_ROWLANES; ++q) {
+            a += s_sum[q * NFEAT + j];
+            mn = min(mn, s_min[q * NFEAT + j]);
+            mx = max(mx, s_max[q * NFEAT + j]);
+        }
+        part_sum[blockIdx.x * NFEAT + j] = a;
+        if (part_min) {
+            part_min[blockIdx.x * NFEAT + j] = mn;
+            part_max[blockIdx.x * NFEAT + j] = mx;
+        }
+    }
+}
+
+// One thread per feature: combine the partials in order. Pass 1 writes the
+// mean (or the constant's logarithm), pass 2 the population deviation.
+__global__ void zscore_final_kernel(const double *__restrict__ part_sum,
+                                    const int64_t *__restrict__ part_min,
+                                    const int64_t *__restrict__ part_max, int n_blocks, int64_t n,
+                                    int pass, double *__restrict__ mu, double *__restrict__ sigma,
+                                    int *__restrict__ constant)
+{
+    const int j = threadIdx.x;
+    if (j >= NFEAT) return;
+    double a = 0.0;
+    for (int b = 0; b < n_blocks; ++b) a += part_sum[b * NFEAT + j];
+    if (pass == 1) {
+        int64_t mn = INT64_MAX, mx = INT64_MIN;
+        for (int b = 0; b < n_blocks; ++b) {
+            mn = min(mn, part_min[b * NFEAT + j]);
+            mx = max(mx, part_max[b * NFEAT + j]);
+        }
+        constant[j] = (mn == mx);
+        mu[j] = (mn == mx) ? log2((double)mn + 1.0) : a / (double)n;
+    } else {
+        const double sd = sqrt(a / (double)n);
+        sigma[j] = (constant[j] || !(sd > 0.0)) ? 1.0 : sd;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segmented argmin on predictions: one wave per kernel segment. The key of a
+// variant orders (prediction, index) lexicographically as one unsigned
+// 64-bit integer: the prediction's bits mapped to an order-preserving
+// unsigned form (after folding -0 into +0) in the high half, the index in the
+// low half. The minimum key is the lowest prediction, lowest index on ties.
+__device__ __forceinline__ uint64_t pred_key(float p, uint32_t idx)
+{
+    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)u << 32) | idx;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+constexpr int AM_WAVES = 4;
+
+__global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
+    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, int64_t *__restrict__ best)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
+    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + (threadIdx.x >> 6); k < n_k;
+         k += nwaves_total) {
+        // clamp to the prediction array so malformed offsets cannot read out of bounds
+        const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
+        const int64_t hi = max(lo, min(offsets[k + 1], n_v));
+        uint64_t key = ~0ull;
+        for (int64_t i = lo + lane; i < hi; i += 64) {
+            const float p = pred[i];
+            if (!__builtin_isnan(p)) {
+                const uint64_t q = pred_key(p, (uint32_t)i);
+                key = q < key ? q : key;
+            }
+        }
+        key = wave_min_u64(key);
+        if (lane == 0) best[k] = key == ~0ull ? -1 : (int64_t)(key & 0xffffffffull);
+    }
+}
+
+}  // namespace adv
+
+using namespace adv;
+
+extern "C" int advisor_featurize(const int64_t *kdesc, const int64_t *vdesc, int64_t n_kernels,
+                                 int64_t n_variants, int64_t *feat_out, uint8_t *invalid_out,
+                                 void *stream)
+{
+    clear_error();
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants == 0) return ADVISOR_OK;
+    if (!vdesc || !feat_out || (n_kernels > 0 && !kdesc))
+        return fail(ADVISOR_EINVAL, "advisor_featurize: null pointer");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    const int64_t blocks = (n_variants + FZ_THREADS - 1) / FZ_THREADS;
+    hipLaunchKernelGGL(featurize_kernel, dim3((unsigned)blocks), dim3(FZ_THREADS), 0,
+                       as_stream(stream), kdesc, vdesc, n_kernels, n_variants, feat_out,
+                       invalid_out);
+    ADV_LAUNCHED("featurize_kernel");
+    return ADVISOR_OK;
+}
+
+extern "C" int advisor_zscore_fit(const int64_t *feat, int64_t n, double *mu_out,
+                                  double *sigma_out, void *stream)
+{
+    clear_error();
+    if (n < 1) return fail(ADVISOR_ESHAPE, "advisor_zscore_fit: n must be >= 1");
+    if (!feat || !mu_out || !sigma_out) return fail(ADVISOR_EINVAL, "advisor_zscore_fit: null pointer");
+    hipStream_t s = as_stream(stream);
+    const int n_blocks = (int)std::min<int64_t>(256, (n + 255) / 256);
+    const int64_t rows_per_block = (n + n_blocks - 1) / n_blocks;
+    const size_t bytes = (size_t)n_blocks * NFEAT * (sizeof(double) + 2 * sizeof(int64_t)) +
+                         NFEAT * sizeof(int);
+    void *ws = nullptr;
+    ADV_HIP(hipMallocAsync(&ws, bytes, s));
+    double *psum = (double *)ws;
+    int64_t *pmin = (int64_t *)(psum + n_blocks * NFEAT);
+    int64_t *pmax = pmin + n_blocks * NFEAT;
+    int *cflag = (int *)(pmax + n_blocks * NFEAT);
+    hipLaunchKernelGGL(zscore_partial_kernel, dim3(n_blocks), dim3(ZS_THREADS), 0, s, feat, n,
+                       rows_per_block, (const double *)nullptr, psum, pmin, pmax);
+    hipLaunchKernelGGL(zscore_final_kernel, dim3(1), dim3(64), 0, s, psum, pmin, pmax, n_blocks,
+                       n, 1, mu_out, sigma_out, cflag);
+    hipLaunchKernelGGL(zscore_partial_kernel, dim3(n_blocks), dim3(ZS_THREADS), 0, s, feat, n,
+                       rows_per_block, (const double *)mu_out, psum, (int64_t *)nullptr,
+                       (int64_t *)nullptr);
+    hipLaunchKernelGGL(zscore_final_kernel, dim3(1), dim3(64), 0, s, psum, pmin, pmax, n_blocks,
+                       n, 2, mu_out, sigma_out, cflag);
+    hipError_t le = hipGetLastError();
+    hipError_t fe = hipFreeAsync(ws, s);
+    if (le != hipSuccess) return hip_fail(le, "zscore kernels");
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+    return ADVISOR_OK;
+}
+
+extern "C" int advisor_rank_preds(const float *pred, const int64_t *offsets, int64_t n_kernels,
+                                  int64_t n_variants, int64_t *best_out, void *stream)
+{
+    clear_error();
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels == 0) return ADVISOR_OK;
+    if (!offsets || !best_out || (n_variants > 0 && !pred))
+        return fail(ADVISOR_EINVAL, "advisor_rank_preds: null pointer");
+    const int64_t blocks = std::min<int64_t>((n_kernels + AM_WAVES - 1) / AM_WAVES, 1 << 20);
+    hipLaunchKernelGGL(argmin_preds_kernel, dim3((unsigned)blocks), dim3(AM_WAVES * 64), 0,
+                       as_stream(stream), pred, offsets, n_kernels, n_variants, best_out);
+    ADV_LAUNCHED("argmin_preds_kernel");
+    return ADVISOR_OK;
+}

@@ -1,0 +1,60 @@
+"""Owning wrapper of a libadvisor model handle."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+
+
+class Model:
+    """A cost model (32 -> hidden widths -> 1) living on the current GPU."""
+
+    def __init__(self, widths, precision="fp32"):
+        self.widths = tuple(int(w) for w in widths)
+        self.precision = precision
+        self.handle = _lib.advisor_model_create(self.widths, precision)
+
+    @property
+    def param_count(self) -> int:
+        return _lib.advisor_model_param_count(self.handle)
+
+    def set_params(self, w_master, mu, sigma):
+        _lib.advisor_model_set_params(self.handle, w_master, mu, sigma)
+
+    def get_params(self):
+        return _lib.advisor_model_get_params(self.handle)
+
+    def set_zscore(self, mu, sigma):
+        _lib.advisor_model_set_zscore(self.handle, mu, sigma)
+
+    def predict(self, feat, pred_out=None):
+        return _lib.advisor_predict(self.handle, feat, pred_out)
+
+    def rank(self, kdesc, vdesc, offsets, best_out=None, pred_out=None, want_pred=False):
+        return _lib.advisor_rank(self.handle, kdesc, vdesc, offsets, best_out, pred_out, want_pred)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.advisor_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def flops_per_variant(widths) -> int:
+    """Algorithmic multiply-add flops of one forward pass (2 per MAC)."""
+    return int(sum(2 * widths[i] * widths[i + 1] for i in range(len(widths) - 1)))
+
+
+def as_numpy_params(w):
+    return np.ascontiguousarray(w, dtype=np.float32)

@@ -1,0 +1,97 @@
+"""The C ABI without a GPU: the library loads, exports every entry point its
+header declares, and rejects bad arguments on the host with the documented
+status codes before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2301_03636_amd as adv
+from paper_2301_03636_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "advisor.h")
+
+OK, EINVAL, ESHAPE, EHIP, ENOMEM, EUNSUP = 0, -1, -2, -3, -4, -5
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(advisor_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_error_text():
+    L = _lib.lib()
+    assert b"gfx950" in L.advisor_version()
+    rc = L.advisor_featurize(None, None, -1, 5, None, None, None)
+    assert rc == ESHAPE and "negative" in _lib.last_error()
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, None, 1, 10, None, None, None), EINVAL),
+    ((None, None, -1, 10, None, None, None), ESHAPE),
+    ((C.c_void_p(8), C.c_void_p(8), 1, 1 << 32, C.c_void_p(8), C.c_void_p(8), None), ESHAPE),
+    ((None, None, 0, 0, None, None, None), OK),
+])
+def test_featurize_argument_checks(args, code):
+    assert _lib.lib().advisor_featurize(*args) == code
+
+
+def test_rank_preds_argument_checks():
+    L = _lib.lib()
+    assert L.advisor_rank_preds(None, None, 1, 4, None, None) == EINVAL
+    assert L.advisor_rank_preds(None, None, -1, 4, None, None) == ESHAPE
+    assert L.advisor_rank_preds(C.c_void_p(8), C.c_void_p(8), 1, 1 << 32, C.c_void_p(8),
+                                None) == ESHAPE
+    assert L.advisor_rank_preds(None, None, 0, 0, None, None) == OK
+
+
+def test_model_create_argument_checks():
+    L = _lib.lib()
+    h = C.c_void_p()
+
+    def create(widths, prec):
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        return L.advisor_model_create(w.ctypes.data_as(C.c_void_p), w.size, prec, C.byref(h))
+    assert create([32, 64, 1], 7) == EINVAL
+    assert create([31, 64, 1], 0) == ESHAPE
+    assert create([32, 64, 2], 0) == ESHAPE
+    assert create([32, 2048, 1], 1) == ESHAPE
+    assert create([32, 1], 0) == ESHAPE
+    assert create([32] + [64] * 9 + [1], 0) == ESHAPE
+    assert L.advisor_model_create(None, 3, 0, C.byref(h)) == EINVAL
+    assert L.advisor_model_create(None, 3, 0, None) == EINVAL
+
+
+def test_entry_points_reject_null_model():
+    L = _lib.lib()
+    assert L.advisor_predict(None, None, 4, None, None) == EINVAL
+    assert L.advisor_rank(None, None, None, None, 1, 4, None, None, None) == EINVAL
+    assert L.advisor_model_set_params(None, None, None, None) == EINVAL
+    assert L.advisor_model_param_count(None) == -1
+    L.advisor_model_destroy(None)
+
+
+def test_zscore_argument_checks():
+    L = _lib.lib()
+    assert L.advisor_zscore_fit(None, 0, None, None, None) == ESHAPE
+    assert L.advisor_zscore_fit(None, 5, None, None, None) == EINVAL
+
+
+def test_python_binding_names_match_c():
+    for n in declared_symbols():
+        if n in ("advisor_last_error", "advisor_version"):
+            continue
+        assert hasattr(_lib, n), n
+    assert adv.PRECISIONS == {"fp32": 0, "bf16": 1, "fp8": 2}

@@ -316,10 +316,14 @@ def test_rank_composes_the_steps():
     best, pred = oracle.rank(kd, vd, off, widths, p, mu, sd)
     x = oracle.normalize(f, mu, sd)
     y = oracle.forward(widths, p, x)
-    y[inv == 1] = np.nan
-    assert np.array_equal(np.isnan(pred), inv == 1)
-    assert np.array_equal(pred[inv == 0], y[inv == 0])
-    assert best.tolist() == _brute_argmin(y, off, inv)
+    # rows whose kernel id is not their segment take no part
+    seg = np.repeat(np.arange(30), off[1:] - off[:-1])
+    out = (inv == 1) | (vd[:, 0] != seg)
+    assert out.sum() > inv.sum()
+    y[out] = np.nan
+    assert np.array_equal(np.isnan(pred), out)
+    assert np.array_equal(pred[~out], y[~out])
+    assert best.tolist() == _brute_argmin(y, off, out)
     assert best[3] == -1
 
 
