@@ -1,0 +1,254 @@
+"""Throughput of the cost-model hot path on one MI355X.
+
+One step = one advisor_rank call over the whole synthetic workload: feature
+extraction of every variant, Z-score, the MLP on the matrix cores and the
+per-kernel argmin (the paper's prediction flow, many kernels at once). The
+descriptors and weights are resident in HBM before the timed region; the
+timed region is exactly --steps calls bracketed by device synchronization.
+
+Prints one JSON line. `value` is variants ranked per second; `roofline`
+prices the fused tile kernel (the dominant kernel) against the matrix-core
+peak of its precision, with its duration taken from HIP events recorded
+around each of its launches; `cpu_baseline` is the float64 CPU oracle timed
+on a seeded sample of whole kernels of the same workload on this host.
+`precisions` repeats the measurement for the other compute precisions on the
+same inputs, each with its argmin agreement against the oracle on the sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workload  # noqa: E402
+
+# MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
+PEAK_HBM_GBS = 8000.0
+DEFAULT_PRECISION = {1: "fp32", 2: "fp32", 3: "bf16", 5: "fp8"}
+WORKLOAD_NAME = {
+    1: "single kernel x 256 variants, 32-64-64-1",
+    2: "4096 kernels x U[16,1024] variants (2.1M), 32-256x3-1",
+    3: "16384 kernels x U[64,1024] variants (8.9M), 32-512x4-1",
+    5: "32768 kernels x U[128,1024] variants (18.9M), 32-1024x4-1",
+}
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def layer_flops(widths):
+    return [2 * widths[i] * widths[i + 1] for i in range(len(widths) - 1)]
+
+
+def roofline_peak(widths, precision):
+    """Peak for the whole network: the fp8 model keeps its first layer in
+    bf16, so its roofline time is the sum of per-layer times."""
+    fl = layer_flops(widths)
+    if precision != "fp8":
+        return PEAK_TFLOPS[precision]
+    t = fl[0] / PEAK_TFLOPS["bf16"] + sum(fl[1:-1]) / PEAK_TFLOPS["fp8"] + fl[-1] / PEAK_TFLOPS["bf16"]
+    return sum(fl) / t
+
+
+def kernel_source_hash():
+    """Hash of the sources the fused tile kernel is built from; a stored
+    traffic measurement only applies to the kernel it was taken on."""
+    h = hashlib.sha256()
+    for f in ("mlp_tile.h", "features.h", "mlp.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2301_03636_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(cfg, precision):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, scaled by a copy-kernel calibration), if taken on the
+    current kernel sources; else None."""
+    path = os.path.join(PROFILE_DIR, "traffic_tiles_cfg%d_%s.json" % (cfg, precision))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_inputs(cfg, seed_desc=None):
+    c = workload.CONFIGS[cfg]
+    s = workload.seeds(cfg)
+    kd, vd, off = workload.make_descriptors(c["n_kernels"], c["count_lo"], c["count_hi"],
+                                            s["desc"] if seed_desc is None else seed_desc)
+    params = workload.he_init(c["widths"], s["w"])
+    return kd, vd, off, params, tuple(c["widths"])
+
+
+def time_rank(adv, torch, model, kdd, vdd, offd, best, steps, warmup):
+    for _ in range(warmup):
+        model.rank(kdd, vdd, offd, best_out=best)
+    torch.cuda.synchronize()
+    adv.advisor_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        model.rank(kdd, vdd, offd, best_out=best)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kern_ms = adv.advisor_profile_read()
+    adv.advisor_profile_enable(False)
+    return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches
+
+
+def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds, gpu_best_by_prec):
+    """The float64 oracle (as written, parallel over kernels) on a seeded
+    sample of whole kernels sized to about `seconds` of CPU time."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    p64 = params.astype(np.float64)
+
+    def run(n_kernels, seed):
+        ks, rows, sub_off = workload.sample_kernels(off, n_kernels, seed)
+        vsub = vd[rows].copy()
+        vsub[:, 0] = np.repeat(np.arange(ks.size), sub_off[1:] - sub_off[:-1])
+        t0 = time.perf_counter()
+        best, _ = oracle.rank(kd[ks], vsub, sub_off, widths, p64, mu, sd, n_threads=threads,
+                              want_pred=False)
+        dt = time.perf_counter() - t0
+        glob = np.where(best >= 0, rows[np.maximum(best, 0)], -1)
+        return ks, rows.size, dt, glob
+
+    nk = off.size - 1
+    probe = min(nk, max(1, 2 * threads))
+    _, nv_probe, dt_probe, _ = run(probe, 4242)
+    per_variant = dt_probe / max(nv_probe, 1)
+    avg = (off[-1] / nk)
+    n_sample = int(min(nk, max(probe, seconds / max(per_variant * avg, 1e-9))))
+    ks, nv_s, dt, best_cpu = run(n_sample, 4243)
+    agree = {}
+    for prec, gb in gpu_best_by_prec.items():
+        agree[prec] = float(np.mean(gb[ks] == best_cpu))
+    return {
+        "value": nv_s / dt,
+        "unit": "variants/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "%d of %d kernels (seeded), %d variants, %.1f s wall" % (ks.size, nk, nv_s, dt),
+    }, agree
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--also", default="bf16",
+                    help="comma-separated extra precisions timed on the same inputs ('' for none)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates the "
+                         "HBM byte counters of a profiler run) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X here "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2301_03636_amd as adv
+
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=d)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "launches": 3}), flush=True)
+        return
+    cfg = args.config
+    prec = args.precision or DEFAULT_PRECISION[cfg]
+    kd, vd, off, params, widths = make_inputs(cfg)
+    nv, nk = vd.shape[0], off.size - 1
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(d)
+    kdd, vdd, offd = T(kd), T(vd), T(off)
+    # Z-score statistics from a seeded calibration sample, fitted on the GPU
+    cal = T(workload.sample_rows(nv, 65536, workload.seeds(cfg)["desc"] + 7))
+    feat_cal, inv_cal = adv.advisor_featurize(kdd, vdd[cal])
+    mu_d, sd_d = adv.advisor_zscore_fit(feat_cal[inv_cal == 0].contiguous())
+    mu, sd = mu_d.cpu().numpy(), sd_d.cpu().numpy()
+    del feat_cal, inv_cal
+
+    results = {}
+    best_by_prec = {}
+    precs = [prec] + [p for p in args.also.split(",") if p and p != prec]
+    for p in precs:
+        if p == "fp8":
+            continue  # needs calibration support
+        m = adv.Model(widths, p)
+        m.set_params(params, mu, sd)
+        best = torch.empty(nk, dtype=torch.int64, device=d)
+        ms, kern_ms, launches = time_rank(adv, torch, m, kdd, vdd, offd, best,
+                                          args.steps if p == prec else max(5, args.steps // 2),
+                                          args.warmup)
+        best_by_prec[p] = best.cpu().numpy()
+        fl = sum(layer_flops(widths))
+        results[p] = dict(ms_per_step=ms, kernel_ms=kern_ms, launches=launches,
+                          value=nv / (ms / 1e3),
+                          tflops=fl * nv / (kern_ms / 1e3) / 1e12)
+        m.close()
+
+    main_r = results[prec]
+    peak = roofline_peak(widths, prec)
+    traffic = stored_traffic(cfg, prec)
+    out = {
+        "metric": "variants ranked/sec (featurize+MLP+argmin), BF16/FP8 vs FP32 at argmin agreement",
+        "value": main_r["value"],
+        "unit": "variants/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[prec],
+        "data": "synthetic (seeded descriptors and He-init weights)",
+        "config": {"workload": WORKLOAD_NAME[cfg], "n_kernels": nk, "n_variants": nv,
+                   "widths": list(widths), "precision": prec},
+        "roofline": {"bound": "mfma", "achieved": main_r["tflops"], "peak": round(peak, 1),
+                     "unit": "TFLOP/s", "frac": main_r["tflops"] / peak,
+                     "traffic": traffic,
+                     "kernel": "mlp_tiles_kernel (fused featurize+MLP+argmin)",
+                     "kernel_ms": main_r["kernel_ms"],
+                     "flops_per_variant": sum(layer_flops(widths))},
+    }
+    if not args.no_cpu_baseline:
+        cb, agree = cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, args.cpu_seconds,
+                                     best_by_prec)
+        out["cpu_baseline"] = cb
+    else:
+        agree = {}
+    out["precisions"] = {
+        p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+            "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
+            "argmin_agreement_vs_oracle_sample": agree.get(p)}
+        for p, r in results.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

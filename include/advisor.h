@@ -189,6 +189,18 @@ int advisor_rank(const advisor_model *model, const int64_t *kdesc, const int64_t
 int advisor_rank_preds(const float *pred, const int64_t *offsets, int64_t n_kernels,
                        int64_t n_variants, int64_t *best_out, void *stream);
 
+/*
+ * Measurement aid (not part of the method): while enabled, every launch of
+ * the fused tile kernel (advisor_rank, advisor_predict) is bracketed by a
+ * pair of HIP events recorded on the caller's stream. advisor_profile_read
+ * waits for the recorded events, returns the number of bracketed launches
+ * and their summed duration in milliseconds (either pointer may be NULL),
+ * and forgets them. Enabling or disabling also forgets them. Not thread-safe
+ * against concurrent calls that launch the tile kernel.
+ */
+int advisor_profile_enable(int on);
+int advisor_profile_read(int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

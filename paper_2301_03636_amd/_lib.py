@@ -55,6 +55,8 @@ def lib():
             "advisor_predict": ([P, P, i64, P, P], i32),
             "advisor_rank": ([P, P, P, P, i64, i64, P, P, P], i32),
             "advisor_rank_preds": ([P, P, i64, i64, P, P], i32),
+            "advisor_profile_enable": ([i32], i32),
+            "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -223,3 +225,19 @@ def advisor_rank_preds(pred, offsets, best_out=None):
     _check(lib().advisor_rank_preds(_ptr(pred), _ptr(offsets), nk, pred.shape[0], _ptr(best_out),
                                     _stream()), "advisor_rank_preds")
     return best_out
+
+
+# --------------------------------------------------------------------------- measurement
+
+
+def advisor_profile_enable(on: bool):
+    _check(lib().advisor_profile_enable(1 if on else 0), "advisor_profile_enable")
+
+
+def advisor_profile_read():
+    """(launches, summed milliseconds) of the tile-kernel launches bracketed
+    since profiling was enabled or last read."""
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    _check(lib().advisor_profile_read(C.byref(n), C.byref(ms)), "advisor_profile_read")
+    return n.value, ms.value

@@ -69,15 +69,19 @@ __device__ __forceinline__ bool featurize_one(const int64_t *__restrict__ kdesc,
     const uint64_t q = Pc / TH;
     const uint64_t waves = q + (Pc - q * TH != 0);
     const uint64_t S = (uint64_t)E * I;
-    uint64_t cnt[4] = {0, 0, 0, 0};
-    uint64_t ns = 0;
+    // arrays per map clause and strided arrays (no indexed register arrays)
+    uint64_t c_alloc = 0, c_to = 0, c_from = 0, c_tofrom = 0, ns = 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         if (a < A) {
-            cnt[m[a]] += 1;
+            c_alloc += m[a] == 0;
+            c_to += m[a] == 1;
+            c_from += m[a] == 2;
+            c_tofrom += m[a] == 3;
             ns += (uint64_t)k[7 + a];
         }
     }
+    const uint64_t cnt[4] = {c_alloc, c_to, c_from, c_tofrom};
     const uint64_t h2d = S * (cnt[1] + cnt[3]);
     const uint64_t d2h = S * (cnt[2] + cnt[3]);
     const uint64_t line = (uint64_t)(64u / (uint32_t)E);

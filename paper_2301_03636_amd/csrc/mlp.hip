@@ -2,10 +2,26 @@
 // width), kernel instances, the argmin-key set-up and read-out kernels, and
 // the advisor_predict / advisor_rank entry points.
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "mlp_tile.h"
 
 namespace adv {
+
+// Event pairs around tile-kernel launches while profiling is enabled.
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+
+static void prof_clear_locked()
+{
+    for (auto &e : g_prof_events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    g_prof_events.clear();
+}
 
 // Rows per tile: as many as fit LDS (activations [M][W] plus the input tile).
 template <int P, int W> struct TileRows {
@@ -54,8 +70,22 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
     const int64_t ntiles = (args.n_rows + M - 1) / M;
     const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus() * blocks_per_cu);
     if (grid <= 0) return ADVISOR_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        if (g_prof_on) {
+            ADV_HIP(hipEventCreate(&e0));
+            ADV_HIP(hipEventCreate(&e1));
+            ADV_HIP(hipEventRecord(e0, s));
+        }
+    }
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), C::LDS, s, args);
     ADV_LAUNCHED("mlp_tiles_kernel");
+    if (e0) {
+        std::lock_guard<std::mutex> lock(g_prof_mu);
+        ADV_HIP(hipEventRecord(e1, s));
+        g_prof_events.emplace_back(e0, e1);
+    }
     return ADVISOR_OK;
 }
 
@@ -156,5 +186,31 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
     }
     hipLaunchKernelGGL(keys_final_kernel, dim3(kb), dim3(256), 0, s, best_out, n_kernels);
     ADV_LAUNCHED("keys_final_kernel");
+    return ADVISOR_OK;
+}
+
+extern "C" int advisor_profile_enable(int on)
+{
+    clear_error();
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on = on != 0;
+    return ADVISOR_OK;
+}
+
+extern "C" int advisor_profile_read(int64_t *launches, double *total_ms)
+{
+    clear_error();
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    double sum = 0.0;
+    for (auto &e : g_prof_events) {
+        ADV_HIP(hipEventSynchronize(e.second));
+        float ms = 0.0f;
+        ADV_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        sum += ms;
+    }
+    if (launches) *launches = (int64_t)g_prof_events.size();
+    if (total_ms) *total_ms = sum;
+    prof_clear_locked();
     return ADVISOR_OK;
 }

@@ -138,7 +138,13 @@ struct TileCfg {
     static constexpr int PARTS = THREADS / M;              // threads per row in the input stage
     static_assert(PARTS >= 1 && NFEAT % PARTS == 0, "input split");
     static constexpr int FPP = NFEAT / PARTS;              // features per thread
-    static constexpr size_t LDS = (size_t)M * XS + (size_t)M * AS + (size_t)WN * M * 4 + M * 8;
+    // the activation region also parks the tile's int64 features during the
+    // input stage, so it holds whichever of the two is larger
+    static constexpr size_t ACT_BYTES = (size_t)M * AS > (size_t)M * NFEAT * 8
+                                            ? (size_t)M * AS : (size_t)M * NFEAT * 8;
+    static constexpr size_t LDS = (size_t)M * XS + ACT_BYTES + (size_t)WN * M * 4 + M * 8;
+    static_assert(M % 32 == 0 && (M * XS) % 16 == 0 && ACT_BYTES % 16 == 0, "LDS alignment");
+    static_assert(LDS <= 160 * 1024, "tile does not fit the 160 KiB of LDS");
 };
 
 // 16-byte-aligned LDS vector load (an fp8 vector is two 16-byte halves).
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *xin = lds;                                   // [M][XS]
     unsigned char *act = xin + (size_t)M * C::XS;               // [M][AS]
-    float *hpart = reinterpret_cast<float *>(act + (size_t)M * C::AS);  // [WN][M]
+    float *hpart = reinterpret_cast<float *>(act + C::ACT_BYTES);       // [WN][M]
     int *meta_ok = reinterpret_cast<int *>(hpart + C::WN * M);  // [M]
     int *meta_kid = meta_ok + M;                                // [M]
 
@@ -245,31 +251,50 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
-        // ---- input stage: PARTS threads per row, FPP features each
-        {
-            const int r = tid / C::PARTS, part = tid % C::PARTS;
-            const int64_t row = row0 + r;
-            bool ok = row < n;
-            int64_t kid = -1;
-            double xv[C::FPP];
-            if constexpr (SRC == SRC_DESC) {
+        // ---- input stage, step 1: one thread per row builds its 32 integer
+        // features and parks them in the activation buffer (free until layer
+        // 0 writes it), rotated by the row so the 8-byte stores spread over
+        // the banks
+        int64_t *fstage = reinterpret_cast<int64_t *>(act);
+        if constexpr (SRC == SRC_DESC) {
+            if (tid < M) {
+                const int64_t row = row0 + tid;
+                bool ok = row < n;
+                int64_t kid = -1;
                 Feat f;
                 if (ok) {
                     ok = featurize_one(args.kdesc, args.vdesc + row * VD, args.n_k, f);
                     kid = args.vdesc[row * VD];
                     if (SINK == SINK_RANK && ok)  // the variant must sit in its kernel's segment
                         ok = args.offsets[kid] <= row && row < args.offsets[kid + 1];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NFEAT; ++j) f.f[j] = 0;
                 }
 #pragma unroll
-                for (int q = 0; q < C::FPP; ++q) {
-                    const int j = part * C::FPP + q;
-                    xv[q] = ok ? zscore((int64_t)f.f[j], net.mu[j], net.sigma[j]) : 0.0;
-                }
-            } else {
+                for (int j = 0; j < NFEAT; ++j)
+                    fstage[tid * NFEAT + ((j + tid) & (NFEAT - 1))] = (int64_t)f.f[j];
+                meta_ok[tid] = ok ? 1 : 0;
+                meta_kid[tid] = (int)kid;
+            }
+            __syncthreads();
+        }
+        // step 2: PARTS threads per row standardize FPP features each in
+        // float64 and store them in the first layer's precision
+        {
+            const int r = tid % M, part = tid / M;
+            const int64_t row = row0 + r;
+            double xv[C::FPP];
 #pragma unroll
-                for (int q = 0; q < C::FPP; ++q) {
-                    const int j = part * C::FPP + q;
-                    xv[q] = ok ? zscore(args.feat[row * NFEAT + j], net.mu[j], net.sigma[j]) : 0.0;
+            for (int q = 0; q < C::FPP; ++q) {
+                const int j = part * C::FPP + q;
+                if constexpr (SRC == SRC_DESC) {
+                    const bool ok = meta_ok[r] != 0;
+                    const int64_t fv = fstage[r * NFEAT + ((j + r) & (NFEAT - 1))];
+                    xv[q] = ok ? zscore(fv, net.mu[j], net.sigma[j]) : 0.0;
+                } else {
+                    xv[q] = row < n ? zscore(args.feat[row * NFEAT + j], net.mu[j], net.sigma[j])
+                                    : 0.0;
                 }
             }
             unsigned char *xr = xin + (size_t)r * C::XS + part * C::FPP * G0::EB;
@@ -281,9 +306,11 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                 else
                     reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
             }
-            if (part == 0) {
-                meta_ok[r] = ok ? 1 : 0;
-                meta_kid[r] = (int)kid;
+            if constexpr (SRC == SRC_FEAT) {
+                if (part == 0) {
+                    meta_ok[r] = row < n ? 1 : 0;
+                    meta_kid[r] = -1;
+                }
             }
         }
         __syncthreads();
@@ -390,7 +417,7 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                 }
                 const int next = __shfl_down(kid, 1, 64);
                 const bool last = (lane == 63) || (next != kid);
-                if (last && kid >= 0 && key != ~0ull)
+                if (last && kid >= 0 && kid < args.n_k && key != ~0ull)
                     atomicMin(reinterpret_cast<unsigned long long *>(args.keys + kid),
                               (unsigned long long)key);
             }
