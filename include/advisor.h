@@ -190,6 +190,51 @@ int advisor_rank_preds(const float *pred, const int64_t *offsets, int64_t n_kern
                        int64_t n_variants, int64_t *best_out, void *stream);
 
 /*
+ * Training (section 5.3: the network is fit to measured runtimes with a
+ * squared-error loss; here Adam on the MSE, eq. RMSE squared). Only fp32 and
+ * bf16 models train (bf16: bf16 operands, fp32 accumulation, fp32 master
+ * weights). Calls on one model must not overlap: the model owns a workspace
+ * that grows (synchronous hipMalloc) to the largest batch seen.
+ *
+ * advisor_mlp_saved_bytes: size of the buffer advisor_mlp_forward fills for a
+ * batch of n rows (the transposed inputs and hidden activations), or -1.
+ */
+int64_t advisor_mlp_saved_bytes(const advisor_model *model, int64_t n);
+
+/* Forward pass for training: feat (device, int64 [n, 32]) -> y_out (device,
+ * float [n]) and saved (device, advisor_mlp_saved_bytes(model, n) bytes,
+ * caller-owned, read by advisor_mlp_backward). 1 <= n < 2^32. */
+int advisor_mlp_forward(advisor_model *model, const int64_t *feat, int64_t n, float *y_out,
+                        void *saved, void *stream);
+
+/* Backward pass: dy (device, float [n]) = dLoss/dy_hat for the rows of the
+ * forward call that filled `saved`; writes grads_out (device, float
+ * [param_count], the master layout: dW_l [out, in], db_l per layer) by the
+ * chain rule (ReLU derivative 0 at 0). Weights must be unchanged since the
+ * forward call. */
+int advisor_mlp_backward(advisor_model *model, const float *dy, const void *saved, int64_t n,
+                         float *grads_out, void *stream);
+
+/* One full training step on a batch: forward, float64 MSE loss
+ * L = (1/n) sum (y_hat - y)^2 with y (device, double [n], ln runtime in us),
+ * backward, float64 gradient 2-norm, and one Adam step (Kingma and Ba; t
+ * counts from 1, no weight decay) on the fp32 master weights, after which the
+ * compute copies are rebuilt. loss_out, gnorm_out (device, double [1]) may be
+ * NULL. 0 < lr, 0 <= beta1, beta2 < 1, eps >= 0. */
+int advisor_train_step(advisor_model *model, const int64_t *feat, const double *y, int64_t n,
+                       float lr, float beta1, float beta2, float eps, double *loss_out,
+                       double *gnorm_out, void *stream);
+
+/* Replace the fp32 master weights from a device buffer (float [param_count])
+ * and rebuild the compute copies; for optimizers that run outside the
+ * library. Adam state is left as it is. */
+int advisor_model_load_params(advisor_model *model, const float *w_master, void *stream);
+
+/* Copy the gradient of the last advisor_train_step (device, float
+ * [param_count]) into grads_out (device). */
+int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
+
+/*
  * Measurement aid (not part of the method): while enabled, every launch of
  * the fused tile kernel (advisor_rank, advisor_predict) is bracketed by a
  * pair of HIP events recorded on the caller's stream. advisor_profile_read

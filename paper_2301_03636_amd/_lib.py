@@ -55,6 +55,13 @@ def lib():
             "advisor_predict": ([P, P, i64, P, P], i32),
             "advisor_rank": ([P, P, P, P, i64, i64, P, P, P], i32),
             "advisor_rank_preds": ([P, P, i64, i64, P, P], i32),
+            "advisor_mlp_saved_bytes": ([P, i64], i64),
+            "advisor_mlp_forward": ([P, P, i64, P, P, P], i32),
+            "advisor_mlp_backward": ([P, P, P, i64, P, P], i32),
+            "advisor_train_step": ([P, P, P, i64, C.c_float, C.c_float, C.c_float, C.c_float, P, P,
+                                    P], i32),
+            "advisor_model_load_params": ([P, P, P], i32),
+            "advisor_model_grads": ([P, P, P], i32),
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
         }
@@ -241,3 +248,65 @@ def advisor_profile_read():
     ms = C.c_double(0.0)
     _check(lib().advisor_profile_read(C.byref(n), C.byref(ms)), "advisor_profile_read")
     return n.value, ms.value
+
+
+# --------------------------------------------------------------------------- training
+
+
+def advisor_mlp_saved_bytes(h, n) -> int:
+    return int(lib().advisor_mlp_saved_bytes(h, int(n)))
+
+
+def advisor_mlp_forward(h, feat, y_out=None, saved=None):
+    _dev(feat, torch.int64, "feat")
+    n = feat.shape[0]
+    if y_out is None:
+        y_out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    if saved is None:
+        saved = torch.empty(advisor_mlp_saved_bytes(h, n), dtype=torch.uint8, device=feat.device)
+    _dev(y_out, torch.float32, "y_out")
+    _dev(saved, torch.uint8, "saved")
+    if saved.numel() < advisor_mlp_saved_bytes(h, n):
+        raise ValueError("saved buffer too small")
+    _check(lib().advisor_mlp_forward(h, _ptr(feat), n, _ptr(y_out), _ptr(saved), _stream()),
+           "advisor_mlp_forward")
+    return y_out, saved
+
+
+def advisor_mlp_backward(h, dy, saved, n, grads_out=None):
+    _dev(dy, torch.float32, "dy")
+    _dev(saved, torch.uint8, "saved")
+    if grads_out is None:
+        grads_out = torch.empty(advisor_model_param_count(h), dtype=torch.float32, device=dy.device)
+    _dev(grads_out, torch.float32, "grads_out")
+    _check(lib().advisor_mlp_backward(h, _ptr(dy), _ptr(saved), int(n), _ptr(grads_out), _stream()),
+           "advisor_mlp_backward")
+    return grads_out
+
+
+def advisor_train_step(h, feat, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None,
+                       gnorm_out=None):
+    _dev(feat, torch.int64, "feat")
+    _dev(y, torch.float64, "y")
+    if loss_out is None:
+        loss_out = torch.empty(1, dtype=torch.float64, device=feat.device)
+    if gnorm_out is None:
+        gnorm_out = torch.empty(1, dtype=torch.float64, device=feat.device)
+    _check(lib().advisor_train_step(h, _ptr(feat), _ptr(y), feat.shape[0], lr, beta1, beta2, eps,
+                                    _ptr(loss_out), _ptr(gnorm_out), _stream()),
+           "advisor_train_step")
+    return loss_out, gnorm_out
+
+
+def advisor_model_load_params(h, w_master):
+    _dev(w_master, torch.float32, "w_master")
+    if w_master.numel() != advisor_model_param_count(h):
+        raise ValueError("parameter count mismatch")
+    _check(lib().advisor_model_load_params(h, _ptr(w_master), _stream()),
+           "advisor_model_load_params")
+
+
+def advisor_model_grads(h, grads_out):
+    _dev(grads_out, torch.float32, "grads_out")
+    _check(lib().advisor_model_grads(h, _ptr(grads_out), _stream()), "advisor_model_grads")
+    return grads_out

@@ -8,6 +8,8 @@
 
 #include "../../include/advisor.h"
 
+struct advisor_model;
+
 namespace adv {
 
 constexpr int NFEAT = ADVISOR_NFEAT;
@@ -36,6 +38,9 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 // Number of compute units of the current device (cached per device).
 int device_cus();
+
+// Training workspace release (train.hip).
+void free_train_ws(advisor_model *m);
 
 // Kernel-side view of a model's packed parameters.
 struct NetView {
@@ -78,4 +83,6 @@ struct advisor_model {
     float qscale[ADVISOR_MAX_LAYERS] = {0};  // fp8: wscale * ascale (dequantization)
     float qinv[ADVISOR_MAX_LAYERS] = {0};    // fp8: 1 / ascale of the next layer
     bool fp8_calibrated = false;
+    void *train_ws = nullptr;  // training workspace (train.hip), grown on demand
+    bool wt_valid = false;     // transposed packs (backward) match the master weights
 };

@@ -103,6 +103,10 @@ int dispatch_tiles(int precision, int W, const TileArgs &a, hipStream_t s)
     return fail(ADVISOR_EUNSUPPORTED, "no tile kernel for this precision and width");
 }
 
+// Training forward: predictions plus the transposed activations the
+// backward pass reads (fp32 and bf16 models).
+int launch_train_forward(const advisor_model *m, const TileArgs &a0, hipStream_t s);
+
 NetView net_view(const advisor_model *m)
 {
     NetView v{};
@@ -129,6 +133,19 @@ int check_model_ready(const advisor_model *m)
     ADV_HIP(hipGetDevice(&dev));
     if (dev != m->device) return fail(ADVISOR_EINVAL, "model lives on another device");
     return ADVISOR_OK;
+}
+
+int launch_train_forward(const advisor_model *m, const TileArgs &a0, hipStream_t s)
+{
+    TileArgs a = a0;
+    a.net = net_view(m);
+#define ADV_T(P, WW) \
+    if (m->precision == P && m->tile_w == WW) return launch_tiles<P, WW, SRC_FEAT, SINK_TRAIN>(a, s);
+    ADV_T(PREC_FP32, 64) ADV_T(PREC_FP32, 128) ADV_T(PREC_FP32, 256) ADV_T(PREC_FP32, 512)
+    ADV_T(PREC_FP32, 1024) ADV_T(PREC_BF16, 64) ADV_T(PREC_BF16, 128) ADV_T(PREC_BF16, 256)
+    ADV_T(PREC_BF16, 512) ADV_T(PREC_BF16, 1024)
+#undef ADV_T
+    return fail(ADVISOR_EUNSUPPORTED, "training needs an fp32 or bf16 model");
 }
 
 }  // namespace adv

@@ -30,7 +30,7 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 
 enum { PREC_FP32 = ADVISOR_FP32, PREC_BF16 = ADVISOR_BF16, PREC_FP8 = ADVISOR_FP8_E4M3 };
 enum { SRC_DESC = 0, SRC_FEAT = 1 };
-enum { SINK_PRED = 0, SINK_RANK = 1 };
+enum { SINK_PRED = 0, SINK_RANK = 1, SINK_TRAIN = 2 };
 
 // Per-precision fragment geometry. A lane loads KV consecutive k values in
 // one vector (16 or 32 bytes); each matrix-core op consumes KL of them per
@@ -119,7 +119,23 @@ struct TileArgs {
     // output
     float *pred;          // [n_rows] or null
     uint64_t *keys;       // [n_k] argmin keys (rank)
+    // training forward: transposed copies of what each layer consumed,
+    // x^T [32][save_ld] then h_l^T [W][save_ld] per hidden layer, in the
+    // layer's compute precision; rows >= n_rows are stored as zero
+    void *save_x;
+    void *save_h;
+    int64_t save_ld;
 };
+
+// Store one value of a saved activation (transposed layout) in precision P.
+template <int P>
+__device__ __forceinline__ void save_elem(void *base, int64_t idx, float v)
+{
+    if constexpr (P == PREC_FP32)
+        reinterpret_cast<float *>(base)[idx] = v;
+    else
+        reinterpret_cast<__bf16 *>(base)[idx] = (__bf16)v;
+}
 
 template <int P, int W, int M, int NWAVES>
 struct TileCfg {
@@ -246,7 +262,8 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
     const int half = lane >> 5, col = lane & 31;
     const NetView &net = args.net;
     const int64_t n = args.n_rows;
-    const int64_t ntiles = (n + M - 1) / M;
+    // the training forward covers every row of the saved buffers (zeros past n)
+    const int64_t ntiles = SINK == SINK_TRAIN ? args.save_ld / M : (n + M - 1) / M;
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
@@ -305,6 +322,9 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                     reinterpret_cast<float *>(xr)[q] = x;
                 else
                     reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
+                if constexpr (SINK == SINK_TRAIN)
+                    save_elem<P0>(args.save_x, (int64_t)(part * C::FPP + q) * args.save_ld + row,
+                                  row < n ? x : 0.0f);
             }
             if constexpr (SRC == SRC_FEAT) {
                 if (part == 0) {
@@ -348,6 +368,14 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                             }
                             const int m = (mb0 + j) * 32 + col;
                             store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
+                            if constexpr (SINK == SINK_TRAIN) {
+                                const int64_t rr = row0 + m;
+                                const int64_t base = ((int64_t)l * W + nn) * args.save_ld + rr;
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    save_elem<P>(args.save_h, base + e * args.save_ld,
+                                                 rr < n ? v[e] : 0.0f);
+                            }
                         }
                     }
                 }
@@ -369,7 +397,14 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const float z = acc[i][j][4 * g + e] * qs + bb[e];
-                                s += (z > 0.0f ? z : 0.0f) * ww[e];
+                                const float h = z > 0.0f ? z : 0.0f;
+                                s += h * ww[e];
+                                if constexpr (SINK == SINK_TRAIN) {
+                                    const int64_t rr = row0 + (mb0 + j) * 32 + col;
+                                    save_elem<P>(args.save_h,
+                                                 ((int64_t)l * W + nn + e) * args.save_ld + rr,
+                                                 rr < n ? h : 0.0f);
+                                }
                             }
                         }
                     }
@@ -389,7 +424,7 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                 for (int q = 0; q < C::WN; ++q) p += hpart[q * M + tid];
             }
             const bool ok = inrow && meta_ok[tid] != 0;
-            if constexpr (SINK == SINK_PRED) {
+            if constexpr (SINK == SINK_PRED || SINK == SINK_TRAIN) {
                 if (inrow && row < n) args.pred[row] = p;
             } else {
                 if (inrow && row < n && args.pred) args.pred[row] = ok ? p : __builtin_nanf("");

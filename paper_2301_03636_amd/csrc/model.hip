@@ -144,6 +144,7 @@ extern "C" void advisor_model_destroy(advisor_model *m)
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
+    free_train_ws(m);
     void *ptrs[] = {m->master, m->adam_m, m->adam_v, m->mu, m->sigma, m->bias, m->head,
                     m->d_layer_off, m->d_widths};
     for (void *p : ptrs)
@@ -268,6 +269,7 @@ extern "C" int advisor_model_set_params(advisor_model *m, const float *w_master,
     }
     m->step = 0;
     m->fp8_calibrated = false;
+    m->wt_valid = false;
     int rc = repack(m, nullptr);
     if (!rc) {
         e = hipDeviceSynchronize();

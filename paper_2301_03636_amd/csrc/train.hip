@@ -1,0 +1,671 @@
+// Training of the cost model (section 5.3: the network is fit to measured
+// runtimes; here with Adam on the MSE): the forward pass reuses the fused tile
+// kernel and saves transposed activations; a fused backward tile kernel runs
+// the chain of input gradients through all layers on the matrix cores; split-K
+// matrix-core kernels form the weight gradients; loss, gradient norm and the
+// order of every reduction are fixed (float64 where the loss and norm are
+// summed), so a step is deterministic.
+#include <algorithm>
+#include <mutex>
+
+#include "mlp_tile.h"
+
+namespace adv {
+
+int repack(advisor_model *m, hipStream_t s);  // model.hip
+
+// ---------------------------------------------------------------------------
+// Transposed packed weights for the backward chain: element (k, n) of
+// W_l^T (rows = inputs k, reduction over outputs n), same fragment order as
+// the forward packing.
+template <int P>
+__global__ void pack_transposed_kernel(const float *__restrict__ w, int out, int in, int tile_w,
+                                       void *__restrict__ dst)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)tile_w * tile_w) return;
+    const int k = (int)(idx / tile_w), n = (int)(idx % tile_w);
+    const float v = (n < out && k < in) ? w[(int64_t)n * in + k] : 0.0f;
+    const int64_t at = pack_index<P>(k, n, tile_w);
+    if constexpr (P == PREC_FP32)
+        reinterpret_cast<float *>(dst)[at] = v;
+    else
+        reinterpret_cast<__bf16 *>(dst)[at] = (__bf16)v;
+}
+
+template <int P> struct CT;
+template <> struct CT<PREC_FP32> { using T = float; };
+template <> struct CT<PREC_BF16> { using T = __bf16; };
+
+// ---------------------------------------------------------------------------
+// Backward chain over one tile of M rows:
+//   g_{L-1}[m][j] = dy[m] * w_out[j] * [h_{L-1}[m][j] > 0]
+//   g_{l-1}[m][k] = (sum_n g_l[m][n] W_l[n][k]) * [h_{l-1}[m][k] > 0]
+// Each g_l is written transposed ([W][ld], for the weight gradients); the
+// chain runs through LDS exactly like the forward pass, with W_l^T packed.
+struct BwdArgs {
+    const float *dy;        // [n] dL/dyhat
+    const float *head_w;    // [W] output-layer weights (padded)
+    const void *wt[MAX_LAYERS];
+    const void *save_h;     // h_l^T, layer l at l * W * ld
+    void *gt;               // g_l^T, layer l at l * W * ld
+    int64_t ld;
+    int64_t n;
+    int n_hidden;
+};
+
+template <int P, int W, int M, int NWAVES>
+__global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
+{
+    using C = TileCfg<P, W, M, NWAVES>;
+    using G = typename C::G;
+    using T = typename CT<P>::T;
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *act = lds;  // [M][AS]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wn = wave % C::WN, wm = wave / C::WN;
+    const int nb0 = wn * C::NBW, mb0 = wm * C::MBW;
+    const int half = lane >> 5, col = lane & 31;
+    const int64_t ld = a.ld, n = a.n;
+    const T *H = reinterpret_cast<const T *>(a.save_h);
+    T *GT = reinterpret_cast<T *>(a.gt);
+    const int L = a.n_hidden;
+    const int64_t ntiles = ld / M;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * M;
+        __syncthreads();
+        // seed: gradient at the last hidden layer's pre-activation
+        {
+            const T *Hl = H + (int64_t)(L - 1) * W * ld;
+            T *Gl = GT + (int64_t)(L - 1) * W * ld;
+            for (int idx = tid; idx < M * W; idx += C::THREADS) {
+                const int m = idx % M, j = idx / M;
+                const int64_t row = row0 + m;
+                const float d = row < n ? a.dy[row] : 0.0f;
+                const float h = (float)Hl[(int64_t)j * ld + row];
+                const float g = h > 0.0f ? d * a.head_w[j] : 0.0f;
+                const T gq = (T)g;
+                Gl[(int64_t)j * ld + row] = gq;
+                reinterpret_cast<T *>(act + (size_t)m * C::AS)[j] = gq;
+            }
+        }
+        __syncthreads();
+        v16f acc[C::NBW][C::MBW];
+        for (int l = L - 1; l >= 1; --l) {
+            layer_mma<P, W, C::NBW, C::MBW>(reinterpret_cast<const typename G::Vec *>(a.wt[l]),
+                                            act, C::AS, nb0, mb0, lane, acc);
+            __syncthreads();  // every wave has read g_l
+            const T *Hp = H + (int64_t)(l - 1) * W * ld;
+            T *Gp = GT + (int64_t)(l - 1) * W * ld;
+#pragma unroll
+            for (int i = 0; i < C::NBW; ++i) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int kk = (nb0 + i) * 32 + 8 * g + 4 * half;
+#pragma unroll
+                    for (int j = 0; j < C::MBW; ++j) {
+                        const int m = (mb0 + j) * 32 + col;
+                        const int64_t row = row0 + m;
+                        v4f v;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float h = (float)Hp[(int64_t)(kk + e) * ld + row];
+                            const float gv = h > 0.0f ? acc[i][j][4 * g + e] : 0.0f;
+                            const T gq = (T)gv;
+                            Gp[(int64_t)(kk + e) * ld + row] = gq;
+                            v[e] = (float)gq;
+                        }
+                        if (l > 1) store4<P>(act + (size_t)m * C::AS, kk, v, 1.0f);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient dW[n][k] = sum_b g^T[n][b] h^T[k][b] (both operands with
+// the batch contiguous), split over the batch into `splits` chunks whose fp32
+// partial tiles are summed in a fixed order by wgrad_reduce_kernel. A
+// workgroup of 4 waves owns a 128 x 128 output tile, each wave 64 x 64.
+template <int P>
+__global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__restrict__ A, int na,
+                                                    const typename CT<P>::T *__restrict__ B, int nb,
+                                                    int64_t ld, int64_t kchunk,
+                                                    float *__restrict__ partial)
+{
+    using G = Geo<P>;
+    using V = typename G::Vec;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    const int n0 = blockIdx.x * 128 + (wave & 1) * 64;   // rows of A (outputs)
+    const int k0 = blockIdx.y * 128 + (wave >> 1) * 64;  // rows of B (inputs)
+    const int64_t b0 = (int64_t)blockIdx.z * kchunk;
+    bool va[2], vb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        va[i] = n0 + 32 * i < na;
+        vb[i] = k0 + 32 * i < nb;
+    }
+    v16f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v16f{0};
+    const typename CT<P>::T *ap[2], *bp[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        ap[i] = A + (int64_t)(n0 + 32 * i + col) * ld + b0 + half * G::KV;
+        bp[i] = B + (int64_t)(k0 + 32 * i + col) * ld + b0 + half * G::KV;
+    }
+    for (int64_t kb = 0; kb < kchunk; kb += G::KG) {
+        V x[2], y[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            x[i] = va[i] ? *reinterpret_cast<const V *>(ap[i] + kb) : V{0};
+            y[i] = vb[i] ? *reinterpret_cast<const V *>(bp[i] + kb) : V{0};
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!(va[i] && vb[j])) continue;
+                if constexpr (P == PREC_FP32) {
+#pragma unroll
+                    for (int t = 0; t < G::KV; ++t) acc[i][j] = mma(x[i][t], y[j][t], acc[i][j]);
+                } else {
+                    acc[i][j] = mma(x[i], y[j], acc[i][j]);
+                }
+            }
+    }
+    // D[n][k]: lane holds column k = col, rows n = 8*(r/4) + 4*half + r%4
+    float *out = partial + (int64_t)blockIdx.z * na * nb;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!(va[i] && vb[j])) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int nn = n0 + 32 * i + 8 * (r / 4) + 4 * half + (r % 4);
+                const int kk = k0 + 32 * j + col;
+                out[(int64_t)nn * nb + kk] = acc[i][j][r];
+            }
+        }
+}
+
+// grads[off + n * in + k] = sum over splits of partial[s][n][k], n < out, k < in
+__global__ void wgrad_reduce_kernel(const float *__restrict__ partial, int splits, int na, int nb,
+                                    int out, int in, float *__restrict__ grads)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)out * in) return;
+    const int nn = (int)(idx / in), kk = (int)(idx % in);
+    float s = 0.0f;
+    for (int q = 0; q < splits; ++q) s += partial[((int64_t)q * na + nn) * nb + kk];
+    grads[idx] = s;
+}
+
+// One wave per output row: sum_b v[row][b] (times w[b] if given), b < n, in a
+// fixed order (lane-strided partial sums, then a butterfly).
+template <typename T>
+__global__ __launch_bounds__(256) void rowdot_kernel(const T *__restrict__ v, int64_t ld, int rows,
+                                                     int64_t n, const float *__restrict__ w,
+                                                     float *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const T *p = v + (int64_t)r * ld;
+    float s = 0.0f;
+    for (int64_t b = lane; b < n; b += 64) s += (float)p[b] * (w ? w[b] : 1.0f);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[r] = s;
+}
+
+// sum_b dy[b] (output-layer bias gradient), fixed order
+__global__ __launch_bounds__(64) void sum_kernel(const float *__restrict__ v, int64_t n,
+                                                 float *__restrict__ out)
+{
+    const int lane = threadIdx.x;
+    float s = 0.0f;
+    for (int64_t b = lane; b < n; b += 64) s += v[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Float64 reductions with a fixed tree: each of RB blocks sums a contiguous
+// chunk, then one block sums the RB partials in order.
+constexpr int RB = 256, RT = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Loss partials sum (pred - y)^2 and the output gradient dy = 2 (pred - y) / n.
+__global__ __launch_bounds__(RT) void loss_kernel(const float *__restrict__ pred,
+                                                  const double *__restrict__ y, int64_t n,
+                                                  float *__restrict__ dy, double *__restrict__ part)
+{
+    __shared__ double sh[RT];
+    const int64_t chunk = (n + RB - 1) / RB;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RT) {
+        const double r = (double)pred[i] - y[i];
+        s += r * r;
+        dy[i] = (float)(2.0 * r / (double)n);
+    }
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Partials of sum g^2 over the gradient vector.
+__global__ __launch_bounds__(RT) void sumsq_kernel(const float *__restrict__ g, int64_t n,
+                                                   double *__restrict__ part)
+{
+    __shared__ double sh[RT];
+    const int64_t chunk = (n + RB - 1) / RB;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RT) {
+        const double v = (double)g[i];
+        s += v * v;
+    }
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out = scale * sum(part[0..RB)), then sqrt if asked.
+__global__ void finish_kernel(const double *__restrict__ part, double scale, int take_sqrt,
+                              double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < RB; ++i) s += part[i];
+    s *= scale;
+    *out = take_sqrt ? sqrt(s) : s;
+}
+
+// Adam (Kingma and Ba) on fp32 master weights; c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                            const float *__restrict__ g, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Model-owned training workspace.
+struct TrainWs {
+    int64_t ld = 0;
+    void *saved = nullptr;    // x^T + h_l^T (used by advisor_train_step)
+    void *gt = nullptr;       // g_l^T
+    float *partial = nullptr; // wgrad partial tiles
+    float *pred = nullptr;
+    float *dy = nullptr;
+    float *grads = nullptr;
+    double *red = nullptr;    // RB partials
+    void *wt[MAX_LAYERS] = {nullptr};
+    size_t partial_floats = 0;
+};
+
+static std::mutex g_ws_mu;
+
+static size_t elem_bytes(const advisor_model *m) { return m->precision == PREC_FP32 ? 4 : 2; }
+
+static int64_t ld_for(int64_t n) { return ((n + 255) / 256) * 256; }
+
+// Batch splits of the weight-gradient product: enough workgroups to fill the
+// chip, each chunk a multiple of 64 rows (ld is a multiple of 256).
+static int splits_for(int na, int nb, int64_t ld)
+{
+    const int tiles = ((na + 127) / 128) * ((nb + 127) / 128);
+    int s = 1;
+    while (tiles * s < 256 && s < 64) s *= 2;
+    while (s > 1 && (ld / 64) % s != 0) s /= 2;
+    return s;
+}
+
+size_t saved_bytes(const advisor_model *m, int64_t n)
+{
+    const int64_t ld = ld_for(n);
+    return (size_t)(NFEAT + (int64_t)m->n_hidden * m->tile_w) * ld * elem_bytes(m);
+}
+
+TrainWs *train_ws(advisor_model *m) { return reinterpret_cast<TrainWs *>(m->train_ws); }
+
+void free_train_ws(advisor_model *m)
+{
+    TrainWs *w = train_ws(m);
+    if (!w) return;
+    void *ptrs[] = {w->saved, w->gt, w->partial, w->pred, w->dy, w->grads, w->red};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int l = 0; l < MAX_LAYERS; ++l)
+        if (w->wt[l]) (void)hipFree(w->wt[l]);
+    delete w;
+    m->train_ws = nullptr;
+}
+
+// Grow the workspace for batches of up to n rows (synchronous allocation).
+static int ensure_ws(advisor_model *m, int64_t n, bool with_saved)
+{
+    TrainWs *w = train_ws(m);
+    if (!w) {
+        w = new (std::nothrow) TrainWs();
+        if (!w) return fail(ADVISOR_ENOMEM, "host allocation");
+        m->train_ws = w;
+        const int tw = m->tile_w;
+        const size_t eb = elem_bytes(m);
+        for (int l = 1; l < m->n_hidden; ++l) ADV_HIP(hipMalloc(&w->wt[l], (size_t)tw * tw * eb));
+        ADV_HIP(hipMalloc(&w->grads, sizeof(float) * m->n_params));
+        ADV_HIP(hipMalloc(&w->red, sizeof(double) * 2 * RB));
+        size_t pf = 0;
+        for (int l = 0; l < m->n_hidden; ++l) {
+            const int na = tw, nb = l == 0 ? NFEAT : tw;
+            pf = std::max(pf, (size_t)64 * na * nb);
+        }
+        w->partial_floats = pf;
+        ADV_HIP(hipMalloc(&w->partial, sizeof(float) * pf));
+    }
+    const int64_t ld = ld_for(n);
+    if (ld > w->ld || (with_saved && !w->saved)) {
+        const int64_t newld = std::max(ld, w->ld);
+        for (void **p : {&w->saved, &w->gt, (void **)&w->pred, (void **)&w->dy})
+            if (*p) { (void)hipFree(*p); *p = nullptr; }
+        const size_t eb = elem_bytes(m);
+        ADV_HIP(hipMalloc(&w->gt, (size_t)m->n_hidden * m->tile_w * newld * eb));
+        ADV_HIP(hipMalloc((void **)&w->pred, sizeof(float) * newld));
+        ADV_HIP(hipMalloc((void **)&w->dy, sizeof(float) * newld));
+        ADV_HIP(hipMalloc(&w->saved, (size_t)(NFEAT + (int64_t)m->n_hidden * m->tile_w) * newld * eb));
+        w->ld = newld;
+    }
+    return ADVISOR_OK;
+}
+
+// W_l^T packs of layers 1..L-1 from the fp32 master weights.
+static int repack_transposed(advisor_model *m, hipStream_t s)
+{
+    TrainWs *w = train_ws(m);
+    const int tw = m->tile_w;
+    for (int l = 1; l < m->n_hidden; ++l) {
+        const float *src = m->master + m->layer_off[l];
+        const unsigned blocks = (unsigned)(((int64_t)tw * tw + 255) / 256);
+        if (m->precision == PREC_FP32)
+            hipLaunchKernelGGL(pack_transposed_kernel<PREC_FP32>, dim3(blocks), dim3(256), 0, s, src,
+                               m->widths[l + 1], m->widths[l], tw, w->wt[l]);
+        else
+            hipLaunchKernelGGL(pack_transposed_kernel<PREC_BF16>, dim3(blocks), dim3(256), 0, s, src,
+                               m->widths[l + 1], m->widths[l], tw, w->wt[l]);
+        ADV_LAUNCHED("pack_transposed_kernel");
+    }
+    m->wt_valid = true;
+    return ADVISOR_OK;
+}
+
+int launch_train_forward(const advisor_model *m, const TileArgs &a, hipStream_t s);  // mlp.hip
+
+template <int P, int W>
+static int launch_bwd(const BwdArgs &a, hipStream_t s)
+{
+    constexpr int M = P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32)) : (W <= 512 ? 128 : 64);
+    using C = TileCfg<P, W, M, 8>;
+    auto kern = bwd_tiles_kernel<P, W, M, 8>;
+    constexpr size_t lds = (size_t)M * C::AS;
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [&] {
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    });
+    if (err != hipSuccess) return hip_fail(err, "bwd kernel set-up");
+    const int64_t ntiles = a.ld / M;
+    const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus());
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), lds, s, a);
+    ADV_LAUNCHED("bwd_tiles_kernel");
+    return ADVISOR_OK;
+}
+
+static int dispatch_bwd(const advisor_model *m, const BwdArgs &a, hipStream_t s)
+{
+#define ADV_B(P, WW) if (m->precision == P && m->tile_w == WW) return launch_bwd<P, WW>(a, s);
+    ADV_B(PREC_FP32, 64) ADV_B(PREC_FP32, 128) ADV_B(PREC_FP32, 256) ADV_B(PREC_FP32, 512)
+    ADV_B(PREC_FP32, 1024) ADV_B(PREC_BF16, 64) ADV_B(PREC_BF16, 128) ADV_B(PREC_BF16, 256)
+    ADV_B(PREC_BF16, 512) ADV_B(PREC_BF16, 1024)
+#undef ADV_B
+    return fail(ADVISOR_EUNSUPPORTED, "training needs an fp32 or bf16 model");
+}
+
+// Gradients of every parameter (fp32, master layout) from the saved forward
+// state and dy = dL/dyhat; the core of advisor_mlp_backward and the step.
+static int backward_core(advisor_model *m, const float *dy, const void *saved, int64_t n,
+                         float *grads, hipStream_t s)
+{
+    TrainWs *w = train_ws(m);
+    const int tw = m->tile_w, L = m->n_hidden;
+    const int64_t ld = ld_for(n);
+    const size_t eb = elem_bytes(m);
+    if (!m->wt_valid) {
+        int rc = repack_transposed(m, s);
+        if (rc) return rc;
+    }
+    const unsigned char *xs = reinterpret_cast<const unsigned char *>(saved);
+    const unsigned char *hs = xs + (size_t)NFEAT * ld * eb;
+    // output layer: dW_out[j] = sum_b dy[b] h_{L-1}[b][j], db_out = sum_b dy[b]
+    float *g_head = grads + m->layer_off[L];
+    const int in_last = m->widths[L];
+    if (m->precision == PREC_FP32)
+        hipLaunchKernelGGL(rowdot_kernel<float>, dim3((in_last + 3) / 4), dim3(256), 0, s,
+                           reinterpret_cast<const float *>(hs + (size_t)(L - 1) * tw * ld * eb), ld,
+                           in_last, n, dy, g_head);
+    else
+        hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3((in_last + 3) / 4), dim3(256), 0, s,
+                           reinterpret_cast<const __bf16 *>(hs + (size_t)(L - 1) * tw * ld * eb), ld,
+                           in_last, n, dy, g_head);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s, dy, n, g_head + in_last);
+    ADV_LAUNCHED("output-layer gradient");
+    // chain of input gradients through the hidden layers
+    BwdArgs a{};
+    a.dy = dy;
+    a.head_w = m->head;
+    for (int l = 1; l < L; ++l) a.wt[l] = w->wt[l];
+    a.save_h = hs;
+    a.gt = w->gt;
+    a.ld = ld;
+    a.n = n;
+    a.n_hidden = L;
+    int rc = dispatch_bwd(m, a, s);
+    if (rc) return rc;
+    // weight and bias gradients per hidden layer
+    for (int l = 0; l < L; ++l) {
+        const int na = tw, nb = l == 0 ? NFEAT : tw;
+        const int out = m->widths[l + 1], in = m->widths[l];
+        const int splits = splits_for(na, nb, ld);
+        const int64_t kchunk = ld / splits;
+        const unsigned char *Ab = reinterpret_cast<const unsigned char *>(w->gt) + (size_t)l * tw * ld * eb;
+        const unsigned char *Bb = l == 0 ? xs : hs + (size_t)(l - 1) * tw * ld * eb;
+        dim3 grid((na + 127) / 128, (nb + 127) / 128, splits);
+        if (m->precision == PREC_FP32)
+            hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, grid, dim3(256), 0, s,
+                               reinterpret_cast<const float *>(Ab), na,
+                               reinterpret_cast<const float *>(Bb), nb, ld, kchunk, w->partial);
+        else
+            hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, grid, dim3(256), 0, s,
+                               reinterpret_cast<const __bf16 *>(Ab), na,
+                               reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, w->partial);
+        ADV_LAUNCHED("wgrad_kernel");
+        float *gw = grads + m->layer_off[l];
+        const int64_t ne = (int64_t)out * in;
+        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
+                           w->partial, splits, na, nb, out, in, gw);
+        float *gb = gw + ne;
+        if (m->precision == PREC_FP32)
+            hipLaunchKernelGGL(rowdot_kernel<float>, dim3((out + 3) / 4), dim3(256), 0, s,
+                               reinterpret_cast<const float *>(Ab), ld, out, n,
+                               (const float *)nullptr, gb);
+        else
+            hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3((out + 3) / 4), dim3(256), 0, s,
+                               reinterpret_cast<const __bf16 *>(Ab), ld, out, n,
+                               (const float *)nullptr, gb);
+        ADV_LAUNCHED("wgrad reduce / bias gradient");
+    }
+    return ADVISOR_OK;
+}
+
+static int check_trainable(const advisor_model *m)
+{
+    if (!m) return fail(ADVISOR_EINVAL, "null model");
+    if (m->precision != PREC_FP32 && m->precision != PREC_BF16)
+        return fail(ADVISOR_EUNSUPPORTED, "training needs an fp32 or bf16 model");
+    int dev = -1;
+    ADV_HIP(hipGetDevice(&dev));
+    if (dev != m->device) return fail(ADVISOR_EINVAL, "model lives on another device");
+    return ADVISOR_OK;
+}
+
+}  // namespace adv
+
+using namespace adv;
+
+extern "C" int64_t advisor_mlp_saved_bytes(const advisor_model *m, int64_t n)
+{
+    if (!m || n < 0) return -1;
+    return (int64_t)saved_bytes(m, n);
+}
+
+extern "C" int advisor_mlp_forward(advisor_model *m, const int64_t *feat, int64_t n, float *y_out,
+                                   void *saved, void *stream)
+{
+    clear_error();
+    int rc = check_trainable(m);
+    if (rc) return rc;
+    if (n < 1 || n >= ((int64_t)1 << 32)) return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+    if (!feat || !y_out || !saved) return fail(ADVISOR_EINVAL, "advisor_mlp_forward: null pointer");
+    const int64_t ld = ld_for(n);
+    TileArgs a{};
+    a.feat = feat;
+    a.n_rows = n;
+    a.pred = y_out;
+    a.save_ld = ld;
+    a.save_x = saved;
+    a.save_h = reinterpret_cast<unsigned char *>(saved) + (size_t)NFEAT * ld * elem_bytes(m);
+    return launch_train_forward(m, a, as_stream(stream));
+}
+
+extern "C" int advisor_mlp_backward(advisor_model *m, const float *dy, const void *saved, int64_t n,
+                                    float *grads_out, void *stream)
+{
+    clear_error();
+    int rc = check_trainable(m);
+    if (rc) return rc;
+    if (n < 1 || n >= ((int64_t)1 << 32)) return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+    if (!dy || !saved || !grads_out) return fail(ADVISOR_EINVAL, "advisor_mlp_backward: null pointer");
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    rc = ensure_ws(m, n, false);
+    if (rc) return rc;
+    return backward_core(m, dy, saved, n, grads_out, as_stream(stream));
+}
+
+extern "C" int advisor_train_step(advisor_model *m, const int64_t *feat, const double *y, int64_t n,
+                                  float lr, float beta1, float beta2, float eps, double *loss_out,
+                                  double *gnorm_out, void *stream)
+{
+    clear_error();
+    int rc = check_trainable(m);
+    if (rc) return rc;
+    if (n < 1 || n >= ((int64_t)1 << 32)) return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+    if (!feat || !y) return fail(ADVISOR_EINVAL, "advisor_train_step: null pointer");
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps >= 0.0f))
+        return fail(ADVISOR_EINVAL, "bad Adam hyper-parameters");
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    rc = ensure_ws(m, n, true);
+    if (rc) return rc;
+    TrainWs *w = train_ws(m);
+    hipStream_t s = as_stream(stream);
+    const int64_t ld = ld_for(n);
+    // forward, saving what the backward needs
+    TileArgs a{};
+    a.feat = feat;
+    a.n_rows = n;
+    a.pred = w->pred;
+    a.save_ld = ld;
+    a.save_x = w->saved;
+    a.save_h = reinterpret_cast<unsigned char *>(w->saved) + (size_t)NFEAT * ld * elem_bytes(m);
+    rc = launch_train_forward(m, a, s);
+    if (rc) return rc;
+    // float64 MSE and dL/dyhat
+    hipLaunchKernelGGL(loss_kernel, dim3(RB), dim3(RT), 0, s, w->pred, y, n, w->dy, w->red);
+    if (loss_out)
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, w->red, 1.0 / (double)n, 0,
+                           loss_out);
+    ADV_LAUNCHED("loss kernels");
+    rc = backward_core(m, w->dy, w->saved, n, w->grads, s);
+    if (rc) return rc;
+    // float64 gradient norm
+    if (gnorm_out) {
+        hipLaunchKernelGGL(sumsq_kernel, dim3(RB), dim3(RT), 0, s, w->grads, m->n_params,
+                           w->red + RB);
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, w->red + RB, 1.0, 1, gnorm_out);
+        ADV_LAUNCHED("gradient norm kernels");
+    }
+    // Adam on the fp32 master weights, then new compute copies
+    m->step += 1;
+    const double c1 = 1.0 - pow((double)beta1, (double)m->step);
+    const double c2 = 1.0 - pow((double)beta2, (double)m->step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((m->n_params + 255) / 256)), dim3(256), 0, s,
+                       m->master, m->adam_m, m->adam_v, w->grads, m->n_params, lr, beta1, beta2, eps,
+                       (float)c1, (float)c2);
+    ADV_LAUNCHED("adam_kernel");
+    rc = repack(m, s);
+    if (rc) return rc;
+    return repack_transposed(m, s);
+}
+
+// Replace the fp32 master parameters from a device buffer (for optimizers
+// driven outside the library) and rebuild every compute copy.
+extern "C" int advisor_model_load_params(advisor_model *m, const float *w_master, void *stream)
+{
+    clear_error();
+    if (!m || !w_master) return fail(ADVISOR_EINVAL, "load_params: null pointer");
+    if (m->precision == PREC_FP8)
+        return fail(ADVISOR_EUNSUPPORTED, "fp8 models take parameters through set_params");
+    hipStream_t s = as_stream(stream);
+    ADV_HIP(hipMemcpyAsync(m->master, w_master, sizeof(float) * m->n_params,
+                           hipMemcpyDeviceToDevice, s));
+    int rc = repack(m, s);
+    if (rc) return rc;
+    m->wt_valid = false;
+    return ADVISOR_OK;
+}
+
+extern "C" int advisor_model_grads(const advisor_model *m, float *grads_out, void *stream)
+{
+    clear_error();
+    if (!m || !grads_out) return fail(ADVISOR_EINVAL, "model_grads: null pointer");
+    TrainWs *w = reinterpret_cast<TrainWs *>(m->train_ws);
+    if (!w) return fail(ADVISOR_EINVAL, "no training step has run on this model");
+    ADV_HIP(hipMemcpyAsync(grads_out, w->grads, sizeof(float) * m->n_params,
+                           hipMemcpyDeviceToDevice, as_stream(stream)));
+    return ADVISOR_OK;
+}
