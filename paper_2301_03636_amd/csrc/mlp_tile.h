@@ -155,9 +155,11 @@ struct TileCfg {
     static_assert(PARTS >= 1 && NFEAT % PARTS == 0, "input split");
     static constexpr int FPP = NFEAT / PARTS;              // features per thread
     // the activation region also parks the tile's int64 features during the
-    // input stage, so it holds whichever of the two is larger
-    static constexpr size_t ACT_BYTES = (size_t)M * AS > (size_t)M * NFEAT * 8
-                                            ? (size_t)M * AS : (size_t)M * NFEAT * 8;
+    // input stage (rows of FS = 33 int64, one spare to spread the banks), so
+    // it holds whichever of the two is larger
+    static constexpr int FS = NFEAT + 1;
+    static constexpr size_t ACT_BYTES = (size_t)M * AS > (size_t)M * FS * 8
+                                            ? (size_t)M * AS : (size_t)M * FS * 8;
     static constexpr size_t LDS = (size_t)M * XS + ACT_BYTES + (size_t)WN * M * 4 + M * 8;
     static_assert(M % 32 == 0 && (M * XS) % 16 == 0 && ACT_BYTES % 16 == 0, "LDS alignment");
     static_assert(LDS <= 160 * 1024, "tile does not fit the 160 KiB of LDS");
@@ -182,7 +184,11 @@ __device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
 }
 
 // acc[i][j] += W (A vectors streamed from global/L2) x act^T (B vectors from
-// LDS) over the K inputs of one layer.
+// LDS) over the K inputs of one layer. Software-pipelined: the weight vectors
+// of k-group kg + PF are requested while group kg is multiplied (a ring of PF
+// register slots, PF dividing the group count so every slot index is a
+// compile-time constant), and the LDS operands of kg + 1 are read while kg is
+// multiplied.
 template <int PL, int K, int NBW, int MBW>
 __device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restrict__ wl,
                                           const unsigned char *lds_in, int stride, int nb0,
@@ -191,31 +197,60 @@ __device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restric
     using G = Geo<PL>;
     using V = typename G::Vec;
     constexpr int KGROUPS = K / G::KG;
+    constexpr int PF = (KGROUPS % 2 == 0 && sizeof(V) <= 16) ? 2 : 1;  // 32-byte fp8 vectors: 1
     const int half = lane >> 5, col = lane & 31;
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
         for (int j = 0; j < MBW; ++j) acc[i][j] = v16f{0};
     const unsigned char *bbase = lds_in + (size_t)(mb0 * 32 + col) * stride + half * G::KV * G::EB;
-#pragma unroll 2
-    for (int kg = 0; kg < KGROUPS; ++kg) {
-        V a[NBW], b[MBW];
+    const V *abase = wl + (int64_t)nb0 * KGROUPS * 64 + lane;
+    V ring[PF][NBW];
 #pragma unroll
-        for (int i = 0; i < NBW; ++i) a[i] = wl[((int64_t)(nb0 + i) * KGROUPS + kg) * 64 + lane];
+    for (int p = 0; p < PF; ++p)
 #pragma unroll
-        for (int j = 0; j < MBW; ++j)
-            b[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride + kg * G::KG * G::EB);
+        for (int i = 0; i < NBW; ++i) ring[p][i] = abase[((int64_t)i * KGROUPS + p) * 64];
+    V bcur[MBW];
 #pragma unroll
-        for (int i = 0; i < NBW; ++i)
+    for (int j = 0; j < MBW; ++j) bcur[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride);
+    for (int kg0 = 0; kg0 < KGROUPS; kg0 += PF) {
 #pragma unroll
-            for (int j = 0; j < MBW; ++j) {
-                if constexpr (PL == PREC_FP32) {
+        for (int u = 0; u < PF; ++u) {
+            const int kg = kg0 + u;
+            V a[NBW];
 #pragma unroll
-                    for (int t = 0; t < G::KV; ++t) acc[i][j] = mma(a[i][t], b[j][t], acc[i][j]);
-                } else {
-                    acc[i][j] = mma(a[i], b[j], acc[i][j]);
-                }
+            for (int i = 0; i < NBW; ++i) a[i] = ring[u][i];
+            if (kg + PF < KGROUPS) {
+#pragma unroll
+                for (int i = 0; i < NBW; ++i)
+                    ring[u][i] = abase[((int64_t)i * KGROUPS + kg + PF) * 64];
             }
+            V bnext[MBW];
+            if (kg + 1 < KGROUPS) {
+#pragma unroll
+                for (int j = 0; j < MBW; ++j)
+                    bnext[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride + (kg + 1) * G::KG * G::EB);
+            }
+            // keep the requests above ahead of the multiplies below: without
+            // this the scheduler sinks each load next to its first use
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < NBW; ++i)
+#pragma unroll
+                for (int j = 0; j < MBW; ++j) {
+                    if constexpr (PL == PREC_FP32) {
+#pragma unroll
+                        for (int t = 0; t < G::KV; ++t)
+                            acc[i][j] = mma(a[i][t], bcur[j][t], acc[i][j]);
+                    } else {
+                        acc[i][j] = mma(a[i], bcur[j], acc[i][j]);
+                    }
+                }
+            if (kg + 1 < KGROUPS) {
+#pragma unroll
+                for (int j = 0; j < MBW; ++j) bcur[j] = bnext[j];
+            }
+        }
     }
 }
 
@@ -270,8 +305,8 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
         // ---- input stage, step 1: one thread per row builds its 32 integer
         // features and parks them in the activation buffer (free until layer
-        // 0 writes it), rotated by the row so the 8-byte stores spread over
-        // the banks
+        // 0 writes it), in rows padded to 33 entries so neighbouring rows
+        // start in different banks
         int64_t *fstage = reinterpret_cast<int64_t *>(act);
         if constexpr (SRC == SRC_DESC) {
             if (tid < M) {
@@ -289,8 +324,7 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                     for (int j = 0; j < NFEAT; ++j) f.f[j] = 0;
                 }
 #pragma unroll
-                for (int j = 0; j < NFEAT; ++j)
-                    fstage[tid * NFEAT + ((j + tid) & (NFEAT - 1))] = (int64_t)f.f[j];
+                for (int j = 0; j < NFEAT; ++j) fstage[tid * C::FS + j] = (int64_t)f.f[j];
                 meta_ok[tid] = ok ? 1 : 0;
                 meta_kid[tid] = (int)kid;
             }
@@ -307,7 +341,7 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                 const int j = part * C::FPP + q;
                 if constexpr (SRC == SRC_DESC) {
                     const bool ok = meta_ok[r] != 0;
-                    const int64_t fv = fstage[r * NFEAT + ((j + r) & (NFEAT - 1))];
+                    const int64_t fv = fstage[r * C::FS + j];
                     xv[q] = ok ? zscore(fv, net.mu[j], net.sigma[j]) : 0.0;
                 } else {
                     xv[q] = row < n ? zscore(args.feat[row * NFEAT + j], net.mu[j], net.sigma[j])
@@ -352,12 +386,19 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
             const float qs = (P == PREC_FP8 && l > 0) ? net.qscale[l] : 1.0f;
             if (l + 1 < net.n_hidden) {
                 const float qinv = net.qinv[l];
+                v4f bias_r[C::NBW][4];  // all loads in flight at once
+#pragma unroll
+                for (int i = 0; i < C::NBW; ++i)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        bias_r[i][g] = *reinterpret_cast<const v4f *>(
+                            bias + (nb0 + i) * 32 + 8 * g + 4 * half);
 #pragma unroll
                 for (int i = 0; i < C::NBW; ++i) {
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
-                        const v4f bb = *reinterpret_cast<const v4f *>(bias + nn);
+                        const v4f bb = bias_r[i][g];
 #pragma unroll
                         for (int j = 0; j < C::MBW; ++j) {
                             v4f v;
@@ -384,6 +425,15 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                 // output layer: per-lane partial dot products of the ReLU'd
                 // last hidden layer with the head weights (fp32)
                 const float *hw = net.head_w;
+                v4f bias_r[C::NBW][4], hw_r[C::NBW][4];  // all loads in flight at once
+#pragma unroll
+                for (int i = 0; i < C::NBW; ++i)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                        bias_r[i][g] = *reinterpret_cast<const v4f *>(bias + nn);
+                        hw_r[i][g] = *reinterpret_cast<const v4f *>(hw + nn);
+                    }
 #pragma unroll
                 for (int j = 0; j < C::MBW; ++j) {
                     float s = 0.0f;
@@ -392,8 +442,8 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
-                            const v4f bb = *reinterpret_cast<const v4f *>(bias + nn);
-                            const v4f ww = *reinterpret_cast<const v4f *>(hw + nn);
+                            const v4f bb = bias_r[i][g];
+                            const v4f ww = hw_r[i][g];
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const float z = acc[i][j][4 * g + e] * qs + bb[e];

@@ -441,7 +441,7 @@ static int launch_bwd(const BwdArgs &a, hipStream_t s)
     if (err != hipSuccess) return hip_fail(err, "bwd kernel set-up");
     const int64_t ntiles = a.ld / M;
     const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus());
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
     ADV_LAUNCHED("bwd_tiles_kernel");
     return ADVISOR_OK;
 }
