@@ -142,6 +142,49 @@ def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds, gpu_best_by_p
     }, agree
 
 
+def train_flops_per_sample(widths):
+    """Forward, input gradients of every layer but the first, and weight
+    gradients of every layer: 2 flops per multiply-add."""
+    fl = layer_flops(widths)
+    return sum(fl) + sum(fl[1:]) + sum(fl)
+
+
+def train_leg(adv, torch, d, steps, warmup):
+    """Training throughput: batch 65536 of the 4096-kernel workload, bf16
+    32-512x4-1, Adam lr 1e-3, float64 loss and gradient norm. The targets are
+    seeded draws of the same scale as ln(runtime in us) (the timing does not
+    depend on their values; the tests train on the synthetic runtime model)."""
+    c = workload.CONFIGS[4]
+    s = workload.seeds(4)
+    widths = tuple(c["widths"])
+    B = c["batch"]
+    kd, vd, off = workload.make_descriptors(c["n_kernels"], c["count_lo"], c["count_hi"], s["desc"])
+    rows = workload.sample_rows(vd.shape[0], B, s["desc"] + 11)
+    feat, inv = adv.advisor_featurize(torch.from_numpy(kd).to(d), torch.from_numpy(vd[rows]).to(d))
+    assert int(inv.sum().item()) == 0
+    mu, sd = adv.advisor_zscore_fit(feat)
+    y = torch.from_numpy(10.0 + 3.0 * workload.noise(B, s["noise"])).to(d)
+    m = adv.Model(widths, "bf16")
+    m.set_params(workload.he_init(widths, s["w"]), mu.cpu().numpy(), sd.cpu().numpy())
+    loss = torch.empty(1, dtype=torch.float64, device=d)
+    gn = torch.empty(1, dtype=torch.float64, device=d)
+    for _ in range(warmup):
+        adv.advisor_train_step(m.handle, feat, y, 1e-3, 0.9, 0.999, 1e-8, loss, gn)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        adv.advisor_train_step(m.handle, feat, y, 1e-3, 0.9, 0.999, 1e-8, loss, gn)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    m.close()
+    fps = train_flops_per_sample(widths)
+    tflops = fps * B / (ms / 1e3) / 1e12
+    return {"workload": "batch 65536 of 4096 kernels, 32-512x4-1, bf16, Adam",
+            "steps_per_s": 1e3 / ms, "samples_per_s": B / (ms / 1e3), "ms_per_step": ms,
+            "flops_per_sample": fps, "tflops": tflops, "peak": PEAK_TFLOPS["bf16"],
+            "roofline_frac": tflops / PEAK_TFLOPS["bf16"], "loss_last": float(loss.item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +195,8 @@ def main():
     ap.add_argument("--also", default="bf16",
                     help="comma-separated extra precisions timed on the same inputs ('' for none)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--train-steps", type=int, default=20,
+                    help="timed training steps (batch 65536, bf16 32-512x4-1); 0 to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the "
@@ -188,18 +233,18 @@ def main():
     # Z-score statistics from a seeded calibration sample, fitted on the GPU
     cal = T(workload.sample_rows(nv, 65536, workload.seeds(cfg)["desc"] + 7))
     feat_cal, inv_cal = adv.advisor_featurize(kdd, vdd[cal])
-    mu_d, sd_d = adv.advisor_zscore_fit(feat_cal[inv_cal == 0].contiguous())
+    feat_cal = feat_cal[inv_cal == 0].contiguous()
+    mu_d, sd_d = adv.advisor_zscore_fit(feat_cal)
     mu, sd = mu_d.cpu().numpy(), sd_d.cpu().numpy()
-    del feat_cal, inv_cal
 
     results = {}
     best_by_prec = {}
     precs = [prec] + [p for p in args.also.split(",") if p and p != prec]
     for p in precs:
-        if p == "fp8":
-            continue  # needs calibration support
         m = adv.Model(widths, p)
         m.set_params(params, mu, sd)
+        if p == "fp8":
+            m.calibrate_fp8(feat_cal)
         best = torch.empty(nk, dtype=torch.int64, device=d)
         ms, kern_ms, launches = time_rank(adv, torch, m, kdd, vdd, offd, best,
                                           args.steps if p == prec else max(5, args.steps // 2),
@@ -210,6 +255,7 @@ def main():
                           value=nv / (ms / 1e3),
                           tflops=fl * nv / (kern_ms / 1e3) / 1e12)
         m.close()
+    del feat_cal, inv_cal
 
     main_r = results[prec]
     peak = roofline_peak(widths, prec)
@@ -247,6 +293,8 @@ def main():
             "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
             "argmin_agreement_vs_oracle_sample": agree.get(p)}
         for p, r in results.items()}
+    if args.train_steps > 0:
+        out["train"] = train_leg(adv, torch, d, args.train_steps, args.warmup)
     print(json.dumps(out), flush=True)
 
 

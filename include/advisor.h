@@ -116,6 +116,24 @@ int advisor_model_get_adam(const advisor_model *model, float *m, float *v, int64
 int advisor_model_set_adam(advisor_model *model, const float *m, const float *v, int64_t step);
 
 /*
+ * Static activation scales of an ADVISOR_FP8_E4M3 model (required before it
+ * predicts or ranks; cleared by advisor_model_set_params). Runs the model in
+ * bf16 on feat (device, int64 [n, 32], a calibration sample of variants,
+ * 1 <= n < 2^32) and sets each hidden layer's input scale to
+ * amax(activation) / 448, the e4m3 maximum; weights were quantized per
+ * tensor with amax(|W_l|) / 448 when the parameters were loaded. Conversion
+ * is round-to-nearest-even with saturation to +-448. Synchronizes the stream;
+ * allocates temporary device memory.
+ */
+int advisor_model_calibrate_fp8(advisor_model *model, const int64_t *feat, int64_t n,
+                                void *stream);
+
+/* Per-layer fp8 scales (host, float [n_hidden] each): weight scale of each
+ * hidden layer, and the input-activation scale of each hidden layer (1 for
+ * the bf16 first layer). */
+int advisor_model_get_fp8_scales(const advisor_model *model, float *wscale, float *ascale);
+
+/*
  * Feature extraction (the Feature Extraction step of the training and
  * prediction flows, section 3; the paper does not list its features, this
  * library defines 32). For each variant i (device inputs kdesc, vdesc as in

@@ -62,6 +62,8 @@ def lib():
                                     P], i32),
             "advisor_model_load_params": ([P, P, P], i32),
             "advisor_model_grads": ([P, P, P], i32),
+            "advisor_model_calibrate_fp8": ([P, P, i64, P], i32),
+            "advisor_model_get_fp8_scales": ([P, P, P], i32),
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
         }
@@ -166,6 +168,21 @@ def advisor_model_set_zscore(h, mu, sigma):
     _dev(sigma, torch.float64, "sigma")
     _check(lib().advisor_model_set_zscore(h, _ptr(mu), _ptr(sigma), _stream()),
            "advisor_model_set_zscore")
+
+
+def advisor_model_calibrate_fp8(h, feat):
+    _dev(feat, torch.int64, "feat")
+    _check(lib().advisor_model_calibrate_fp8(h, _ptr(feat), feat.shape[0], _stream()),
+           "advisor_model_calibrate_fp8")
+
+
+def advisor_model_get_fp8_scales(h, n_hidden):
+    w = np.zeros(n_hidden, dtype=np.float32)
+    a = np.zeros(n_hidden, dtype=np.float32)
+    _check(lib().advisor_model_get_fp8_scales(h, w.ctypes.data_as(C.c_void_p),
+                                              a.ctypes.data_as(C.c_void_p)),
+           "advisor_model_get_fp8_scales")
+    return w, a
 
 
 # --------------------------------------------------------------------------- hot path

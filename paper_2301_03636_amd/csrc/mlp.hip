@@ -29,7 +29,12 @@ template <int P, int W> struct TileRows {
         P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
                        : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : (W <= 512 ? 128 : 64));
 };
-constexpr int TILE_WAVES = 8;
+// Waves per workgroup: 8 (two per SIMD, 256 registers each) except for the
+// 1024-wide bf16/fp8 tiles, whose accumulators need one wave per SIMD and
+// its 512 registers.
+template <int P, int W> struct TileWaves {
+    static constexpr int value = (W == 1024 && P != PREC_FP32) ? 4 : 8;
+};
 
 __global__ void keys_init_kernel(uint64_t *keys, int64_t n)
 {
@@ -51,8 +56,9 @@ template <int P, int W, int SRC, int SINK>
 int launch_tiles(const TileArgs &args, hipStream_t s)
 {
     constexpr int M = TileRows<P, W>::value;
-    using C = TileCfg<P, W, M, TILE_WAVES>;
-    auto kern = mlp_tiles_kernel<P, W, M, TILE_WAVES, SRC, SINK>;
+    constexpr int NW = TileWaves<P, W>::value;
+    using C = TileCfg<P, W, M, NW>;
+    auto kern = mlp_tiles_kernel<P, W, M, NW, SRC, SINK>;
     static std::once_flag once;
     static int blocks_per_cu = 1;
     static hipError_t setup_err = hipSuccess;

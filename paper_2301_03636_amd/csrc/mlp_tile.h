@@ -386,19 +386,20 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
             const float qs = (P == PREC_FP8 && l > 0) ? net.qscale[l] : 1.0f;
             if (l + 1 < net.n_hidden) {
                 const float qinv = net.qinv[l];
-                v4f bias_r[C::NBW][4];  // all loads in flight at once
-#pragma unroll
-                for (int i = 0; i < C::NBW; ++i)
-#pragma unroll
-                    for (int g = 0; g < 4; ++g)
-                        bias_r[i][g] = *reinterpret_cast<const v4f *>(
-                            bias + (nb0 + i) * 32 + 8 * g + 4 * half);
+                // one 32-neuron block at a time: its 4 bias vectors are loaded
+                // together, and the fence keeps the next block's loads from
+                // being hoisted (which would raise register pressure)
 #pragma unroll
                 for (int i = 0; i < C::NBW; ++i) {
+                    v4f bias_r[4];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        bias_r[g] = *reinterpret_cast<const v4f *>(
+                            bias + (nb0 + i) * 32 + 8 * g + 4 * half);
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
-                        const v4f bb = bias_r[i][g];
+                        const v4f bb = bias_r[g];
 #pragma unroll
                         for (int j = 0; j < C::MBW; ++j) {
                             v4f v;
@@ -419,36 +420,36 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                             }
                         }
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 __syncthreads();  // next layer reads the complete activations
             } else {
                 // output layer: per-lane partial dot products of the ReLU'd
-                // last hidden layer with the head weights (fp32)
+                // last hidden layer with the head weights (fp32), summed per
+                // row over blocks, groups and elements in a fixed order
                 const float *hw = net.head_w;
-                v4f bias_r[C::NBW][4], hw_r[C::NBW][4];  // all loads in flight at once
+                float srow[C::MBW];
 #pragma unroll
-                for (int i = 0; i < C::NBW; ++i)
+                for (int j = 0; j < C::MBW; ++j) srow[j] = 0.0f;
+#pragma unroll
+                for (int i = 0; i < C::NBW; ++i) {
+                    v4f bias_r[4], hw_r[4];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
-                        bias_r[i][g] = *reinterpret_cast<const v4f *>(bias + nn);
-                        hw_r[i][g] = *reinterpret_cast<const v4f *>(hw + nn);
+                        bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
+                        hw_r[g] = *reinterpret_cast<const v4f *>(hw + nn);
                     }
 #pragma unroll
-                for (int j = 0; j < C::MBW; ++j) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int i = 0; i < C::NBW; ++i) {
+                    for (int j = 0; j < C::MBW; ++j) {
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
-                            const v4f bb = bias_r[i][g];
-                            const v4f ww = hw_r[i][g];
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
-                                const float z = acc[i][j][4 * g + e] * qs + bb[e];
+                                const float z = acc[i][j][4 * g + e] * qs + bias_r[g][e];
                                 const float h = z > 0.0f ? z : 0.0f;
-                                s += h * ww[e];
+                                srow[j] += h * hw_r[g][e];
                                 if constexpr (SINK == SINK_TRAIN) {
                                     const int64_t rr = row0 + (mb0 + j) * 32 + col;
                                     save_elem<P>(args.save_h,
@@ -458,8 +459,13 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                             }
                         }
                     }
-                    s += __shfl_xor(s, 32, 64);  // the two lane halves hold different neurons
-                    if (half == 0) hpart[wn * M + (mb0 + j) * 32 + col] = s;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int j = 0; j < C::MBW; ++j) {
+                    float sj = srow[j];
+                    sj += __shfl_xor(sj, 32, 64);  // the two lane halves hold different neurons
+                    if (half == 0) hpart[wn * M + (mb0 + j) * 32 + col] = sj;
                 }
             }
         }

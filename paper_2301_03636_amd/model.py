@@ -27,6 +27,12 @@ class Model:
     def set_zscore(self, mu, sigma):
         _lib.advisor_model_set_zscore(self.handle, mu, sigma)
 
+    def calibrate_fp8(self, feat):
+        _lib.advisor_model_calibrate_fp8(self.handle, feat)
+
+    def fp8_scales(self):
+        return _lib.advisor_model_get_fp8_scales(self.handle, len(self.widths) - 2)
+
     def predict(self, feat, pred_out=None):
         return _lib.advisor_predict(self.handle, feat, pred_out)
 
