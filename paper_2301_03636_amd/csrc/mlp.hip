@@ -27,13 +27,18 @@ static void prof_clear_locked()
 template <int P, int W> struct TileRows {
     static constexpr int value =
         P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
-                       : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : (W <= 512 ? 128 : 64));
+                       : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
 };
 // Waves per workgroup: 8 (two per SIMD, 256 registers each) except for the
 // 1024-wide bf16/fp8 tiles, whose accumulators need one wave per SIMD and
 // its 512 registers.
 template <int P, int W> struct TileWaves {
-    static constexpr int value = (W == 1024 && P != PREC_FP32) ? 4 : 8;
+    static constexpr int value = (W == 1024 && P == PREC_FP8) ? 4 : 8;
+};
+// Passes over each wave's output neurons (accumulator size vs re-reading
+// the activations from LDS); outputs are bitwise the same for any split.
+template <int P, int W> struct TileSplit {
+    static constexpr int value = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1)) : 1;
 };
 
 __global__ void keys_init_kernel(uint64_t *keys, int64_t n)
@@ -57,8 +62,9 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
 {
     constexpr int M = TileRows<P, W>::value;
     constexpr int NW = TileWaves<P, W>::value;
-    using C = TileCfg<P, W, M, NW>;
-    auto kern = mlp_tiles_kernel<P, W, M, NW, SRC, SINK>;
+    constexpr int NS = TileSplit<P, W>::value;
+    using C = TileCfg<P, W, M, NW, NS>;
+    auto kern = mlp_tiles_kernel<P, W, M, NW, NS, SRC, SINK>;
     static std::once_flag once;
     static int blocks_per_cu = 1;
     static hipError_t setup_err = hipSuccess;

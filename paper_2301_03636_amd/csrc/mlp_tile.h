@@ -18,6 +18,8 @@
 // the 32 rows of a B operand fall in distinct banks.
 #pragma once
 
+#include <type_traits>
+
 #include "features.h"
 
 namespace adv {
@@ -137,8 +139,9 @@ __device__ __forceinline__ void save_elem(void *base, int64_t idx, float v)
         reinterpret_cast<__bf16 *>(base)[idx] = (__bf16)v;
 }
 
-template <int P, int W, int M, int NWAVES>
+template <int P, int W, int M, int NWAVES, int NSPLIT_ = 1>
 struct TileCfg {
+    static constexpr int NSPLIT = NSPLIT_;                 // passes over a wave's neurons
     using G = Geo<P>;
     using G0 = Geo<FirstP<P>::value>;
     static constexpr int NB = W / 32;                      // n-blocks of a layer
@@ -148,6 +151,8 @@ struct TileCfg {
     static constexpr int NBW = NB / WN;                    // n-blocks per wave
     static constexpr int MBW = MB / WM;                    // m-blocks per wave
     static_assert(NB % WN == 0 && MB % WM == 0 && NWAVES % WN == 0, "tile split");
+    static constexpr int NBP = NBW / NSPLIT;               // n-blocks per pass
+    static_assert(NBW % NSPLIT == 0, "passes split the wave's n-blocks evenly");
     static constexpr int XS = 32 * G0::EB + G0::PAD;       // input row stride (bytes)
     static constexpr int AS = W * G::EB + G::PAD;          // activation row stride (bytes)
     static constexpr int THREADS = NWAVES * 64;
@@ -254,33 +259,73 @@ __device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restric
     }
 }
 
-// Bias + ReLU, then store four consecutive neurons of one variant into the
-// next layer's activation rows (optionally scaled for fp8).
+// Four consecutive neurons of one variant in a layer's activation precision
+// (fp8: scaled by 1/s first), as held in registers until they are stored.
+template <int P> struct Held;
+template <> struct Held<PREC_FP32> { using T = v4f; };
+template <> struct Held<PREC_BF16> { using T = v4bf; };
+template <> struct Held<PREC_FP8> { using T = uint32_t; };
+
 template <int P>
-__device__ __forceinline__ void store4(unsigned char *row, int n, v4f v, float qinv)
+__device__ __forceinline__ typename Held<P>::T pack4(v4f v, float qinv)
 {
-    using G = Geo<P>;
     if constexpr (P == PREC_FP32) {
-        *reinterpret_cast<v4f *>(row + n * 4) = v;
+        return v;
     } else if constexpr (P == PREC_BF16) {
         v4bf o;
         o[0] = (__bf16)v[0];
         o[1] = (__bf16)v[1];
         o[2] = (__bf16)v[2];
         o[3] = (__bf16)v[3];
-        *reinterpret_cast<v4bf *>(row + n * 2) = o;
+        return o;
     } else {
-        const uint32_t q = f32_to_e4m3(v[0] * qinv) | (f32_to_e4m3(v[1] * qinv) << 8) |
-                           (f32_to_e4m3(v[2] * qinv) << 16) | (f32_to_e4m3(v[3] * qinv) << 24);
-        *reinterpret_cast<uint32_t *>(row + n) = q;
+        return f32_to_e4m3(v[0] * qinv) | (f32_to_e4m3(v[1] * qinv) << 8) |
+               (f32_to_e4m3(v[2] * qinv) << 16) | (f32_to_e4m3(v[3] * qinv) << 24);
     }
-    (void)sizeof(G);
 }
 
-template <int P, int W, int M, int NWAVES, int SRC, int SINK>
+template <int P>
+__device__ __forceinline__ void store_held(unsigned char *row, int n, typename Held<P>::T h)
+{
+    *reinterpret_cast<typename Held<P>::T *>(row + n * Geo<P>::EB) = h;
+}
+
+// Bias + ReLU have been applied; store four consecutive neurons of one
+// variant into a next-layer activation row.
+template <int P>
+__device__ __forceinline__ void store4(unsigned char *row, int n, v4f v, float qinv)
+{
+    store_held<P>(row, n, pack4<P>(v, qinv));
+}
+
+// Copy a tile's activations [M][W] (LDS rows of stride AS) to the transposed
+// global layout dst[n * ld + row0 + m] (rows >= n_rows as zero). A thread
+// moves one 16-byte run of neurons of one row; lanes of a wave take
+// consecutive rows, so each global store is a contiguous run of the batch.
+template <int P, int W, int M, int THREADS, int AS>
+__device__ __forceinline__ void copy_act_transposed(const unsigned char *act, void *dst,
+                                                    int64_t ld, int64_t row0, int64_t n_rows,
+                                                    int tid)
+{
+    using T = typename std::conditional<P == PREC_FP32, float, __bf16>::type;
+    constexpr int CE = 16 / (int)sizeof(T);
+    T *d = reinterpret_cast<T *>(dst);
+    for (int c = tid; c < M * (W / CE); c += THREADS) {
+        const int m = c % M, nc = c / M;
+        const int64_t row = row0 + m;
+        typedef int v4i_ __attribute__((ext_vector_type(4)));
+        const v4i_ raw = *reinterpret_cast<const v4i_ *>(act + (size_t)m * AS + nc * 16);
+        const T *vals = reinterpret_cast<const T *>(&raw);
+#pragma unroll
+        for (int e = 0; e < CE; ++e)
+            d[(int64_t)(nc * CE + e) * ld + row] = row < n_rows ? vals[e] : (T)0.0f;
+    }
+}
+
+template <int P, int W, int M, int NWAVES, int NSPLIT, int SRC, int SINK>
 __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
 {
-    using C = TileCfg<P, W, M, NWAVES>;
+    using C = TileCfg<P, W, M, NWAVES, NSPLIT>;
     using G = typename C::G;
     constexpr int P0 = FirstP<P>::value;
     using G0 = Geo<P0>;
@@ -369,98 +414,101 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
         }
         __syncthreads();
 
-        v16f acc[C::NBW][C::MBW];
-        // ---- layer 0 (32 inputs), then hidden layers 1..n_hidden-1
+        // ---- layer 0 (32 inputs), then hidden layers 1..n_hidden-1. Each wave
+        // covers its n-blocks in NSPLIT passes (smaller accumulators): the
+        // outputs of all passes but the last wait packed in registers; the
+        // last pass's accumulators cross the barrier after which every wave
+        // has read the layer's input, and all outputs then go to LDS in its
+        // place.
         for (int l = 0; l < net.n_hidden; ++l) {
-            if (l == 0) {
-                layer_mma<P0, 32, C::NBW, C::MBW>(
-                    reinterpret_cast<const typename G0::Vec *>(net.w[0]), xin, C::XS, nb0, mb0,
-                    lane, acc);
-            } else {
-                layer_mma<P, W, C::NBW, C::MBW>(
-                    reinterpret_cast<const typename G::Vec *>(net.w[l]), act, C::AS, nb0, mb0,
-                    lane, acc);
-                __syncthreads();  // every wave finished reading act before it is overwritten
-            }
+            const bool last = l + 1 == net.n_hidden;
             const float *bias = net.b[l];
             const float qs = (P == PREC_FP8 && l > 0) ? net.qscale[l] : 1.0f;
-            if (l + 1 < net.n_hidden) {
-                const float qinv = net.qinv[l];
-                // one 32-neuron block at a time: its 4 bias vectors are loaded
-                // together, and the fence keeps the next block's loads from
-                // being hoisted (which would raise register pressure)
+            const float qinv = net.qinv[l];
+            typename Held<P>::T held[C::NSPLIT > 1 ? C::NSPLIT - 1 : 1][C::NBP][4][C::MBW];
+            float srow[C::MBW];
 #pragma unroll
-                for (int i = 0; i < C::NBW; ++i) {
-                    v4f bias_r[4];
+            for (int j = 0; j < C::MBW; ++j) srow[j] = 0.0f;
 #pragma unroll
-                    for (int g = 0; g < 4; ++g)
-                        bias_r[g] = *reinterpret_cast<const v4f *>(
-                            bias + (nb0 + i) * 32 + 8 * g + 4 * half);
+            for (int ps = 0; ps < C::NSPLIT; ++ps) {
+                const int nbp0 = nb0 + ps * C::NBP;
+                const bool final_pass = ps + 1 == C::NSPLIT;
+                v16f acc[C::NBP][C::MBW];
+                if (l == 0)
+                    layer_mma<P0, 32, C::NBP, C::MBW>(
+                        reinterpret_cast<const typename G0::Vec *>(net.w[0]), xin, C::XS, nbp0,
+                        mb0, lane, acc);
+                else
+                    layer_mma<P, W, C::NBP, C::MBW>(
+                        reinterpret_cast<const typename G::Vec *>(net.w[l]), act, C::AS, nbp0,
+                        mb0, lane, acc);
+                // training keeps the last hidden layer's outputs too (copied out below)
+                constexpr bool keep_last = SINK == SINK_TRAIN;
+                if (final_pass && (!last || keep_last)) {
+                    if (l > 0) __syncthreads();  // every wave finished reading this layer's input
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
-                        const v4f bb = bias_r[g];
+                    for (int hp = 0; hp + 1 < C::NSPLIT; ++hp)
 #pragma unroll
-                        for (int j = 0; j < C::MBW; ++j) {
-                            v4f v;
+                        for (int i = 0; i < C::NBP; ++i)
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const float z = acc[i][j][4 * g + e] * qs + bb[e];
-                                v[e] = z > 0.0f ? z : 0.0f;
-                            }
-                            const int m = (mb0 + j) * 32 + col;
-                            store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
-                            if constexpr (SINK == SINK_TRAIN) {
-                                const int64_t rr = row0 + m;
-                                const int64_t base = ((int64_t)l * W + nn) * args.save_ld + rr;
+                            for (int j = 0; j < C::MBW; ++j)
 #pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    save_elem<P>(args.save_h, base + e * args.save_ld,
-                                                 rr < n ? v[e] : 0.0f);
-                            }
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
+                                for (int g = 0; g < 4; ++g) {
+                                    const int nn = (nb0 + hp * C::NBP + i) * 32 + 8 * g + 4 * half;
+                                    const int m = (mb0 + j) * 32 + col;
+                                    store_held<P>(act + (size_t)m * C::AS, nn, held[hp][i][g][j]);
+                                }
                 }
-                __syncthreads();  // next layer reads the complete activations
-            } else {
-                // output layer: per-lane partial dot products of the ReLU'd
-                // last hidden layer with the head weights (fp32), summed per
-                // row over blocks, groups and elements in a fixed order
-                const float *hw = net.head_w;
-                float srow[C::MBW];
+                // one 32-neuron block at a time: its bias (and output-layer
+                // weight) vectors are loaded together, and the fence keeps the
+                // next block's loads from being hoisted
 #pragma unroll
-                for (int j = 0; j < C::MBW; ++j) srow[j] = 0.0f;
-#pragma unroll
-                for (int i = 0; i < C::NBW; ++i) {
+                for (int i = 0; i < C::NBP; ++i) {
                     v4f bias_r[4], hw_r[4];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                        const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
                         bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
-                        hw_r[g] = *reinterpret_cast<const v4f *>(hw + nn);
+                        if (last) hw_r[g] = *reinterpret_cast<const v4f *>(net.head_w + nn);
                     }
 #pragma unroll
                     for (int j = 0; j < C::MBW; ++j) {
+                        const int m = (mb0 + j) * 32 + col;
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
-                            const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                            const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
+                            v4f v;
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const float z = acc[i][j][4 * g + e] * qs + bias_r[g][e];
-                                const float h = z > 0.0f ? z : 0.0f;
-                                srow[j] += h * hw_r[g][e];
-                                if constexpr (SINK == SINK_TRAIN) {
-                                    const int64_t rr = row0 + (mb0 + j) * 32 + col;
-                                    save_elem<P>(args.save_h,
-                                                 ((int64_t)l * W + nn + e) * args.save_ld + rr,
-                                                 rr < n ? h : 0.0f);
-                                }
+                                v[e] = z > 0.0f ? z : 0.0f;
+                            }
+                            if (last) {
+                                // output layer: fixed order over blocks, groups, elements
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) srow[j] += v[e] * hw_r[g][e];
+                            }
+                            if (!last || keep_last) {
+                                if (final_pass)
+                                    store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
+                                else
+                                    held[final_pass ? 0 : ps][i][g][j] = pack4<P>(v, qinv);
                             }
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
+            }
+            if (!last || SINK == SINK_TRAIN) {
+                __syncthreads();  // next layer (or the copy below) reads the complete activations
+                if constexpr (SINK == SINK_TRAIN)
+                    copy_act_transposed<P, W, M, C::THREADS, C::AS>(
+                        act,
+                        reinterpret_cast<unsigned char *>(args.save_h) +
+                            (size_t)l * W * args.save_ld * Geo<P>::EB,
+                        args.save_ld, row0, n, tid);
+            }
+            if (last) {
 #pragma unroll
                 for (int j = 0; j < C::MBW; ++j) {
                     float sj = srow[j];

@@ -60,6 +60,8 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     using C = TileCfg<P, W, M, NWAVES>;
     using G = typename C::G;
     using T = typename CT<P>::T;
+    constexpr int CE = 16 / (int)sizeof(T);  // elements per 16-byte run
+    typedef int v4i_ __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *act = lds;  // [M][AS]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -75,19 +77,26 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
         __syncthreads();
-        // seed: gradient at the last hidden layer's pre-activation
+        // seed: gradient at the last hidden layer's pre-activation; one thread
+        // per 16-byte run of neurons of one row (lanes take consecutive rows)
         {
             const T *Hl = H + (int64_t)(L - 1) * W * ld;
             T *Gl = GT + (int64_t)(L - 1) * W * ld;
-            for (int idx = tid; idx < M * W; idx += C::THREADS) {
-                const int m = idx % M, j = idx / M;
+            for (int c = tid; c < M * (W / CE); c += C::THREADS) {
+                const int m = c % M, nc = c / M;
                 const int64_t row = row0 + m;
                 const float d = row < n ? a.dy[row] : 0.0f;
-                const float h = (float)Hl[(int64_t)j * ld + row];
-                const float g = h > 0.0f ? d * a.head_w[j] : 0.0f;
-                const T gq = (T)g;
-                Gl[(int64_t)j * ld + row] = gq;
-                reinterpret_cast<T *>(act + (size_t)m * C::AS)[j] = gq;
+                v4i_ raw;
+                T *vals = reinterpret_cast<T *>(&raw);
+#pragma unroll
+                for (int e = 0; e < CE; ++e) {
+                    const int j = nc * CE + e;
+                    const float h = (float)Hl[(int64_t)j * ld + row];
+                    const T g = (T)(h > 0.0f ? d * a.head_w[j] : 0.0f);
+                    vals[e] = g;
+                    Gl[(int64_t)j * ld + row] = g;
+                }
+                *reinterpret_cast<v4i_ *>(act + (size_t)m * C::AS + nc * 16) = raw;
             }
         }
         __syncthreads();
@@ -96,29 +105,40 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
             layer_mma<P, W, C::NBW, C::MBW>(reinterpret_cast<const typename G::Vec *>(a.wt[l]),
                                             act, C::AS, nb0, mb0, lane, acc);
             __syncthreads();  // every wave has read g_l
-            const T *Hp = H + (int64_t)(l - 1) * W * ld;
-            T *Gp = GT + (int64_t)(l - 1) * W * ld;
+            // raw input gradients (sum_n g_l W_l) to LDS ...
 #pragma unroll
-            for (int i = 0; i < C::NBW; ++i) {
+            for (int i = 0; i < C::NBW; ++i)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int kk = (nb0 + i) * 32 + 8 * g + 4 * half;
 #pragma unroll
                     for (int j = 0; j < C::MBW; ++j) {
                         const int m = (mb0 + j) * 32 + col;
-                        const int64_t row = row0 + m;
                         v4f v;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const float h = (float)Hp[(int64_t)(kk + e) * ld + row];
-                            const float gv = h > 0.0f ? acc[i][j][4 * g + e] : 0.0f;
-                            const T gq = (T)gv;
-                            Gp[(int64_t)(kk + e) * ld + row] = gq;
-                            v[e] = (float)gq;
-                        }
-                        if (l > 1) store4<P>(act + (size_t)m * C::AS, kk, v, 1.0f);
+                        for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * g + e];
+                        store4<P>(act + (size_t)m * C::AS, kk, v, 1.0f);
                     }
                 }
+            __syncthreads();
+            // ... then the ReLU mask of h_{l-1}, written back for the next
+            // layer and out, transposed, for the weight gradients
+            const T *Hp = H + (int64_t)(l - 1) * W * ld;
+            T *Gp = GT + (int64_t)(l - 1) * W * ld;
+            for (int c = tid; c < M * (W / CE); c += C::THREADS) {
+                const int m = c % M, nc = c / M;
+                const int64_t row = row0 + m;
+                v4i_ raw = *reinterpret_cast<const v4i_ *>(act + (size_t)m * C::AS + nc * 16);
+                T *vals = reinterpret_cast<T *>(&raw);
+#pragma unroll
+                for (int e = 0; e < CE; ++e) {
+                    const int k = nc * CE + e;
+                    const float h = (float)Hp[(int64_t)k * ld + row];
+                    const T g = h > 0.0f ? vals[e] : (T)0.0f;
+                    vals[e] = g;
+                    Gp[(int64_t)k * ld + row] = g;
+                }
+                if (l > 1) *reinterpret_cast<v4i_ *>(act + (size_t)m * C::AS + nc * 16) = raw;
             }
             __syncthreads();
         }
@@ -208,34 +228,40 @@ __global__ void wgrad_reduce_kernel(const float *__restrict__ partial, int split
     grads[idx] = s;
 }
 
-// One wave per output row: sum_b v[row][b] (times w[b] if given), b < n, in a
-// fixed order (lane-strided partial sums, then a butterfly).
+// One workgroup per output row r: out[r] = sum_{b < n} v[r][b] * w[b] (w may
+// be null: plain row sums). Threads stride over 16-byte runs of the row,
+// then a fixed tree in LDS combines them, so the result is deterministic.
+constexpr int RS_THREADS = 256;
+
 template <typename T>
-__global__ __launch_bounds__(256) void rowdot_kernel(const T *__restrict__ v, int64_t ld, int rows,
-                                                     int64_t n, const float *__restrict__ w,
-                                                     float *__restrict__ out)
+__global__ __launch_bounds__(RS_THREADS) void rowdot_kernel(const T *__restrict__ v, int64_t ld,
+                                                            int rows, int64_t n,
+                                                            const float *__restrict__ w,
+                                                            float *__restrict__ out)
 {
-    const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ float sh[RS_THREADS];
+    constexpr int CE = 16 / (int)sizeof(T);
+    typedef int v4i_ __attribute__((ext_vector_type(4)));
+    const int r = blockIdx.x;
     if (r >= rows) return;
     const T *p = v + (int64_t)r * ld;
     float s = 0.0f;
-    for (int64_t b = lane; b < n; b += 64) s += (float)p[b] * (w ? w[b] : 1.0f);
+    const int64_t nfull = (n / CE) * CE;
+    for (int64_t b = (int64_t)threadIdx.x * CE; b < nfull; b += (int64_t)RS_THREADS * CE) {
+        const v4i_ raw = *reinterpret_cast<const v4i_ *>(p + b);
+        const T *x = reinterpret_cast<const T *>(&raw);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) out[r] = s;
-}
-
-// sum_b dy[b] (output-layer bias gradient), fixed order
-__global__ __launch_bounds__(64) void sum_kernel(const float *__restrict__ v, int64_t n,
-                                                 float *__restrict__ out)
-{
-    const int lane = threadIdx.x;
-    float s = 0.0f;
-    for (int64_t b = lane; b < n; b += 64) s += v[b];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) *out = s;
+        for (int e = 0; e < CE; ++e) s += (float)x[e] * (w ? w[b + e] : 1.0f);
+    }
+    if (threadIdx.x == 0)
+        for (int64_t b = nfull; b < n; ++b) s += (float)p[b] * (w ? w[b] : 1.0f);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = RS_THREADS / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r] = sh[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -475,14 +501,15 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
     float *g_head = grads + m->layer_off[L];
     const int in_last = m->widths[L];
     if (m->precision == PREC_FP32)
-        hipLaunchKernelGGL(rowdot_kernel<float>, dim3((in_last + 3) / 4), dim3(256), 0, s,
+        hipLaunchKernelGGL(rowdot_kernel<float>, dim3(in_last), dim3(RS_THREADS), 0, s,
                            reinterpret_cast<const float *>(hs + (size_t)(L - 1) * tw * ld * eb), ld,
                            in_last, n, dy, g_head);
     else
-        hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3((in_last + 3) / 4), dim3(256), 0, s,
+        hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3(in_last), dim3(RS_THREADS), 0, s,
                            reinterpret_cast<const __bf16 *>(hs + (size_t)(L - 1) * tw * ld * eb), ld,
                            in_last, n, dy, g_head);
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, s, dy, n, g_head + in_last);
+    hipLaunchKernelGGL(rowdot_kernel<float>, dim3(1), dim3(RS_THREADS), 0, s, dy, n, 1, n,
+                       (const float *)nullptr, g_head + in_last);
     ADV_LAUNCHED("output-layer gradient");
     // chain of input gradients through the hidden layers
     BwdArgs a{};
@@ -520,11 +547,11 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
                            w->partial, splits, na, nb, out, in, gw);
         float *gb = gw + ne;
         if (m->precision == PREC_FP32)
-            hipLaunchKernelGGL(rowdot_kernel<float>, dim3((out + 3) / 4), dim3(256), 0, s,
+            hipLaunchKernelGGL(rowdot_kernel<float>, dim3(out), dim3(RS_THREADS), 0, s,
                                reinterpret_cast<const float *>(Ab), ld, out, n,
                                (const float *)nullptr, gb);
         else
-            hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3((out + 3) / 4), dim3(256), 0, s,
+            hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3(out), dim3(RS_THREADS), 0, s,
                                reinterpret_cast<const __bf16 *>(Ab), ld, out, n,
                                (const float *)nullptr, gb);
         ADV_LAUNCHED("wgrad reduce / bias gradient");
