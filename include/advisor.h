@@ -253,6 +253,28 @@ int advisor_model_load_params(advisor_model *model, const float *w_master, void 
 int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
 
 /*
+ * Captured plans: one advisor_rank or advisor_train_step call with fixed
+ * arguments recorded into a HIP graph, replayed by advisor_plan_launch on
+ * any stream with the same effect as repeating the call (the same kernels,
+ * bit-identical results). The buffers named at creation must stay allocated
+ * and their contents are read at replay time. advisor_train_plan_create
+ * reserves the training workspace for n rows and rebuilds the transposed
+ * weights before capturing; it does not run a step. A plan belongs to the
+ * device current at creation. Replays of one plan must not overlap, and the
+ * model must not be destroyed while a plan of it exists.
+ */
+typedef struct advisor_plan advisor_plan;
+int advisor_rank_plan_create(const advisor_model *model, const int64_t *kdesc,
+                             const int64_t *vdesc, const int64_t *offsets, int64_t n_kernels,
+                             int64_t n_variants, int64_t *best_out, float *pred_out,
+                             advisor_plan **out);
+int advisor_train_plan_create(advisor_model *model, const int64_t *feat, const double *y,
+                              int64_t n, float lr, float beta1, float beta2, float eps,
+                              double *loss_out, double *gnorm_out, advisor_plan **out);
+int advisor_plan_launch(advisor_plan *plan, void *stream);
+void advisor_plan_destroy(advisor_plan *plan);
+
+/*
  * Measurement aid (not part of the method): while enabled, every launch of
  * the fused tile kernel (advisor_rank, advisor_predict) is bracketed by a
  * pair of HIP events recorded on the caller's stream. advisor_profile_read

@@ -9,6 +9,8 @@ from ._lib import (AdvisorError, PRECISIONS, advisor_featurize, advisor_model_cr
                    advisor_profile_read, advisor_rank, advisor_rank_preds,
                    advisor_zscore_fit, last_error, advisor_mlp_saved_bytes, advisor_mlp_forward,
                    advisor_mlp_backward, advisor_train_step, advisor_model_load_params,
-                   advisor_model_grads, advisor_model_calibrate_fp8, advisor_model_get_fp8_scales)
-from .model import Model  # noqa: F401
+                   advisor_model_grads, advisor_model_calibrate_fp8, advisor_model_get_fp8_scales,
+                   advisor_rank_plan_create, advisor_train_plan_create, advisor_plan_launch,
+                   advisor_plan_destroy)
+from .model import Model, Plan  # noqa: F401
 from .train import MLPFunction, Trainer, mlp  # noqa: F401

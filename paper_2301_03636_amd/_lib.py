@@ -64,6 +64,11 @@ def lib():
             "advisor_model_grads": ([P, P, P], i32),
             "advisor_model_calibrate_fp8": ([P, P, i64, P], i32),
             "advisor_model_get_fp8_scales": ([P, P, P], i32),
+            "advisor_rank_plan_create": ([P, P, P, P, i64, i64, P, P, C.POINTER(C.c_void_p)], i32),
+            "advisor_train_plan_create": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
+                                           C.c_float, P, P, C.POINTER(C.c_void_p)], i32),
+            "advisor_plan_launch": ([P, P], i32),
+            "advisor_plan_destroy": ([P], None),
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
         }
@@ -327,3 +332,37 @@ def advisor_model_grads(h, grads_out):
     _dev(grads_out, torch.float32, "grads_out")
     _check(lib().advisor_model_grads(h, _ptr(grads_out), _stream()), "advisor_model_grads")
     return grads_out
+
+
+# --------------------------------------------------------------------------- captured plans
+
+
+def advisor_rank_plan_create(h, kdesc, vdesc, offsets, best_out, pred_out=None):
+    for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets"), (best_out, "best_out")):
+        _dev(t, torch.int64, nm)
+    _dev(pred_out, torch.float32, "pred_out")
+    p = C.c_void_p()
+    _check(lib().advisor_rank_plan_create(h, _ptr(kdesc), _ptr(vdesc), _ptr(offsets),
+                                          offsets.shape[0] - 1, vdesc.shape[0], _ptr(best_out),
+                                          _ptr(pred_out), C.byref(p)), "advisor_rank_plan_create")
+    return p
+
+
+def advisor_train_plan_create(h, feat, y, loss_out, gnorm_out, lr=1e-3, beta1=0.9, beta2=0.999,
+                              eps=1e-8):
+    _dev(feat, torch.int64, "feat")
+    for t, nm in ((y, "y"), (loss_out, "loss_out"), (gnorm_out, "gnorm_out")):
+        _dev(t, torch.float64, nm)
+    p = C.c_void_p()
+    _check(lib().advisor_train_plan_create(h, _ptr(feat), _ptr(y), feat.shape[0], lr, beta1, beta2,
+                                           eps, _ptr(loss_out), _ptr(gnorm_out), C.byref(p)),
+           "advisor_train_plan_create")
+    return p
+
+
+def advisor_plan_launch(p):
+    _check(lib().advisor_plan_launch(p, _stream()), "advisor_plan_launch")
+
+
+def advisor_plan_destroy(p):
+    lib().advisor_plan_destroy(p)

@@ -42,6 +42,15 @@ int device_cus();
 // Training workspace release (train.hip).
 void free_train_ws(advisor_model *m);
 
+// One-time launch set-up (dynamic LDS limits, occupancy) of every kernel a
+// model of this precision and tile width uses, so that later calls can be
+// captured into a graph (mlp.hip, train.hip).
+int prepare_model_kernels(int precision, int tile_w);
+int prepare_train_kernels(int precision, int tile_w);
+
+// True while `s` is being captured into a graph.
+bool stream_capturing(hipStream_t s);
+
 // Kernel-side view of a model's packed parameters.
 struct NetView {
     const void *w[MAX_LAYERS];      // packed hidden-layer weights (fragment-major)
@@ -69,7 +78,7 @@ struct advisor_model {
     float *master = nullptr;  // fp32 master parameters [n_params]
     float *adam_m = nullptr;
     float *adam_v = nullptr;
-    int64_t step = 0;
+    int64_t *d_step = nullptr;  // Adam step counter, on the device so a captured step replays
     double *mu = nullptr;     // [32]
     double *sigma = nullptr;  // [32]
     void *wpack[ADVISOR_MAX_LAYERS] = {nullptr};

@@ -58,40 +58,54 @@ __global__ void keys_final_kernel(int64_t *best, int64_t n)
 }
 
 template <int P, int W, int SRC, int SINK>
+struct TileLaunch {
+    static constexpr int M = TileRows<P, W>::value;
+    static constexpr int NW = TileWaves<P, W>::value;
+    static constexpr int NS = TileSplit<P, W>::value;
+    using C = TileCfg<P, W, M, NW, NS>;
+    static constexpr auto kern = mlp_tiles_kernel<P, W, M, NW, NS, SRC, SINK>;
+    static inline std::once_flag once;
+    static inline int blocks_per_cu = 1;
+    static inline hipError_t setup_err = hipSuccess;
+    // dynamic-LDS limit and occupancy, once per process
+    static int setup()
+    {
+        std::call_once(once, [] {
+            setup_err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)C::LDS);
+            if (setup_err == hipSuccess) {
+                int nb = 0;
+                setup_err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &nb, reinterpret_cast<const void *>(kern), C::THREADS, C::LDS);
+                blocks_per_cu = nb > 0 ? nb : 1;
+            }
+        });
+        return setup_err == hipSuccess ? ADVISOR_OK : hip_fail(setup_err, "tile kernel set-up");
+    }
+};
+
+template <int P, int W, int SRC, int SINK>
 int launch_tiles(const TileArgs &args, hipStream_t s)
 {
-    constexpr int M = TileRows<P, W>::value;
-    constexpr int NW = TileWaves<P, W>::value;
-    constexpr int NS = TileSplit<P, W>::value;
-    using C = TileCfg<P, W, M, NW, NS>;
-    auto kern = mlp_tiles_kernel<P, W, M, NW, NS, SRC, SINK>;
-    static std::once_flag once;
-    static int blocks_per_cu = 1;
-    static hipError_t setup_err = hipSuccess;
-    std::call_once(once, [&] {
-        setup_err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-        if (setup_err == hipSuccess) {
-            int nb = 0;
-            setup_err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &nb, reinterpret_cast<const void *>(kern), C::THREADS, C::LDS);
-            blocks_per_cu = nb > 0 ? nb : 1;
-        }
-    });
-    if (setup_err != hipSuccess) return hip_fail(setup_err, "tile kernel set-up");
-    const int64_t ntiles = (args.n_rows + M - 1) / M;
-    const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus() * blocks_per_cu);
+    using TL = TileLaunch<P, W, SRC, SINK>;
+    using C = typename TL::C;
+    int rc = TL::setup();
+    if (rc) return rc;
+    const int64_t ntiles = SINK == SINK_TRAIN ? args.save_ld / TL::M
+                                              : (args.n_rows + TL::M - 1) / TL::M;
+    const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus() * TL::blocks_per_cu);
     if (grid <= 0) return ADVISOR_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_prof_mu);
-        if (g_prof_on) {
+        if (g_prof_on && !stream_capturing(s)) {
             ADV_HIP(hipEventCreate(&e0));
             ADV_HIP(hipEventCreate(&e1));
             ADV_HIP(hipEventRecord(e0, s));
         }
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), C::LDS, s, args);
+    hipLaunchKernelGGL(TL::kern, dim3((unsigned)grid), dim3(C::THREADS), C::LDS, s, args);
     ADV_LAUNCHED("mlp_tiles_kernel");
     if (e0) {
         std::lock_guard<std::mutex> lock(g_prof_mu);
@@ -99,6 +113,25 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
         g_prof_events.emplace_back(e0, e1);
     }
     return ADVISOR_OK;
+}
+
+int prepare_model_kernels(int precision, int tile_w)
+{
+#define ADV_P(P, WW)                                                              \
+    if (precision == P && tile_w == WW) {                                         \
+        int rc = TileLaunch<P, WW, SRC_DESC, SINK_RANK>::setup();                 \
+        if (!rc) rc = TileLaunch<P, WW, SRC_FEAT, SINK_PRED>::setup();            \
+        if constexpr (P != PREC_FP8)                                              \
+            if (!rc) rc = TileLaunch<P, WW, SRC_FEAT, SINK_TRAIN>::setup();       \
+        return rc;                                                                \
+    }
+#define ADV_PW(P) ADV_P(P, 64) ADV_P(P, 128) ADV_P(P, 256) ADV_P(P, 512) ADV_P(P, 1024)
+    ADV_PW(PREC_FP32)
+    ADV_PW(PREC_BF16)
+    ADV_PW(PREC_FP8)
+#undef ADV_PW
+#undef ADV_P
+    return fail(ADVISOR_EUNSUPPORTED, "no tile kernel for this precision and width");
 }
 
 template <int SRC, int SINK>

@@ -26,6 +26,13 @@ int hip_fail(hipError_t e, const char *what)
 
 void clear_error() { g_last_error.clear(); }
 
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
+}
+
 int device_cus()
 {
     static std::mutex mu;
@@ -146,7 +153,7 @@ extern "C" void advisor_model_destroy(advisor_model *m)
     (void)hipDeviceSynchronize();
     free_train_ws(m);
     void *ptrs[] = {m->master, m->adam_m, m->adam_v, m->mu, m->sigma, m->bias, m->head,
-                    m->d_layer_off, m->d_widths};
+                    m->d_layer_off, m->d_widths, m->d_step};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int l = 0; l < ADVISOR_MAX_LAYERS; ++l)
@@ -204,6 +211,7 @@ extern "C" int advisor_model_create(const int32_t *widths, int n_widths, int pre
     alloc((void **)&m->master, sizeof(float) * off);
     alloc((void **)&m->adam_m, sizeof(float) * off);
     alloc((void **)&m->adam_v, sizeof(float) * off);
+    alloc((void **)&m->d_step, sizeof(int64_t));
     alloc((void **)&m->mu, sizeof(double) * NFEAT);
     alloc((void **)&m->sigma, sizeof(double) * NFEAT);
     alloc((void **)&m->bias, sizeof(float) * m->n_hidden * tw);
@@ -231,6 +239,8 @@ extern "C" int advisor_model_create(const int32_t *widths, int n_widths, int pre
         m->wscale[l] = 1.0f;
         m->ascale[l] = 1.0f;
     }
+    if (!rc) rc = prepare_model_kernels(precision, tw);
+    if (!rc && precision != PREC_FP8) rc = prepare_train_kernels(precision, tw);
     if (rc) {
         advisor_model_destroy(m);
         return rc;
@@ -263,11 +273,11 @@ extern "C" int advisor_model_set_params(advisor_model *m, const float *w_master,
     if (e == hipSuccess) e = hipMemcpy(m->sigma, sigma, sizeof(double) * NFEAT, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(m->adam_m, 0, sizeof(float) * m->n_params);
     if (e == hipSuccess) e = hipMemset(m->adam_v, 0, sizeof(float) * m->n_params);
+    if (e == hipSuccess) e = hipMemset(m->d_step, 0, sizeof(int64_t));
     if (e != hipSuccess) {
         (void)hipSetDevice(prev);
         return hip_fail(e, "set_params copy");
     }
-    m->step = 0;
     m->fp8_calibrated = false;
     m->wt_valid = false;
     int rc = repack(m, nullptr);
@@ -309,7 +319,7 @@ extern "C" int advisor_model_get_adam(const advisor_model *m, float *am, float *
     ADV_HIP(hipDeviceSynchronize());
     if (am) ADV_HIP(hipMemcpy(am, m->adam_m, sizeof(float) * m->n_params, hipMemcpyDeviceToHost));
     if (av) ADV_HIP(hipMemcpy(av, m->adam_v, sizeof(float) * m->n_params, hipMemcpyDeviceToHost));
-    if (step) *step = m->step;
+    if (step) ADV_HIP(hipMemcpy(step, m->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
     return ADVISOR_OK;
 }
 
@@ -322,6 +332,6 @@ extern "C" int advisor_model_set_adam(advisor_model *m, const float *am, const f
     ADV_HIP(hipDeviceSynchronize());
     if (am) ADV_HIP(hipMemcpy(m->adam_m, am, sizeof(float) * m->n_params, hipMemcpyHostToDevice));
     if (av) ADV_HIP(hipMemcpy(m->adam_v, av, sizeof(float) * m->n_params, hipMemcpyHostToDevice));
-    m->step = step;
+    ADV_HIP(hipMemcpy(m->d_step, &step, sizeof(int64_t), hipMemcpyHostToDevice));
     return ADVISOR_OK;
 }

@@ -1,0 +1,119 @@
+// Captured launch plans: one advisor_rank or advisor_train_step call with
+// fixed buffers recorded into a HIP graph and replayed with one launch. The
+// kernels are the same as the direct calls; replays give the same bits.
+#include "internal.h"
+
+struct advisor_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+namespace adv {
+
+int repack_transposed_now(advisor_model *m, hipStream_t s);  // train.hip
+int reserve_train_ws(advisor_model *m, int64_t n);           // train.hip
+
+// Record what `body` enqueues on a private capture stream into a new plan.
+template <class F>
+static int capture(F body, advisor_plan **out)
+{
+    *out = nullptr;
+    advisor_plan *p = new (std::nothrow) advisor_plan();
+    if (!p) return fail(ADVISOR_ENOMEM, "host allocation");
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(ADVISOR_EHIP, "hipGetDevice failed");
+    }
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    int rc = ADVISOR_OK;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "hipStreamBeginCapture");
+    } else {
+        rc = body(cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (!rc && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+        p->graph = g;
+        if (!rc) {
+            e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        advisor_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return ADVISOR_OK;
+}
+
+}  // namespace adv
+
+using namespace adv;
+
+extern "C" void advisor_plan_destroy(advisor_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+}
+
+extern "C" int advisor_rank_plan_create(const advisor_model *model, const int64_t *kdesc,
+                                        const int64_t *vdesc, const int64_t *offsets,
+                                        int64_t n_kernels, int64_t n_variants, int64_t *best_out,
+                                        float *pred_out, advisor_plan **out)
+{
+    clear_error();
+    if (!out) return fail(ADVISOR_EINVAL, "advisor_rank_plan_create: out is null");
+    *out = nullptr;
+    if (!model) return fail(ADVISOR_EINVAL, "null model");
+    return capture(
+        [&](hipStream_t cs) {
+            return advisor_rank(model, kdesc, vdesc, offsets, n_kernels, n_variants, best_out,
+                                pred_out, cs);
+        },
+        out);
+}
+
+extern "C" int advisor_train_plan_create(advisor_model *model, const int64_t *feat, const double *y,
+                                         int64_t n, float lr, float beta1, float beta2, float eps,
+                                         double *loss_out, double *gnorm_out, advisor_plan **out)
+{
+    clear_error();
+    if (!out) return fail(ADVISOR_EINVAL, "advisor_train_plan_create: out is null");
+    *out = nullptr;
+    if (!model) return fail(ADVISOR_EINVAL, "null model");
+    if (n < 1 || n >= ((int64_t)1 << 32)) return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+    // everything that allocates or must run once happens before the capture
+    int rc = reserve_train_ws(model, n);
+    if (rc) return rc;
+    rc = repack_transposed_now(model, nullptr);
+    if (rc) return rc;
+    ADV_HIP(hipDeviceSynchronize());
+    return capture(
+        [&](hipStream_t cs) {
+            return advisor_train_step(model, feat, y, n, lr, beta1, beta2, eps, loss_out,
+                                      gnorm_out, cs);
+        },
+        out);
+}
+
+extern "C" int advisor_plan_launch(advisor_plan *p, void *stream)
+{
+    clear_error();
+    if (!p || !p->exec) return fail(ADVISOR_EINVAL, "advisor_plan_launch: null plan");
+    int dev = -1;
+    ADV_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(ADVISOR_EINVAL, "plan was captured on another device");
+    ADV_HIP(hipGraphLaunch(p->exec, as_stream(stream)));
+    return ADVISOR_OK;
+}

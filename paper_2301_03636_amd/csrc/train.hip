@@ -325,13 +325,23 @@ __global__ void finish_kernel(const double *__restrict__ part, double scale, int
     *out = take_sqrt ? sqrt(s) : s;
 }
 
-// Adam (Kingma and Ba) on fp32 master weights; c1 = 1 - b1^t, c2 = 1 - b2^t.
+// Adam step counter lives on the device so a captured step replays correctly.
+__global__ void step_inc_kernel(int64_t *step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+// Adam (Kingma and Ba) on fp32 master weights, t = *step (already
+// incremented); the bias corrections 1 - b^t are formed in float64.
 __global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
                             const float *__restrict__ g, int64_t n, float lr, float b1, float b2,
-                            float eps, float c1, float c2)
+                            float eps, const int64_t *__restrict__ step)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double t = (double)*step;
+    const float c1 = (float)(1.0 - pow((double)b1, t));
+    const float c2 = (float)(1.0 - pow((double)b2, t));
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -452,24 +462,45 @@ static int repack_transposed(advisor_model *m, hipStream_t s)
 int launch_train_forward(const advisor_model *m, const TileArgs &a, hipStream_t s);  // mlp.hip
 
 template <int P, int W>
+struct BwdLaunch {
+    static constexpr int M = P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
+                                            : (W <= 512 ? 128 : 64);
+    using C = TileCfg<P, W, M, 8>;
+    static constexpr auto kern = bwd_tiles_kernel<P, W, M, 8>;
+    static constexpr size_t lds = (size_t)M * C::AS;
+    static inline std::once_flag once;
+    static inline hipError_t err = hipSuccess;
+    static int setup()
+    {
+        std::call_once(once, [] {
+            err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        });
+        return err == hipSuccess ? ADVISOR_OK : hip_fail(err, "bwd kernel set-up");
+    }
+};
+
+template <int P, int W>
 static int launch_bwd(const BwdArgs &a, hipStream_t s)
 {
-    constexpr int M = P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32)) : (W <= 512 ? 128 : 64);
-    using C = TileCfg<P, W, M, 8>;
-    auto kern = bwd_tiles_kernel<P, W, M, 8>;
-    constexpr size_t lds = (size_t)M * C::AS;
-    static std::once_flag once;
-    static hipError_t err = hipSuccess;
-    std::call_once(once, [&] {
-        err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    });
-    if (err != hipSuccess) return hip_fail(err, "bwd kernel set-up");
-    const int64_t ntiles = a.ld / M;
+    using BL = BwdLaunch<P, W>;
+    int rc = BL::setup();
+    if (rc) return rc;
+    const int64_t ntiles = a.ld / BL::M;
     const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus());
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), lds, s, a);
+    hipLaunchKernelGGL(BL::kern, dim3((unsigned)grid), dim3(BL::C::THREADS), BL::lds, s, a);
     ADV_LAUNCHED("bwd_tiles_kernel");
     return ADVISOR_OK;
+}
+
+int prepare_train_kernels(int precision, int tile_w)
+{
+#define ADV_B(P, WW) if (precision == P && tile_w == WW) return BwdLaunch<P, WW>::setup();
+    ADV_B(PREC_FP32, 64) ADV_B(PREC_FP32, 128) ADV_B(PREC_FP32, 256) ADV_B(PREC_FP32, 512)
+    ADV_B(PREC_FP32, 1024) ADV_B(PREC_BF16, 64) ADV_B(PREC_BF16, 128) ADV_B(PREC_BF16, 256)
+    ADV_B(PREC_BF16, 512) ADV_B(PREC_BF16, 1024)
+#undef ADV_B
+    return fail(ADVISOR_EUNSUPPORTED, "training needs an fp32 or bf16 model");
 }
 
 static int dispatch_bwd(const advisor_model *m, const BwdArgs &a, hipStream_t s)
@@ -570,6 +601,20 @@ static int check_trainable(const advisor_model *m)
     return ADVISOR_OK;
 }
 
+int reserve_train_ws(advisor_model *m, int64_t n)
+{
+    int rc = check_trainable(m);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    return ensure_ws(m, n, true);
+}
+
+int repack_transposed_now(advisor_model *m, hipStream_t s)
+{
+    if (!train_ws(m)) return fail(ADVISOR_EINVAL, "no training workspace");
+    return repack_transposed(m, s);
+}
+
 }  // namespace adv
 
 using namespace adv;
@@ -657,12 +702,10 @@ extern "C" int advisor_train_step(advisor_model *m, const int64_t *feat, const d
         ADV_LAUNCHED("gradient norm kernels");
     }
     // Adam on the fp32 master weights, then new compute copies
-    m->step += 1;
-    const double c1 = 1.0 - pow((double)beta1, (double)m->step);
-    const double c2 = 1.0 - pow((double)beta2, (double)m->step);
+    hipLaunchKernelGGL(step_inc_kernel, dim3(1), dim3(64), 0, s, m->d_step);
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((m->n_params + 255) / 256)), dim3(256), 0, s,
                        m->master, m->adam_m, m->adam_v, w->grads, m->n_params, lr, beta1, beta2, eps,
-                       (float)c1, (float)c2);
+                       (const int64_t *)m->d_step);
     ADV_LAUNCHED("adam_kernel");
     rc = repack(m, s);
     if (rc) return rc;

@@ -57,6 +57,41 @@ class Model:
         self.close()
 
 
+class Plan:
+    """A captured advisor_rank or advisor_train_step call (a HIP graph);
+    launch() replays it on torch's current stream. Keep the model and every
+    buffer named at creation alive while the plan exists."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    @classmethod
+    def rank(cls, model, kdesc, vdesc, offsets, best_out, pred_out=None):
+        h = _lib.advisor_rank_plan_create(model.handle, kdesc, vdesc, offsets, best_out, pred_out)
+        return cls(h, (model, kdesc, vdesc, offsets, best_out, pred_out))
+
+    @classmethod
+    def train(cls, model, feat, y, loss_out, gnorm_out, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        h = _lib.advisor_train_plan_create(model.handle, feat, y, loss_out, gnorm_out, lr, beta1,
+                                           beta2, eps)
+        return cls(h, (model, feat, y, loss_out, gnorm_out))
+
+    def launch(self):
+        _lib.advisor_plan_launch(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.advisor_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def flops_per_variant(widths) -> int:
     """Algorithmic multiply-add flops of one forward pass (2 per MAC)."""
     return int(sum(2 * widths[i] * widths[i + 1] for i in range(len(widths) - 1)))
