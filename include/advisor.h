@@ -253,6 +253,27 @@ int advisor_model_load_params(advisor_model *model, const float *w_master, void 
 int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
 
 /*
+ * Tile-shape autotuner. The fused kernel is built in one or two tile shapes
+ * per (precision, width) (rows per tile, waves, passes); advisor_autotune
+ * times each on the given ranking workload (2 warm-up calls, then `reps`
+ * timed advisor_rank calls on the stream, device buffers as for
+ * advisor_rank), keeps the fastest for this model's advisor_rank and
+ * advisor_predict, and records it in a JSON cache keyed by (GPU
+ * architecture, precision, widths): the file named by the environment
+ * variable ADVISOR_TUNE_CACHE (an empty value disables the cache), else
+ * $HOME/.cache/libadvisor/tune.json; advisor_model_create reads it.
+ * times_ms (host, double [max_variants]) receives each shape's mean
+ * milliseconds (-1 where a shape is not built); *chosen (may be NULL) the
+ * chosen shape. Synchronizes the stream and allocates a temporary buffer.
+ * Shapes with the same number of waves give bit-identical predictions.
+ */
+int advisor_autotune(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
+                     const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int reps,
+                     double *times_ms, int max_variants, int *chosen, void *stream);
+int advisor_model_set_tile_variant(advisor_model *model, int variant);
+int advisor_model_get_tile_variant(const advisor_model *model);
+
+/*
  * Captured plans: one advisor_rank or advisor_train_step call with fixed
  * arguments recorded into a HIP graph, replayed by advisor_plan_launch on
  * any stream with the same effect as repeating the call (the same kernels,

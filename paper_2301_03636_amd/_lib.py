@@ -69,6 +69,9 @@ def lib():
                                            C.c_float, P, P, C.POINTER(C.c_void_p)], i32),
             "advisor_plan_launch": ([P, P], i32),
             "advisor_plan_destroy": ([P], None),
+            "advisor_autotune": ([P, P, P, P, i64, i64, i32, P, i32, C.POINTER(C.c_int), P], i32),
+            "advisor_model_set_tile_variant": ([P, i32], i32),
+            "advisor_model_get_tile_variant": ([P], i32),
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
         }
@@ -366,3 +369,25 @@ def advisor_plan_launch(p):
 
 def advisor_plan_destroy(p):
     lib().advisor_plan_destroy(p)
+
+
+# --------------------------------------------------------------------------- autotuner
+
+
+def advisor_autotune(h, kdesc, vdesc, offsets, reps=5, max_variants=4):
+    for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
+        _dev(t, torch.int64, nm)
+    times = np.zeros(max_variants)
+    chosen = C.c_int(-1)
+    _check(lib().advisor_autotune(h, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), offsets.shape[0] - 1,
+                                  vdesc.shape[0], int(reps), times.ctypes.data_as(C.c_void_p),
+                                  max_variants, C.byref(chosen), _stream()), "advisor_autotune")
+    return chosen.value, times
+
+
+def advisor_model_set_tile_variant(h, v):
+    _check(lib().advisor_model_set_tile_variant(h, int(v)), "advisor_model_set_tile_variant")
+
+
+def advisor_model_get_tile_variant(h):
+    return int(lib().advisor_model_get_tile_variant(h))

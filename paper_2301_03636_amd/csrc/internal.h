@@ -51,6 +51,12 @@ int prepare_train_kernels(int precision, int tile_w);
 // True while `s` is being captured into a graph.
 bool stream_capturing(hipStream_t s);
 
+// Whether tile shape V is built for this precision and width (mlp.hip).
+bool tile_shape_exists(int precision, int W, int V);
+
+// Tile shape recorded by the autotuner for a model of this shape, else 0.
+int tuned_variant(const advisor_model *m);
+
 // Kernel-side view of a model's packed parameters.
 struct NetView {
     const void *w[MAX_LAYERS];      // packed hidden-layer weights (fragment-major)
@@ -93,5 +99,6 @@ struct advisor_model {
     float qinv[ADVISOR_MAX_LAYERS] = {0};    // fp8: 1 / ascale of the next layer
     bool fp8_calibrated = false;
     void *train_ws = nullptr;  // training workspace (train.hip), grown on demand
+    int tile_variant = 0;      // tile shape used by rank/predict (autotuned)
     bool wt_valid = false;     // transposed packs (backward) match the master weights
 };

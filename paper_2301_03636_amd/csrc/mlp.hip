@@ -23,23 +23,32 @@ static void prof_clear_locked()
     g_prof_events.clear();
 }
 
-// Rows per tile: as many as fit LDS (activations [M][W] plus the input tile).
-template <int P, int W> struct TileRows {
-    static constexpr int value =
-        P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
-                       : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
+// Tile shapes. Shape 0 is the default of each (precision, width): rows per
+// tile M as large as LDS allows (activations [M][W] plus the input tile),
+// 8 waves (two per SIMD, 256 registers each) except the 1024-wide fp8 tile
+// (one wave per SIMD and its 512 registers), and NS passes over each wave's
+// neurons for the 1024-wide tiles. Shape 1, where built, halves the rows so
+// two workgroups share a CU (one's barriers and epilogues overlap the other's
+// matrix work) at the price of twice the weight traffic from L2. Shapes with
+// the same wave count give bit-identical predictions; the autotuner picks
+// one per model.
+template <int P, int W, int V> struct TileShape;
+template <int P, int W> struct TileShape<P, W, 0> {
+    static constexpr bool exists = true;
+    static constexpr int M = P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
+                                            : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
+    static constexpr int NW = (W == 1024 && P == PREC_FP8) ? 4 : 8;
+    static constexpr int NS = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1)) : 1;
 };
-// Waves per workgroup: 8 (two per SIMD, 256 registers each) except for the
-// 1024-wide bf16/fp8 tiles, whose accumulators need one wave per SIMD and
-// its 512 registers.
-template <int P, int W> struct TileWaves {
-    static constexpr int value = (W == 1024 && P == PREC_FP8) ? 4 : 8;
+template <int P, int W> struct TileShape<P, W, 1> {
+    static constexpr bool exists = (P == PREC_FP32 && W == 256) ||
+                                   (P == PREC_BF16 && (W == 256 || W == 512 || W == 1024)) ||
+                                   (P == PREC_FP8 && (W == 512 || W == 1024));
+    static constexpr int M = (P == PREC_BF16 && W == 1024) ? 32 : 64;
+    static constexpr int NW = 8;
+    static constexpr int NS = (P == PREC_FP8 && W == 1024) ? 2 : 1;
 };
-// Passes over each wave's output neurons (accumulator size vs re-reading
-// the activations from LDS); outputs are bitwise the same for any split.
-template <int P, int W> struct TileSplit {
-    static constexpr int value = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1)) : 1;
-};
+constexpr int N_TILE_SHAPES = 2;
 
 __global__ void keys_init_kernel(uint64_t *keys, int64_t n)
 {
@@ -57,11 +66,12 @@ __global__ void keys_final_kernel(int64_t *best, int64_t n)
     }
 }
 
-template <int P, int W, int SRC, int SINK>
+template <int P, int W, int V, int SRC, int SINK>
 struct TileLaunch {
-    static constexpr int M = TileRows<P, W>::value;
-    static constexpr int NW = TileWaves<P, W>::value;
-    static constexpr int NS = TileSplit<P, W>::value;
+    using S = TileShape<P, W, V>;
+    static constexpr int M = S::M;
+    static constexpr int NW = S::NW;
+    static constexpr int NS = S::NS;
     using C = TileCfg<P, W, M, NW, NS>;
     static constexpr auto kern = mlp_tiles_kernel<P, W, M, NW, NS, SRC, SINK>;
     static inline std::once_flag once;
@@ -85,10 +95,10 @@ struct TileLaunch {
     }
 };
 
-template <int P, int W, int SRC, int SINK>
+template <int P, int W, int V, int SRC, int SINK>
 int launch_tiles(const TileArgs &args, hipStream_t s)
 {
-    using TL = TileLaunch<P, W, SRC, SINK>;
+    using TL = TileLaunch<P, W, V, SRC, SINK>;
     using C = typename TL::C;
     int rc = TL::setup();
     if (rc) return rc;
@@ -115,15 +125,33 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
     return ADVISOR_OK;
 }
 
+bool tile_shape_exists(int precision, int W, int V)
+{
+    if (V == 0) return true;
+    if (V != 1) return false;
+#define ADV_E(P, WW) if (precision == P && W == WW) return TileShape<P, WW, 1>::exists;
+#define ADV_EW(P) ADV_E(P, 64) ADV_E(P, 128) ADV_E(P, 256) ADV_E(P, 512) ADV_E(P, 1024)
+    ADV_EW(PREC_FP32)
+    ADV_EW(PREC_BF16)
+    ADV_EW(PREC_FP8)
+#undef ADV_EW
+#undef ADV_E
+    return false;
+}
+
 int prepare_model_kernels(int precision, int tile_w)
 {
-#define ADV_P(P, WW)                                                              \
-    if (precision == P && tile_w == WW) {                                         \
-        int rc = TileLaunch<P, WW, SRC_DESC, SINK_RANK>::setup();                 \
-        if (!rc) rc = TileLaunch<P, WW, SRC_FEAT, SINK_PRED>::setup();            \
-        if constexpr (P != PREC_FP8)                                              \
-            if (!rc) rc = TileLaunch<P, WW, SRC_FEAT, SINK_TRAIN>::setup();       \
-        return rc;                                                                \
+#define ADV_P(P, WW)                                                                   \
+    if (precision == P && tile_w == WW) {                                              \
+        int rc = TileLaunch<P, WW, 0, SRC_DESC, SINK_RANK>::setup();                   \
+        if (!rc) rc = TileLaunch<P, WW, 0, SRC_FEAT, SINK_PRED>::setup();              \
+        if constexpr (P != PREC_FP8)                                                   \
+            if (!rc) rc = TileLaunch<P, WW, 0, SRC_FEAT, SINK_TRAIN>::setup();         \
+        if constexpr (TileShape<P, WW, 1>::exists) {                                   \
+            if (!rc) rc = TileLaunch<P, WW, 1, SRC_DESC, SINK_RANK>::setup();          \
+            if (!rc) rc = TileLaunch<P, WW, 1, SRC_FEAT, SINK_PRED>::setup();          \
+        }                                                                              \
+        return rc;                                                                     \
     }
 #define ADV_PW(P) ADV_P(P, 64) ADV_P(P, 128) ADV_P(P, 256) ADV_P(P, 512) ADV_P(P, 1024)
     ADV_PW(PREC_FP32)
@@ -135,10 +163,14 @@ int prepare_model_kernels(int precision, int tile_w)
 }
 
 template <int SRC, int SINK>
-int dispatch_tiles(int precision, int W, const TileArgs &a, hipStream_t s)
+int dispatch_tiles(int precision, int W, int variant, const TileArgs &a, hipStream_t s)
 {
-#define ADV_CASE(P, WW) \
-    if (precision == P && W == WW) return launch_tiles<P, WW, SRC, SINK>(a, s);
+#define ADV_CASE(P, WW)                                                          \
+    if (precision == P && W == WW) {                                             \
+        if constexpr (TileShape<P, WW, 1>::exists)                               \
+            if (variant == 1) return launch_tiles<P, WW, 1, SRC, SINK>(a, s);    \
+        return launch_tiles<P, WW, 0, SRC, SINK>(a, s);                          \
+    }
 #define ADV_WIDTHS(P) ADV_CASE(P, 64) ADV_CASE(P, 128) ADV_CASE(P, 256) ADV_CASE(P, 512) ADV_CASE(P, 1024)
     ADV_WIDTHS(PREC_FP32)
     ADV_WIDTHS(PREC_BF16)
@@ -185,7 +217,7 @@ int launch_train_forward(const advisor_model *m, const TileArgs &a0, hipStream_t
     TileArgs a = a0;
     a.net = net_view(m);
 #define ADV_T(P, WW) \
-    if (m->precision == P && m->tile_w == WW) return launch_tiles<P, WW, SRC_FEAT, SINK_TRAIN>(a, s);
+    if (m->precision == P && m->tile_w == WW) return launch_tiles<P, WW, 0, SRC_FEAT, SINK_TRAIN>(a, s);
     ADV_T(PREC_FP32, 64) ADV_T(PREC_FP32, 128) ADV_T(PREC_FP32, 256) ADV_T(PREC_FP32, 512)
     ADV_T(PREC_FP32, 1024) ADV_T(PREC_BF16, 64) ADV_T(PREC_BF16, 128) ADV_T(PREC_BF16, 256)
     ADV_T(PREC_BF16, 512) ADV_T(PREC_BF16, 1024)
@@ -212,8 +244,8 @@ extern "C" int advisor_predict(const advisor_model *model, const int64_t *feat, 
     a.n_rows = n;
     a.net = net_view(model);
     a.pred = pred_out;
-    return dispatch_tiles<SRC_FEAT, SINK_PRED>(model->precision, model->tile_w, a,
-                                               as_stream(stream));
+    return dispatch_tiles<SRC_FEAT, SINK_PRED>(model->precision, model->tile_w,
+                                               model->tile_variant, a, as_stream(stream));
 }
 
 extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
@@ -243,7 +275,8 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
         a.net = net_view(model);
         a.pred = pred_out;
         a.keys = reinterpret_cast<uint64_t *>(best_out);
-        rc = dispatch_tiles<SRC_DESC, SINK_RANK>(model->precision, model->tile_w, a, s);
+        rc = dispatch_tiles<SRC_DESC, SINK_RANK>(model->precision, model->tile_w,
+                                                 model->tile_variant, a, s);
         if (rc) return rc;
     }
     hipLaunchKernelGGL(keys_final_kernel, dim3(kb), dim3(256), 0, s, best_out, n_kernels);

@@ -240,6 +240,7 @@ extern "C" int advisor_model_create(const int32_t *widths, int n_widths, int pre
         m->ascale[l] = 1.0f;
     }
     if (!rc) rc = prepare_model_kernels(precision, tw);
+    if (!rc) m->tile_variant = tuned_variant(m);
     if (!rc && precision != PREC_FP8) rc = prepare_train_kernels(precision, tw);
     if (rc) {
         advisor_model_destroy(m);
