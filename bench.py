@@ -271,7 +271,7 @@ def main():
         results[p] = dict(ms_per_step=ms, kernel_ms=kern_ms, launches=launches,
                           value=nv / (ms / 1e3),
                           tflops=fl * nv / (kern_ms / 1e3) / 1e12,
-                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:2]])
+                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:3]])
         m.close()
     del feat_cal, inv_cal
 

@@ -34,7 +34,7 @@
  *      offsets [n_kernels + 1]: variants of kernel k are rows
  *        offsets[k] .. offsets[k+1]-1; offsets[0] = 0, offsets[n_kernels] =
  *        n_variants, non-decreasing (empty segments allowed).
- *  - n_variants must stay below 2^32.
+ *  - n_variants must stay below 2^32 and n_kernels below 2^31.
  */
 #ifndef ADVISOR_H
 #define ADVISOR_H
@@ -253,7 +253,7 @@ int advisor_model_load_params(advisor_model *model, const float *w_master, void 
 int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
 
 /*
- * Tile-shape autotuner. The fused kernel is built in one or two tile shapes
+ * Tile-shape autotuner. The fused kernel is built in up to three tile shapes
  * per (precision, width) (rows per tile, waves, passes); advisor_autotune
  * times each on the given ranking workload (2 warm-up calls, then `reps`
  * timed advisor_rank calls on the stream, device buffers as for
@@ -265,7 +265,8 @@ int advisor_model_grads(const advisor_model *model, float *grads_out, void *stre
  * times_ms (host, double [max_variants]) receives each shape's mean
  * milliseconds (-1 where a shape is not built); *chosen (may be NULL) the
  * chosen shape. Synchronizes the stream and allocates a temporary buffer.
- * Shapes with the same number of waves give bit-identical predictions.
+ * Shapes with the same number of waves give bit-identical predictions;
+ * otherwise only the order of the output layer's fp32 sum differs.
  */
 int advisor_autotune(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
                      const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int reps,

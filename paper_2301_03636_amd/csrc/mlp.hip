@@ -27,11 +27,15 @@ static void prof_clear_locked()
 // tile M as large as LDS allows (activations [M][W] plus the input tile),
 // 8 waves (two per SIMD, 256 registers each) except the 1024-wide fp8 tile
 // (one wave per SIMD and its 512 registers), and NS passes over each wave's
-// neurons for the 1024-wide tiles. Shape 1, where built, halves the rows so
-// two workgroups share a CU (one's barriers and epilogues overlap the other's
-// matrix work) at the price of twice the weight traffic from L2. Shapes with
-// the same wave count give bit-identical predictions; the autotuner picks
-// one per model.
+// neurons for the 1024-wide tiles. Shape 1 halves the rows with 8 waves.
+// Shape 2 halves the rows (or quarters them for 1024 bf16 and 512 fp32
+// neurons) and the waves, so two workgroups share each CU by LDS and by
+// registers: one's input stage, epilogues and barriers overlap the other's
+// matrix work, at the price of more weight traffic from L2 (and, for bf16
+// and fp8 layers of 512 or more neurons, two or four passes over the
+// activations to stay within 256 registers). Shapes with the
+// same wave count give bit-identical predictions; the autotuner picks one per
+// model.
 template <int P, int W, int V> struct TileShape;
 template <int P, int W> struct TileShape<P, W, 0> {
     static constexpr bool exists = true;
@@ -48,7 +52,15 @@ template <int P, int W> struct TileShape<P, W, 1> {
     static constexpr int NW = 8;
     static constexpr int NS = (P == PREC_FP8 && W == 1024) ? 2 : 1;
 };
-constexpr int N_TILE_SHAPES = 2;
+template <int P, int W> struct TileShape<P, W, 2> {
+    static constexpr bool exists = (P == PREC_FP32 && (W == 256 || W == 512)) ||
+                                   (P == PREC_BF16 && (W == 256 || W == 512 || W == 1024)) ||
+                                   (P == PREC_FP8 && W == 512);
+    static constexpr int M = ((P == PREC_BF16 && W == 1024) || (P == PREC_FP32 && W == 512)) ? 32 : 64;
+    static constexpr int NW = 4;
+    static constexpr int NS = P == PREC_FP32 ? 1 : ((P == PREC_FP8 && W == 1024) ? 4 : (W >= 512 ? 2 : 1));
+};
+constexpr int N_TILE_SHAPES = 3;
 
 __global__ void keys_init_kernel(uint64_t *keys, int64_t n)
 {
@@ -128,8 +140,10 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
 bool tile_shape_exists(int precision, int W, int V)
 {
     if (V == 0) return true;
-    if (V != 1) return false;
-#define ADV_E(P, WW) if (precision == P && W == WW) return TileShape<P, WW, 1>::exists;
+    if (V != 1 && V != 2) return false;
+#define ADV_E(P, WW)                                                                   \
+    if (precision == P && W == WW)                                                     \
+        return V == 1 ? TileShape<P, WW, 1>::exists : TileShape<P, WW, 2>::exists;
 #define ADV_EW(P) ADV_E(P, 64) ADV_E(P, 128) ADV_E(P, 256) ADV_E(P, 512) ADV_E(P, 1024)
     ADV_EW(PREC_FP32)
     ADV_EW(PREC_BF16)
@@ -151,6 +165,10 @@ int prepare_model_kernels(int precision, int tile_w)
             if (!rc) rc = TileLaunch<P, WW, 1, SRC_DESC, SINK_RANK>::setup();          \
             if (!rc) rc = TileLaunch<P, WW, 1, SRC_FEAT, SINK_PRED>::setup();          \
         }                                                                              \
+        if constexpr (TileShape<P, WW, 2>::exists) {                                   \
+            if (!rc) rc = TileLaunch<P, WW, 2, SRC_DESC, SINK_RANK>::setup();          \
+            if (!rc) rc = TileLaunch<P, WW, 2, SRC_FEAT, SINK_PRED>::setup();          \
+        }                                                                              \
         return rc;                                                                     \
     }
 #define ADV_PW(P) ADV_P(P, 64) ADV_P(P, 128) ADV_P(P, 256) ADV_P(P, 512) ADV_P(P, 1024)
@@ -169,6 +187,8 @@ int dispatch_tiles(int precision, int W, int variant, const TileArgs &a, hipStre
     if (precision == P && W == WW) {                                             \
         if constexpr (TileShape<P, WW, 1>::exists)                               \
             if (variant == 1) return launch_tiles<P, WW, 1, SRC, SINK>(a, s);    \
+        if constexpr (TileShape<P, WW, 2>::exists)                               \
+            if (variant == 2) return launch_tiles<P, WW, 2, SRC, SINK>(a, s);    \
         return launch_tiles<P, WW, 0, SRC, SINK>(a, s);                          \
     }
 #define ADV_WIDTHS(P) ADV_CASE(P, 64) ADV_CASE(P, 128) ADV_CASE(P, 256) ADV_CASE(P, 512) ADV_CASE(P, 1024)
@@ -257,6 +277,7 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
     if (rc) return rc;
     if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
     if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels >= (int64_t)1 << 31) return fail(ADVISOR_ESHAPE, "n_kernels must be < 2^31");
     if (n_kernels == 0) return ADVISOR_OK;
     if (!kdesc || !offsets || !best_out || (n_variants > 0 && !vdesc))
         return fail(ADVISOR_EINVAL, "advisor_rank: null pointer");

@@ -159,16 +159,27 @@ struct TileCfg {
     static constexpr int PARTS = THREADS / M;              // threads per row in the input stage
     static_assert(PARTS >= 1 && NFEAT % PARTS == 0, "input split");
     static constexpr int FPP = NFEAT / PARTS;              // features per thread
-    // the activation region also parks the tile's int64 features during the
-    // input stage (rows of FS = 33 int64, one spare to spread the banks), so
-    // it holds whichever of the two is larger
-    static constexpr int FS = NFEAT + 1;
-    static constexpr size_t ACT_BYTES = (size_t)M * AS > (size_t)M * FS * 8
-                                            ? (size_t)M * AS : (size_t)M * FS * 8;
+    static constexpr size_t ACT_BYTES = (size_t)M * AS;
     static constexpr size_t LDS = (size_t)M * XS + ACT_BYTES + (size_t)WN * M * 4 + M * 8;
     static_assert(M % 32 == 0 && (M * XS) % 16 == 0 && ACT_BYTES % 16 == 0, "LDS alignment");
     static_assert(LDS <= 160 * 1024, "tile does not fit the 160 KiB of LDS");
 };
+
+// Waves per SIMD the register allocation of a tile kernel aims at: the
+// workgroups that fit a CU's LDS times the waves each puts on a SIMD, between
+// one and two (two leave 256 registers per wave). Computed apart from
+// TileCfg so that naming a kernel does not check its tile split.
+template <int P, int W, int M, int NWAVES>
+constexpr int tile_waves_per_simd()
+{
+    constexpr int xs = 32 * Geo<FirstP<P>::value>::EB + Geo<FirstP<P>::value>::PAD;
+    constexpr int as = W * Geo<P>::EB + Geo<P>::PAD;
+    constexpr int wn = W / 32 < NWAVES ? W / 32 : NWAVES;
+    constexpr size_t lds = (size_t)M * xs + (size_t)M * as + (size_t)wn * M * 4 + M * 8;
+    constexpr int blocks = (int)((160 * 1024) / lds);
+    constexpr int w = blocks * NWAVES / 4;
+    return w < 1 ? 1 : (w > 2 ? 2 : w);
+}
 
 // 16-byte-aligned LDS vector load (an fp8 vector is two 16-byte halves).
 template <int P>
@@ -188,26 +199,38 @@ __device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
     }
 }
 
-// acc[i][j] += W (A vectors streamed from global/L2) x act^T (B vectors from
-// LDS) over the K inputs of one layer. Software-pipelined: the weight vectors
-// of k-group kg + PF are requested while group kg is multiplied (a ring of PF
-// register slots, PF dividing the group count so every slot index is a
-// compile-time constant), and the LDS operands of kg + 1 are read while kg is
-// multiplied.
+// acc[i][j] = bias + W (A vectors streamed from global/L2) x act^T (B vectors
+// from LDS) over the K inputs of one layer; a null bias starts from zero.
+// Software-pipelined: the weight vectors of k-group kg + PF are requested
+// while group kg is multiplied (a ring of PF register slots, PF dividing the
+// group count so every slot index is a compile-time constant), and the LDS
+// operands of kg + 1 are read while kg is multiplied.
 template <int PL, int K, int NBW, int MBW>
 __device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restrict__ wl,
                                           const unsigned char *lds_in, int stride, int nb0,
-                                          int mb0, int lane, v16f (&acc)[NBW][MBW])
+                                          int mb0, int lane, v16f (&acc)[NBW][MBW],
+                                          const float *__restrict__ bias = nullptr)
 {
     using G = Geo<PL>;
     using V = typename G::Vec;
     constexpr int KGROUPS = K / G::KG;
     constexpr int PF = (KGROUPS % 2 == 0 && sizeof(V) <= 16) ? 2 : 1;  // 32-byte fp8 vectors: 1
     const int half = lane >> 5, col = lane & 31;
+    // accumulator r of block i holds neuron (nb0 + i) * 32 + 8 * (r / 4) + 4 * half + r % 4
 #pragma unroll
-    for (int i = 0; i < NBW; ++i)
+    for (int i = 0; i < NBW; ++i) {
+        v16f b0 = v16f{0};
+        if (bias) {
 #pragma unroll
-        for (int j = 0; j < MBW; ++j) acc[i][j] = v16f{0};
+            for (int g = 0; g < 4; ++g) {
+                const v4f bv = *reinterpret_cast<const v4f *>(bias + (nb0 + i) * 32 + 8 * g + 4 * half);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) b0[4 * g + e] = bv[e];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < MBW; ++j) acc[i][j] = b0;
+    }
     const unsigned char *bbase = lds_in + (size_t)(mb0 * 32 + col) * stride + half * G::KV * G::EB;
     const V *abase = wl + (int64_t)nb0 * KGROUPS * 64 + lane;
     V ring[PF][NBW];
@@ -323,7 +346,9 @@ __device__ __forceinline__ void copy_act_transposed(const unsigned char *act, vo
 }
 
 template <int P, int W, int M, int NWAVES, int NSPLIT, int SRC, int SINK>
-__global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
+__global__ __launch_bounds__(NWAVES * 64)
+__attribute__((amdgpu_waves_per_eu(tile_waves_per_simd<P, W, M, NWAVES>()))) void
+mlp_tiles_kernel(TileArgs args)
 {
     using C = TileCfg<P, W, M, NWAVES, NSPLIT>;
     using G = typename C::G;
@@ -348,68 +373,59 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
-        // ---- input stage, step 1: one thread per row builds its 32 integer
-        // features and parks them in the activation buffer (free until layer
-        // 0 writes it), in rows padded to 33 entries so neighbouring rows
-        // start in different banks
-        int64_t *fstage = reinterpret_cast<int64_t *>(act);
-        if constexpr (SRC == SRC_DESC) {
-            if (tid < M) {
-                const int64_t row = row0 + tid;
-                bool ok = row < n;
-                int64_t kid = -1;
+        // ---- input stage: PARTS threads per row. Each reads the row's
+        // descriptors (the repeated reads are cache hits), forms the row's
+        // integer features in registers, and standardizes its own FPP of
+        // them into the input tile in the first layer's precision.
+        {
+            const int r = tid % M, part = tid / M;
+            const int64_t row = row0 + r;
+            const bool inrow = row < n;
+            uint64_t fsel[C::FPP];
+            bool ok = inrow;
+            if constexpr (SRC == SRC_DESC) {
                 Feat f;
-                if (ok) {
+                int kid = -1;
+                if (inrow) {
                     ok = featurize_one(args.kdesc, args.vdesc + row * VD, args.n_k, f);
-                    kid = args.vdesc[row * VD];
+                    const int64_t k = args.vdesc[row * VD];
+                    kid = (int)k;  // in [0, n_k) when ok, and n_k < 2^31
                     if (SINK == SINK_RANK && ok)  // the variant must sit in its kernel's segment
-                        ok = args.offsets[kid] <= row && row < args.offsets[kid + 1];
+                        ok = args.offsets[k] <= row && row < args.offsets[k + 1];
                 } else {
 #pragma unroll
                     for (int j = 0; j < NFEAT; ++j) f.f[j] = 0;
                 }
+                // this thread's FPP features (part is not a compile-time value)
 #pragma unroll
-                for (int j = 0; j < NFEAT; ++j) fstage[tid * C::FS + j] = (int64_t)f.f[j];
-                meta_ok[tid] = ok ? 1 : 0;
-                meta_kid[tid] = (int)kid;
-            }
-            __syncthreads();
-        }
-        // step 2: PARTS threads per row standardize FPP features each in
-        // float64 and store them in the first layer's precision
-        {
-            const int r = tid % M, part = tid / M;
-            const int64_t row = row0 + r;
-            double xv[C::FPP];
+                for (int q = 0; q < C::FPP; ++q) fsel[q] = 0;
 #pragma unroll
-            for (int q = 0; q < C::FPP; ++q) {
-                const int j = part * C::FPP + q;
-                if constexpr (SRC == SRC_DESC) {
-                    const bool ok = meta_ok[r] != 0;
-                    const int64_t fv = fstage[r * C::FS + j];
-                    xv[q] = ok ? zscore(fv, net.mu[j], net.sigma[j]) : 0.0;
-                } else {
-                    xv[q] = row < n ? zscore(args.feat[row * NFEAT + j], net.mu[j], net.sigma[j])
-                                    : 0.0;
+                for (int j = 0; j < NFEAT; ++j)
+                    if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
+                if (part == 0) {
+                    meta_ok[r] = ok ? 1 : 0;
+                    meta_kid[r] = kid;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < C::FPP; ++q)
+                    fsel[q] = inrow ? (uint64_t)args.feat[row * NFEAT + part * C::FPP + q] : 0;
+                if (part == 0) {
+                    meta_ok[r] = inrow ? 1 : 0;
+                    meta_kid[r] = -1;
                 }
             }
             unsigned char *xr = xin + (size_t)r * C::XS + part * C::FPP * G0::EB;
 #pragma unroll
             for (int q = 0; q < C::FPP; ++q) {
-                const float x = (float)xv[q];
+                const int j = part * C::FPP + q;
+                const float x = ok ? zscore_fast((int64_t)fsel[q], net.mu[j], net.sigma[j]) : 0.0f;
                 if constexpr (P0 == PREC_FP32)
                     reinterpret_cast<float *>(xr)[q] = x;
                 else
                     reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
                 if constexpr (SINK == SINK_TRAIN)
-                    save_elem<P0>(args.save_x, (int64_t)(part * C::FPP + q) * args.save_ld + row,
-                                  row < n ? x : 0.0f);
-            }
-            if constexpr (SRC == SRC_FEAT) {
-                if (part == 0) {
-                    meta_ok[r] = row < n ? 1 : 0;
-                    meta_kid[r] = -1;
-                }
+                    save_elem<P0>(args.save_x, (int64_t)j * args.save_ld + row, inrow ? x : 0.0f);
             }
         }
         __syncthreads();
@@ -423,7 +439,10 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
         for (int l = 0; l < net.n_hidden; ++l) {
             const bool last = l + 1 == net.n_hidden;
             const float *bias = net.b[l];
-            const float qs = (P == PREC_FP8 && l > 0) ? net.qscale[l] : 1.0f;
+            // fp8 layers scale the products before the bias; every other layer
+            // starts its accumulators at the bias
+            const bool scaled = P == PREC_FP8 && l > 0;
+            const float qs = scaled ? net.qscale[l] : 1.0f;
             const float qinv = net.qinv[l];
             typename Held<P>::T held[C::NSPLIT > 1 ? C::NSPLIT - 1 : 1][C::NBP][4][C::MBW];
             float srow[C::MBW];
@@ -437,11 +456,11 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                 if (l == 0)
                     layer_mma<P0, 32, C::NBP, C::MBW>(
                         reinterpret_cast<const typename G0::Vec *>(net.w[0]), xin, C::XS, nbp0,
-                        mb0, lane, acc);
+                        mb0, lane, acc, bias);
                 else
                     layer_mma<P, W, C::NBP, C::MBW>(
                         reinterpret_cast<const typename G::Vec *>(net.w[l]), act, C::AS, nbp0,
-                        mb0, lane, acc);
+                        mb0, lane, acc, scaled ? nullptr : bias);
                 // training keeps the last hidden layer's outputs too (copied out below)
                 constexpr bool keep_last = SINK == SINK_TRAIN;
                 if (final_pass && (!last || keep_last)) {
@@ -468,7 +487,7 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
-                        bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
+                        if (scaled) bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
                         if (last) hw_r[g] = *reinterpret_cast<const v4f *>(net.head_w + nn);
                     }
 #pragma unroll
@@ -480,7 +499,8 @@ __global__ __launch_bounds__(NWAVES * 64) void mlp_tiles_kernel(TileArgs args)
                             v4f v;
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
-                                const float z = acc[i][j][4 * g + e] * qs + bias_r[g][e];
+                                const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
+                                                       : acc[i][j][4 * g + e];
                                 v[e] = z > 0.0f ? z : 0.0f;
                             }
                             if (last) {

@@ -29,3 +29,28 @@ def rel_err(p, r):
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def segment_argmin(pred, offsets):
+    """Per segment, the lowest index holding the smallest non-NaN value, or
+    -1 when the segment is empty or all NaN. Plain numpy (an fmin reduction
+    per segment), independent of the library and of the oracle: it checks
+    that the library's argmin is exact on the library's own predictions."""
+    pred = np.asarray(pred, dtype=np.float64)
+    off = np.asarray(offsets, dtype=np.int64)
+    nk = off.size - 1
+    best = np.full(nk, -1, dtype=np.int64)
+    counts = np.diff(off)
+    nz = np.nonzero(counts)[0]
+    if nz.size == 0:
+        return best
+    assert pred.size == off[-1]
+    segmin = np.full(nk, np.nan)
+    segmin[nz] = np.fmin.reduceat(pred, off[nz])
+    seg = np.repeat(np.arange(nk), counts)
+    idx = np.nonzero(pred == segmin[seg])[0]
+    s = seg[idx]
+    first = np.ones(idx.size, dtype=bool)
+    first[1:] = s[1:] != s[:-1]
+    best[s[first]] = idx[first]
+    return best
