@@ -13,7 +13,9 @@ peak of its precision, with its duration taken from HIP events recorded
 around each of its launches; `cpu_baseline` is the float64 CPU oracle timed
 on a seeded sample of whole kernels of the same workload on this host.
 `precisions` repeats the measurement for the other compute precisions on the
-same inputs, each with its argmin agreement against the oracle on the sample.
+same inputs, each with its argmin agreement against the oracle on the sample
+(He-initialized weights) and for a network first trained by the library on
+the synthetic runtime model.
 """
 from __future__ import annotations
 
@@ -152,7 +154,64 @@ def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds, gpu_best_by_p
         "cores": threads,
         "kind": "oracle",
         "sample": "%d of %d kernels (seeded), %d variants, %.1f s wall" % (ks.size, nk, nv_s, dt),
-    }, agree
+    }, agree, per_variant
+
+
+def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_variant, seconds):
+    """Argmin agreement with the oracle for a network trained by the
+    library's own training step on the synthetic runtime model (the targets
+    of the gain test), which is what a user of the method ranks with. A
+    trained network predicts near-equal runtimes for variants whose true
+    runtimes are near-equal (e.g. launch shapes of a memory-bound kernel), so
+    lower-precision picks can differ from the float64 pick among near-ties;
+    the gap between the two picks under the oracle's own prediction says
+    what such a disagreement costs."""
+    import oracle
+    from oracle import cost
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    rows = workload.sample_rows(vd.shape[0], 131072, 4300)
+    f, inv = oracle.featurize(kd, vd[rows])
+    f = f[inv == 0]
+    mu, sd = oracle.zscore_fit(f)
+    y = cost.target(f, workload.noise(f.shape[0], 4301))
+    m = adv.Model(widths, "bf16")
+    m.set_params(workload.he_init(widths, 4302), mu, sd)
+    F, Y = to_dev(f), to_dev(y)
+    rng = np.random.default_rng(4303)
+    loss = None
+    for _ in range(400):
+        idx = torch.from_numpy(rng.integers(0, f.shape[0], 8192)).to(F.device)
+        loss, _ = adv.advisor_train_step(m.handle, F[idx].contiguous(), Y[idx].contiguous(),
+                                         lr=2e-3)
+    w, _, _ = m.get_params()
+    final_loss = float(loss.item())
+    m.close()
+    nk = off.size - 1
+    n_sample = int(min(nk, max(8, seconds / max(per_variant * (off[-1] / nk), 1e-9))))
+    ks, rws, sub_off = workload.sample_kernels(off, n_sample, 4304)
+    vsub = vd[rws].copy()
+    vsub[:, 0] = np.repeat(np.arange(ks.size), sub_off[1:] - sub_off[:-1])
+    best_cpu, pred_cpu = oracle.rank(kd[ks], vsub, sub_off, widths, w.astype(np.float64), mu,
+                                     sd, n_threads=threads, want_pred=True)
+    K, V, O = to_dev(kd[ks]), to_dev(vsub), to_dev(sub_off)
+    agree, regret = {}, {}
+    has = best_cpu >= 0
+    for p in precs:
+        g = adv.Model(widths, p)
+        g.set_params(w, mu, sd)
+        if p == "fp8":
+            g.calibrate_fp8(F)
+        best_gpu = g.rank(K, V, O).cpu().numpy()
+        g.close()
+        agree[p] = float(np.mean(best_gpu == best_cpu))
+        # how much worse the GPU's pick is by the oracle's own prediction
+        # (ln us): a disagreement between near-tied variants costs ~0
+        gap = pred_cpu[best_gpu[has]] - pred_cpu[best_cpu[has]]
+        regret[p] = {"mean": float(gap.mean()), "max": float(gap.max()),
+                     "frac_below_0.01": float(np.mean(gap < 0.01))}
+    return agree, {"train_steps": 400, "batch": 8192, "final_loss": final_loss,
+                   "sample_kernels": int(ks.size), "sample_variants": int(rws.size),
+                   "pick_gap_ln_us_by_oracle_prediction": regret}
 
 
 def train_flops_per_sample(widths):
@@ -271,7 +330,7 @@ def main():
         results[p] = dict(ms_per_step=ms, kernel_ms=kern_ms, launches=launches,
                           value=nv / (ms / 1e3),
                           tflops=fl * nv / (kern_ms / 1e3) / 1e12,
-                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:3]])
+                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:4]])
         m.close()
     del feat_cal, inv_cal
 
@@ -300,9 +359,13 @@ def main():
                      "kernel_ms": main_r["kernel_ms"],
                      "flops_per_variant": sum(layer_flops(widths))},
     }
+    agree_t = {}
     if not args.no_cpu_baseline:
-        cb, agree = cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, args.cpu_seconds,
-                                     best_by_prec)
+        cb, agree, per_variant = cpu_baseline_leg(kd, vd, off, widths, params, mu, sd,
+                                                  args.cpu_seconds, best_by_prec)
+        agree_t, tinfo = trained_agreement(adv, torch, T, kd, vd, off, widths, list(results),
+                                           per_variant, args.cpu_seconds / 2)
+        cb["argmin_agreement_trained_network"] = dict(agree_t, **tinfo)
         out["cpu_baseline"] = cb
     else:
         agree = {}
@@ -310,7 +373,8 @@ def main():
         p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
             "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
             "tile_shape": r["tile_shape"], "autotune_ms": r["tune_ms"],
-            "argmin_agreement_vs_oracle_sample": agree.get(p)}
+            "argmin_agreement_vs_oracle_sample": agree.get(p),
+            "argmin_agreement_trained_network": agree_t.get(p)}
         for p, r in results.items()}
     if args.train_steps > 0:
         out["train"] = train_leg(adv, torch, d, args.train_steps, args.warmup)

@@ -39,12 +39,14 @@ static void prof_clear_locked()
 template <int P, int W, int V> struct TileShape;
 template <int P, int W> struct TileShape<P, W, 0> {
     static constexpr bool exists = true;
+    static constexpr bool PP = false;
     static constexpr int M = P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
                                             : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
     static constexpr int NW = (W == 1024 && P == PREC_FP8) ? 4 : 8;
     static constexpr int NS = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1)) : 1;
 };
 template <int P, int W> struct TileShape<P, W, 1> {
+    static constexpr bool PP = false;
     static constexpr bool exists = (P == PREC_FP32 && W == 256) ||
                                    (P == PREC_BF16 && (W == 256 || W == 512 || W == 1024)) ||
                                    (P == PREC_FP8 && (W == 512 || W == 1024));
@@ -53,6 +55,7 @@ template <int P, int W> struct TileShape<P, W, 1> {
     static constexpr int NS = (P == PREC_FP8 && W == 1024) ? 2 : 1;
 };
 template <int P, int W> struct TileShape<P, W, 2> {
+    static constexpr bool PP = false;
     static constexpr bool exists = (P == PREC_FP32 && (W == 256 || W == 512)) ||
                                    (P == PREC_BF16 && (W == 256 || W == 512 || W == 1024)) ||
                                    (P == PREC_FP8 && W == 512);
@@ -60,7 +63,28 @@ template <int P, int W> struct TileShape<P, W, 2> {
     static constexpr int NW = 4;
     static constexpr int NS = P == PREC_FP32 ? 1 : ((P == PREC_FP8 && W == 1024) ? 4 : (W >= 512 ? 2 : 1));
 };
-constexpr int N_TILE_SHAPES = 3;
+// Shape 3 is the ping-pong schedule (mlp_pp_kernel) on the rows and waves
+// of shape 0 (of shape 1 for 1024-wide fp8 layers, whose shape 0 has four
+// waves), where each wave holds an even number of 32-row blocks; it gives
+// the same bits as that shape.
+template <int P, int W> struct TileShape<P, W, 3> {
+    static constexpr bool PP = true;
+    static constexpr bool exists = (P == PREC_FP32 && (W == 256 || W == 512)) ||
+                                   (P == PREC_BF16 && (W == 256 || W == 512 || W == 1024)) ||
+                                   (P == PREC_FP8 && (W == 512 || W == 1024));
+    using Base = TileShape<P, W, (P == PREC_FP8 && W == 1024) ? 1 : 0>;
+    static constexpr int M = Base::M;
+    static constexpr int NW = Base::NW;
+    static constexpr int NS = 1;
+};
+constexpr int N_TILE_SHAPES = 4;
+
+template <class S, int P, int W, int SRC, int SINK, bool PP = S::PP> struct TileKernel {
+    static constexpr auto kern = mlp_tiles_kernel<P, W, S::M, S::NW, S::NS, SRC, SINK>;
+};
+template <class S, int P, int W, int SRC, int SINK> struct TileKernel<S, P, W, SRC, SINK, true> {
+    static constexpr auto kern = mlp_pp_kernel<P, W, S::M, S::NW, SRC, SINK>;
+};
 
 __global__ void keys_init_kernel(uint64_t *keys, int64_t n)
 {
@@ -84,8 +108,8 @@ struct TileLaunch {
     static constexpr int M = S::M;
     static constexpr int NW = S::NW;
     static constexpr int NS = S::NS;
-    using C = TileCfg<P, W, M, NW, NS>;
-    static constexpr auto kern = mlp_tiles_kernel<P, W, M, NW, NS, SRC, SINK>;
+    using C = TileCfg<P, W, M, NW, NS, SRC == SRC_DESC && tile_vdesc_prefetch<P, W, M, NW>()>;
+    static constexpr auto kern = TileKernel<S, P, W, SRC, SINK>::kern;
     static inline std::once_flag once;
     static inline int blocks_per_cu = 1;
     static inline hipError_t setup_err = hipSuccess;
@@ -140,10 +164,11 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
 bool tile_shape_exists(int precision, int W, int V)
 {
     if (V == 0) return true;
-    if (V != 1 && V != 2) return false;
+    if (V < 1 || V >= N_TILE_SHAPES) return false;
 #define ADV_E(P, WW)                                                                   \
     if (precision == P && W == WW)                                                     \
-        return V == 1 ? TileShape<P, WW, 1>::exists : TileShape<P, WW, 2>::exists;
+        return V == 1 ? TileShape<P, WW, 1>::exists                                    \
+                      : (V == 2 ? TileShape<P, WW, 2>::exists : TileShape<P, WW, 3>::exists);
 #define ADV_EW(P) ADV_E(P, 64) ADV_E(P, 128) ADV_E(P, 256) ADV_E(P, 512) ADV_E(P, 1024)
     ADV_EW(PREC_FP32)
     ADV_EW(PREC_BF16)
@@ -169,6 +194,10 @@ int prepare_model_kernels(int precision, int tile_w)
             if (!rc) rc = TileLaunch<P, WW, 2, SRC_DESC, SINK_RANK>::setup();          \
             if (!rc) rc = TileLaunch<P, WW, 2, SRC_FEAT, SINK_PRED>::setup();          \
         }                                                                              \
+        if constexpr (TileShape<P, WW, 3>::exists) {                                   \
+            if (!rc) rc = TileLaunch<P, WW, 3, SRC_DESC, SINK_RANK>::setup();          \
+            if (!rc) rc = TileLaunch<P, WW, 3, SRC_FEAT, SINK_PRED>::setup();          \
+        }                                                                              \
         return rc;                                                                     \
     }
 #define ADV_PW(P) ADV_P(P, 64) ADV_P(P, 128) ADV_P(P, 256) ADV_P(P, 512) ADV_P(P, 1024)
@@ -189,6 +218,8 @@ int dispatch_tiles(int precision, int W, int variant, const TileArgs &a, hipStre
             if (variant == 1) return launch_tiles<P, WW, 1, SRC, SINK>(a, s);    \
         if constexpr (TileShape<P, WW, 2>::exists)                               \
             if (variant == 2) return launch_tiles<P, WW, 2, SRC, SINK>(a, s);    \
+        if constexpr (TileShape<P, WW, 3>::exists)                               \
+            if (variant == 3) return launch_tiles<P, WW, 3, SRC, SINK>(a, s);    \
         return launch_tiles<P, WW, 0, SRC, SINK>(a, s);                          \
     }
 #define ADV_WIDTHS(P) ADV_CASE(P, 64) ADV_CASE(P, 128) ADV_CASE(P, 256) ADV_CASE(P, 512) ADV_CASE(P, 1024)

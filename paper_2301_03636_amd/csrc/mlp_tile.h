@@ -139,7 +139,7 @@ __device__ __forceinline__ void save_elem(void *base, int64_t idx, float v)
         reinterpret_cast<__bf16 *>(base)[idx] = (__bf16)v;
 }
 
-template <int P, int W, int M, int NWAVES, int NSPLIT_ = 1>
+template <int P, int W, int M, int NWAVES, int NSPLIT_ = 1, bool VPF_ = false>
 struct TileCfg {
     static constexpr int NSPLIT = NSPLIT_;                 // passes over a wave's neurons
     using G = Geo<P>;
@@ -160,7 +160,13 @@ struct TileCfg {
     static_assert(PARTS >= 1 && NFEAT % PARTS == 0, "input split");
     static constexpr int FPP = NFEAT / PARTS;              // features per thread
     static constexpr size_t ACT_BYTES = (size_t)M * AS;
-    static constexpr size_t LDS = (size_t)M * XS + ACT_BYTES + (size_t)WN * M * 4 + M * 8;
+    static constexpr size_t LDS_BASE = (size_t)M * XS + ACT_BYTES + (size_t)WN * M * 4 + M * 8;
+    // descriptor prefetch (VPF): the next tile's variant rows (M x 64 B) and
+    // the output-layer weights
+    static constexpr bool VPF = VPF_;
+    static constexpr size_t VST_BYTES = VPF ? (size_t)M * 64 : 0;
+    static constexpr size_t HW_BYTES = VPF ? (size_t)W * 4 : 0;
+    static constexpr size_t LDS = LDS_BASE + VST_BYTES + HW_BYTES;
     static_assert(M % 32 == 0 && (M * XS) % 16 == 0 && ACT_BYTES % 16 == 0, "LDS alignment");
     static_assert(LDS <= 160 * 1024, "tile does not fit the 160 KiB of LDS");
 };
@@ -181,6 +187,25 @@ constexpr int tile_waves_per_simd()
     return w < 1 ? 1 : (w > 2 ? 2 : w);
 }
 
+// Whether the fused kernel reading descriptors stages the next tile's
+// variant rows in LDS: only where the staging (plus the output weights it
+// moves to LDS) leaves the workgroups per CU unchanged, and not for fp8
+// tiles (their scaled last layer reads its bias in the epilogue, and the
+// extra registers spill).
+template <int P, int W, int M, int NWAVES>
+constexpr bool tile_vdesc_prefetch()
+{
+    constexpr int xs = 32 * Geo<FirstP<P>::value>::EB + Geo<FirstP<P>::value>::PAD;
+    constexpr int as = W * Geo<P>::EB + Geo<P>::PAD;
+    constexpr int wn = W / 32 < NWAVES ? W / 32 : NWAVES;
+    constexpr size_t base = (size_t)M * xs + (size_t)M * as + (size_t)wn * M * 4 + M * 8;
+    constexpr size_t extra = (size_t)M * 64 + (size_t)W * 4;
+    constexpr int by_regs = tile_waves_per_simd<P, W, M, NWAVES>() * 4 / NWAVES;
+    constexpr int r = by_regs < 1 ? 1 : by_regs;
+    constexpr int b0 = (int)((160 * 1024) / base), b1 = (int)((160 * 1024) / (base + extra));
+    return P != PREC_FP8 && base + extra <= 160 * 1024 && (b0 < r ? b0 : r) == (b1 < r ? b1 : r);
+}
+
 // 16-byte-aligned LDS vector load (an fp8 vector is two 16-byte halves).
 template <int P>
 __device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
@@ -199,87 +224,137 @@ __device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
     }
 }
 
+// Depth of the weight ring of a layer with K inputs: two k-groups ahead when
+// the group count is even and a vector fits 16 bytes, else one (32-byte fp8).
+template <int PL, int K>
+constexpr int ring_depth()
+{
+    constexpr int kgroups = K / Geo<PL>::KG;
+    return (kgroups % 2 == 0 && sizeof(typename Geo<PL>::Vec) <= 16) ? 2 : 1;
+}
+
+// Request the first ring_depth k-groups of the weight vectors of n-blocks
+// nb0 .. nb0 + NBW - 1 (they do not depend on the activations, so this can be
+// issued before the layer's input is ready).
+template <int PL, int K, int NBW>
+__device__ __forceinline__ void ring_load(const typename Geo<PL>::Vec *__restrict__ wl, int nb0,
+                                          int lane,
+                                          typename Geo<PL>::Vec (&ring)[ring_depth<PL, K>()][NBW])
+{
+    constexpr int KGROUPS = K / Geo<PL>::KG;
+    const typename Geo<PL>::Vec *abase = wl + (int64_t)nb0 * KGROUPS * 64 + lane;
+#pragma unroll
+    for (int p = 0; p < ring_depth<PL, K>(); ++p)
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) ring[p][i] = abase[((int64_t)i * KGROUPS + p) * 64];
+}
+
+// One k-group of layer_mma: take the weight vectors of group kg from ring
+// slot U and request those of group kg + PF into it, read the LDS operands of
+// group kg + 1, then multiply. The first group starts from `init` (the bias)
+// through the matrix core's C operand, so the accumulators need no copies.
+template <int PL, int K, int NBW, int MBW, int U, bool FIRST>
+__device__ __forceinline__ void mma_group(const typename Geo<PL>::Vec *__restrict__ abase,
+                                          const unsigned char *bbase, int stride, int kg,
+                                          typename Geo<PL>::Vec (&ring)[ring_depth<PL, K>()][NBW],
+                                          typename Geo<PL>::Vec (&bcur)[MBW],
+                                          v16f (&acc)[NBW][MBW], const v16f (&init)[NBW])
+{
+    using G = Geo<PL>;
+    using V = typename G::Vec;
+    constexpr int KGROUPS = K / G::KG;
+    constexpr int PF = ring_depth<PL, K>();
+    V a[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) a[i] = ring[U][i];
+    if (kg + PF < KGROUPS) {
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) ring[U][i] = abase[((int64_t)i * KGROUPS + kg + PF) * 64];
+    }
+    V bnext[MBW];
+    if (kg + 1 < KGROUPS) {
+#pragma unroll
+        for (int j = 0; j < MBW; ++j)
+            bnext[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride + (kg + 1) * G::KG * G::EB);
+    }
+    // keep the requests above ahead of the multiplies below: without this
+    // the scheduler sinks each load next to its first use
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+        for (int j = 0; j < MBW; ++j) {
+            if constexpr (PL == PREC_FP32) {
+                acc[i][j] = mma(a[i][0], bcur[j][0], FIRST ? init[i] : acc[i][j]);
+#pragma unroll
+                for (int t = 1; t < G::KV; ++t) acc[i][j] = mma(a[i][t], bcur[j][t], acc[i][j]);
+            } else {
+                acc[i][j] = mma(a[i], bcur[j], FIRST ? init[i] : acc[i][j]);
+            }
+        }
+    if (kg + 1 < KGROUPS) {
+#pragma unroll
+        for (int j = 0; j < MBW; ++j) bcur[j] = bnext[j];
+    }
+}
+
 // acc[i][j] = bias + W (A vectors streamed from global/L2) x act^T (B vectors
 // from LDS) over the K inputs of one layer; a null bias starts from zero.
-// Software-pipelined: the weight vectors of k-group kg + PF are requested
-// while group kg is multiplied (a ring of PF register slots, PF dividing the
-// group count so every slot index is a compile-time constant), and the LDS
-// operands of kg + 1 are read while kg is multiplied.
+// Software-pipelined: `ring` arrives holding the weight vectors of the first
+// PF k-groups (ring_load), those of k-group kg + PF are requested while group
+// kg is multiplied (PF dividing the group count so every slot index is a
+// compile-time constant), and the LDS operands of kg + 1 are read while kg is
+// multiplied.
+template <int PL, int K, int NBW, int MBW>
+__device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restrict__ wl,
+                                          const unsigned char *lds_in, int stride, int nb0,
+                                          int mb0, int lane, v16f (&acc)[NBW][MBW],
+                                          const float *__restrict__ bias,
+                                          typename Geo<PL>::Vec (&ring)[ring_depth<PL, K>()][NBW])
+{
+    using G = Geo<PL>;
+    using V = typename G::Vec;
+    constexpr int KGROUPS = K / G::KG;
+    constexpr int PF = ring_depth<PL, K>();
+    const int half = lane >> 5, col = lane & 31;
+    // accumulator r of block i holds neuron (nb0 + i) * 32 + 8 * (r / 4) + 4 * half + r % 4
+    v16f init[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+        init[i] = v16f{0};
+        if (bias) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const v4f bv = *reinterpret_cast<const v4f *>(bias + (nb0 + i) * 32 + 8 * g + 4 * half);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) init[i][4 * g + e] = bv[e];
+            }
+        }
+    }
+    const unsigned char *bbase = lds_in + (size_t)(mb0 * 32 + col) * stride + half * G::KV * G::EB;
+    const V *abase = wl + (int64_t)nb0 * KGROUPS * 64 + lane;
+    V bcur[MBW];
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) bcur[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride);
+    mma_group<PL, K, NBW, MBW, 0, true>(abase, bbase, stride, 0, ring, bcur, acc, init);
+    if constexpr (PF == 2) mma_group<PL, K, NBW, MBW, 1, false>(abase, bbase, stride, 1, ring, bcur, acc, init);
+    for (int kg0 = PF; kg0 < KGROUPS; kg0 += PF) {
+        mma_group<PL, K, NBW, MBW, 0, false>(abase, bbase, stride, kg0, ring, bcur, acc, init);
+        if constexpr (PF == 2)
+            mma_group<PL, K, NBW, MBW, 1, false>(abase, bbase, stride, kg0 + 1, ring, bcur, acc, init);
+    }
+}
+
+// layer_mma with its own ring load (no prefetch across calls).
 template <int PL, int K, int NBW, int MBW>
 __device__ __forceinline__ void layer_mma(const typename Geo<PL>::Vec *__restrict__ wl,
                                           const unsigned char *lds_in, int stride, int nb0,
                                           int mb0, int lane, v16f (&acc)[NBW][MBW],
                                           const float *__restrict__ bias = nullptr)
 {
-    using G = Geo<PL>;
-    using V = typename G::Vec;
-    constexpr int KGROUPS = K / G::KG;
-    constexpr int PF = (KGROUPS % 2 == 0 && sizeof(V) <= 16) ? 2 : 1;  // 32-byte fp8 vectors: 1
-    const int half = lane >> 5, col = lane & 31;
-    // accumulator r of block i holds neuron (nb0 + i) * 32 + 8 * (r / 4) + 4 * half + r % 4
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-        v16f b0 = v16f{0};
-        if (bias) {
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const v4f bv = *reinterpret_cast<const v4f *>(bias + (nb0 + i) * 32 + 8 * g + 4 * half);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) b0[4 * g + e] = bv[e];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < MBW; ++j) acc[i][j] = b0;
-    }
-    const unsigned char *bbase = lds_in + (size_t)(mb0 * 32 + col) * stride + half * G::KV * G::EB;
-    const V *abase = wl + (int64_t)nb0 * KGROUPS * 64 + lane;
-    V ring[PF][NBW];
-#pragma unroll
-    for (int p = 0; p < PF; ++p)
-#pragma unroll
-        for (int i = 0; i < NBW; ++i) ring[p][i] = abase[((int64_t)i * KGROUPS + p) * 64];
-    V bcur[MBW];
-#pragma unroll
-    for (int j = 0; j < MBW; ++j) bcur[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride);
-    for (int kg0 = 0; kg0 < KGROUPS; kg0 += PF) {
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int kg = kg0 + u;
-            V a[NBW];
-#pragma unroll
-            for (int i = 0; i < NBW; ++i) a[i] = ring[u][i];
-            if (kg + PF < KGROUPS) {
-#pragma unroll
-                for (int i = 0; i < NBW; ++i)
-                    ring[u][i] = abase[((int64_t)i * KGROUPS + kg + PF) * 64];
-            }
-            V bnext[MBW];
-            if (kg + 1 < KGROUPS) {
-#pragma unroll
-                for (int j = 0; j < MBW; ++j)
-                    bnext[j] = lds_vec<PL>(bbase + (size_t)j * 32 * stride + (kg + 1) * G::KG * G::EB);
-            }
-            // keep the requests above ahead of the multiplies below: without
-            // this the scheduler sinks each load next to its first use
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int i = 0; i < NBW; ++i)
-#pragma unroll
-                for (int j = 0; j < MBW; ++j) {
-                    if constexpr (PL == PREC_FP32) {
-#pragma unroll
-                        for (int t = 0; t < G::KV; ++t)
-                            acc[i][j] = mma(a[i][t], bcur[j][t], acc[i][j]);
-                    } else {
-                        acc[i][j] = mma(a[i], bcur[j], acc[i][j]);
-                    }
-                }
-            if (kg + 1 < KGROUPS) {
-#pragma unroll
-                for (int j = 0; j < MBW; ++j) bcur[j] = bnext[j];
-            }
-        }
-    }
+    typename Geo<PL>::Vec ring[ring_depth<PL, K>()][NBW];
+    ring_load<PL, K, NBW>(wl, nb0, lane, ring);
+    layer_mma<PL, K, NBW, MBW>(wl, lds_in, stride, nb0, mb0, lane, acc, bias, ring);
 }
 
 // Four consecutive neurons of one variant in a layer's activation precision
@@ -302,8 +377,14 @@ __device__ __forceinline__ typename Held<P>::T pack4(v4f v, float qinv)
         o[3] = (__bf16)v[3];
         return o;
     } else {
-        return f32_to_e4m3(v[0] * qinv) | (f32_to_e4m3(v[1] * qinv) << 8) |
-               (f32_to_e4m3(v[2] * qinv) << 16) | (f32_to_e4m3(v[3] * qinv) << 24);
+        // the values are ReLU outputs (>= 0, never NaN): clamping at 448
+        // gives f32_to_e4m3's saturation, and the hardware pair conversion
+        // then rounds to nearest even exactly as f32_to_e4m3 does for every
+        // float in [0, 448]
+        const float a0 = fminf(v[0] * qinv, 448.0f), a1 = fminf(v[1] * qinv, 448.0f);
+        const float a2 = fminf(v[2] * qinv, 448.0f), a3 = fminf(v[3] * qinv, 448.0f);
+        const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a0, a1, 0, false);
+        return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a2, a3, lo, true);
     }
 }
 
@@ -323,25 +404,157 @@ __device__ __forceinline__ void store4(unsigned char *row, int n, v4f v, float q
 
 // Copy a tile's activations [M][W] (LDS rows of stride AS) to the transposed
 // global layout dst[n * ld + row0 + m] (rows >= n_rows as zero). A thread
-// moves one 16-byte run of neurons of one row; lanes of a wave take
-// consecutive rows, so each global store is a contiguous run of the batch.
+// gathers one neuron of CE consecutive rows from LDS and stores them as one
+// 16-byte vector. Eight consecutive threads take eight consecutive row groups
+// of one neuron, so a wave's store covers eight whole 128-byte lines.
 template <int P, int W, int M, int THREADS, int AS>
 __device__ __forceinline__ void copy_act_transposed(const unsigned char *act, void *dst,
                                                     int64_t ld, int64_t row0, int64_t n_rows,
                                                     int tid)
 {
     using T = typename std::conditional<P == PREC_FP32, float, __bf16>::type;
+    typedef int v4i_ __attribute__((ext_vector_type(4)));
     constexpr int CE = 16 / (int)sizeof(T);
+    constexpr int RG = M / CE;  // row groups per neuron
+    static_assert(M % CE == 0, "row groups");
     T *d = reinterpret_cast<T *>(dst);
-    for (int c = tid; c < M * (W / CE); c += THREADS) {
-        const int m = c % M, nc = c / M;
-        const int64_t row = row0 + m;
-        typedef int v4i_ __attribute__((ext_vector_type(4)));
-        const v4i_ raw = *reinterpret_cast<const v4i_ *>(act + (size_t)m * AS + nc * 16);
-        const T *vals = reinterpret_cast<const T *>(&raw);
+    static_assert(RG % 8 == 0, "row groups come in eights");
+    for (int c = tid; c < W * RG; c += THREADS) {
+        // 8 consecutive threads: 8 row groups (one 128-byte line) of a neuron
+        const int t = c >> 3, nn = t % W, m0 = ((t / W) * 8 + (c & 7)) * CE;
+        v4i_ raw;
+        T *vals = reinterpret_cast<T *>(&raw);
 #pragma unroll
-        for (int e = 0; e < CE; ++e)
-            d[(int64_t)(nc * CE + e) * ld + row] = row < n_rows ? vals[e] : (T)0.0f;
+        for (int e = 0; e < CE; ++e) {
+            const T v = *reinterpret_cast<const T *>(act + (size_t)(m0 + e) * AS + nn * sizeof(T));
+            vals[e] = row0 + m0 + e < n_rows ? v : (T)0.0f;
+        }
+        *reinterpret_cast<v4i_ *>(d + (int64_t)nn * ld + row0 + m0) = raw;
+    }
+}
+
+// Input stage of a tile: PARTS threads per row. Each reads the row's
+// descriptors (from LDS when the kernel stages them, else global; repeated
+// reads are cache hits), forms the row's integer features in registers, and
+// standardizes its own FPP of them into the input tile in the first layer's
+// precision; part 0 records the row's validity and kernel id.
+template <class C, int P, int M, int SRC, int SINK>
+__device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, int tid,
+                                           unsigned char *xin, int *meta_ok, int *meta_kid,
+                                           const unsigned char *vst)
+{
+    constexpr int P0 = FirstP<P>::value;
+    using G0 = Geo<P0>;
+    constexpr bool VPF = C::VPF;
+    const NetView &net = args.net;
+    const int64_t n = args.n_rows;
+    {
+        const int r = tid % M, part = tid / M;
+        const int64_t row = row0 + r;
+        const bool inrow = row < n;
+        uint64_t fsel[C::FPP];
+        bool ok = inrow;
+        if constexpr (SRC == SRC_DESC) {
+            Feat f;
+            int kid = -1;
+            if (inrow) {
+                const int64_t *vrow =
+                    VPF ? reinterpret_cast<const int64_t *>(vst + (size_t)r * 64) : args.vdesc + row * VD;
+                ok = featurize_one(args.kdesc, vrow, args.n_k, f);
+                const int64_t k = vrow[0];
+                kid = (int)k;  // in [0, n_k) when ok, and n_k < 2^31
+                if (SINK == SINK_RANK && ok)  // the variant must sit in its kernel's segment
+                    ok = args.offsets[k] <= row && row < args.offsets[k + 1];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NFEAT; ++j) f.f[j] = 0;
+            }
+            // this thread's FPP features (part is not a compile-time value)
+#pragma unroll
+            for (int q = 0; q < C::FPP; ++q) fsel[q] = 0;
+#pragma unroll
+            for (int j = 0; j < NFEAT; ++j)
+                if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
+            if (part == 0) {
+                meta_ok[r] = ok ? 1 : 0;
+                meta_kid[r] = kid;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < C::FPP; ++q)
+                fsel[q] = inrow ? (uint64_t)args.feat[row * NFEAT + part * C::FPP + q] : 0;
+            if (part == 0) {
+                meta_ok[r] = inrow ? 1 : 0;
+                meta_kid[r] = -1;
+            }
+        }
+        unsigned char *xr = xin + (size_t)r * C::XS + part * C::FPP * G0::EB;
+#pragma unroll
+        for (int q = 0; q < C::FPP; ++q) {
+            const int j = part * C::FPP + q;
+            const float x = ok ? zscore_fast((int64_t)fsel[q], net.mu[j], net.sigma[j]) : 0.0f;
+            if constexpr (P0 == PREC_FP32)
+                reinterpret_cast<float *>(xr)[q] = x;
+            else
+                reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
+            if constexpr (SINK == SINK_TRAIN)
+                save_elem<P0>(args.save_x, (int64_t)j * args.save_ld + row, inrow ? x : 0.0f);
+        }
+    }
+}
+
+// Output stage of a tile: one thread per row (whole waves, for the
+// shuffles) adds the output bias to the waves' partial dot products (fixed
+// order) and stores the prediction or folds it into the per-kernel argmin
+// keys.
+template <class C, int M, int SINK>
+__device__ __forceinline__ void tile_output(const TileArgs &args, int64_t row0, int tid, int lane,
+                                            int wave, const float *hpart, const int *meta_ok,
+                                            const int *meta_kid)
+{
+    const NetView &net = args.net;
+    const int64_t n = args.n_rows;
+    if (wave < (M + 63) / 64) {
+        const bool inrow = tid < M;
+        const int64_t row = row0 + tid;
+        float p = net.head_b[0];
+        if (inrow) {
+#pragma unroll
+            for (int q = 0; q < C::WN; ++q) p += hpart[q * M + tid];
+        }
+        const bool ok = inrow && meta_ok[tid] != 0;
+        if constexpr (SINK == SINK_PRED || SINK == SINK_TRAIN) {
+            if (inrow && row < n) args.pred[row] = p;
+        } else {
+            if (inrow && row < n && args.pred) args.pred[row] = ok ? p : __builtin_nanf("");
+            const bool take = ok && !__builtin_isnan(p);
+            uint64_t key = ~0ull;
+            if (take) {
+                uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
+                u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+                key = ((uint64_t)u << 32) | (uint32_t)row;
+            }
+            // segmented min over runs of equal kernel id within the wave
+            // (inclusive scan with segment-head flags), then one atomic
+            // per run from its last lane
+            const int kid = take ? meta_kid[tid] : -1;
+            const int prev = __shfl_up(kid, 1, 64);
+            int head = (lane == 0) || (prev != kid);
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint64_t kup = __shfl_up(key, off, 64);
+                const int hup = __shfl_up(head, off, 64);
+                if (lane >= off && !head) {
+                    key = kup < key ? kup : key;
+                    head = hup;
+                }
+            }
+            const int next = __shfl_down(kid, 1, 64);
+            const bool last = (lane == 63) || (next != kid);
+            if (last && kid >= 0 && kid < args.n_k && key != ~0ull)
+                atomicMin(reinterpret_cast<unsigned long long *>(args.keys + kid),
+                          (unsigned long long)key);
+        }
     }
 }
 
@@ -350,7 +563,8 @@ __global__ __launch_bounds__(NWAVES * 64)
 __attribute__((amdgpu_waves_per_eu(tile_waves_per_simd<P, W, M, NWAVES>()))) void
 mlp_tiles_kernel(TileArgs args)
 {
-    using C = TileCfg<P, W, M, NWAVES, NSPLIT>;
+    constexpr bool VPF = SRC == SRC_DESC && tile_vdesc_prefetch<P, W, M, NWAVES>();
+    using C = TileCfg<P, W, M, NWAVES, NSPLIT, VPF>;
     using G = typename C::G;
     constexpr int P0 = FirstP<P>::value;
     using G0 = Geo<P0>;
@@ -360,6 +574,8 @@ mlp_tiles_kernel(TileArgs args)
     float *hpart = reinterpret_cast<float *>(act + C::ACT_BYTES);       // [WN][M]
     int *meta_ok = reinterpret_cast<int *>(hpart + C::WN * M);  // [M]
     int *meta_kid = meta_ok + M;                                // [M]
+    unsigned char *vst = lds + C::LDS_BASE;                     // [M][64 B] (VPF)
+    float *hw_lds = reinterpret_cast<float *>(vst + C::VST_BYTES);  // [W] (VPF)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wn = wave % C::WN, wm = wave / C::WN;
@@ -370,64 +586,49 @@ mlp_tiles_kernel(TileArgs args)
     // the training forward covers every row of the saved buffers (zeros past n)
     const int64_t ntiles = SINK == SINK_TRAIN ? args.save_ld / M : (n + M - 1) / M;
 
+    // weight rings of the first layer and of the hidden layers: each call of
+    // layer_mma finds its first k-groups already requested, by the call before
+    // it (across the epilogue and the barriers, which do not wait for global
+    // loads) or, for the first layer, at the end of the input stage. Tiles
+    // whose accumulators fill most registers (more than 4 blocks of 32 x 32)
+    // request them at the call instead: the ring would spill there.
+    constexpr bool XPF = C::NBP * C::MBW <= 4;
+    using R0 = typename G0::Vec;
+    using RH = typename G::Vec;
+    R0 ring0[ring_depth<P0, 32>()][C::NBP];
+    RH ringh[ring_depth<P, W>()][C::NBP];
+    const R0 *w0 = reinterpret_cast<const R0 *>(net.w[0]);
+
+    // Descriptor prefetch: the variant rows of a tile are one contiguous run
+    // of M * 64 bytes, copied straight into LDS by direct-to-LDS loads (lane
+    // l of a wave writes 16 bytes at the wave's base + 16 l); no registers
+    // hold them. The next tile's copy is issued after the last layer's
+    // matrix loop; nothing waited on before the next input stage is a vector
+    // load issued after it (the output weights are read from LDS), so it
+    // completes behind the last epilogue and the output stage.
+    auto issue_vdesc = [&](int64_t t) {
+        const int64_t r0 = t * M;
+        for (int c0 = wave * 64; c0 < M * 4; c0 += C::THREADS) {
+            const int c = c0 + lane;
+            if (r0 + c / 4 < n)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(args.vdesc + r0 * VD + 2 * c),
+                    (__attribute__((address_space(3))) void *)(vst + (size_t)c0 * 16), 16, 0, 0);
+        }
+    };
+    if constexpr (VPF) {
+        for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = net.head_w[i];
+        if ((int64_t)blockIdx.x < ntiles) issue_vdesc(blockIdx.x);
+    }
+
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
+        if constexpr (VPF) __builtin_amdgcn_s_waitcnt(0);  // this tile's rows are in LDS
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
-        // ---- input stage: PARTS threads per row. Each reads the row's
-        // descriptors (the repeated reads are cache hits), forms the row's
-        // integer features in registers, and standardizes its own FPP of
-        // them into the input tile in the first layer's precision.
-        {
-            const int r = tid % M, part = tid / M;
-            const int64_t row = row0 + r;
-            const bool inrow = row < n;
-            uint64_t fsel[C::FPP];
-            bool ok = inrow;
-            if constexpr (SRC == SRC_DESC) {
-                Feat f;
-                int kid = -1;
-                if (inrow) {
-                    ok = featurize_one(args.kdesc, args.vdesc + row * VD, args.n_k, f);
-                    const int64_t k = args.vdesc[row * VD];
-                    kid = (int)k;  // in [0, n_k) when ok, and n_k < 2^31
-                    if (SINK == SINK_RANK && ok)  // the variant must sit in its kernel's segment
-                        ok = args.offsets[k] <= row && row < args.offsets[k + 1];
-                } else {
-#pragma unroll
-                    for (int j = 0; j < NFEAT; ++j) f.f[j] = 0;
-                }
-                // this thread's FPP features (part is not a compile-time value)
-#pragma unroll
-                for (int q = 0; q < C::FPP; ++q) fsel[q] = 0;
-#pragma unroll
-                for (int j = 0; j < NFEAT; ++j)
-                    if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
-                if (part == 0) {
-                    meta_ok[r] = ok ? 1 : 0;
-                    meta_kid[r] = kid;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < C::FPP; ++q)
-                    fsel[q] = inrow ? (uint64_t)args.feat[row * NFEAT + part * C::FPP + q] : 0;
-                if (part == 0) {
-                    meta_ok[r] = inrow ? 1 : 0;
-                    meta_kid[r] = -1;
-                }
-            }
-            unsigned char *xr = xin + (size_t)r * C::XS + part * C::FPP * G0::EB;
-#pragma unroll
-            for (int q = 0; q < C::FPP; ++q) {
-                const int j = part * C::FPP + q;
-                const float x = ok ? zscore_fast((int64_t)fsel[q], net.mu[j], net.sigma[j]) : 0.0f;
-                if constexpr (P0 == PREC_FP32)
-                    reinterpret_cast<float *>(xr)[q] = x;
-                else
-                    reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
-                if constexpr (SINK == SINK_TRAIN)
-                    save_elem<P0>(args.save_x, (int64_t)j * args.save_ld + row, inrow ? x : 0.0f);
-            }
-        }
+        tile_input<C, P, M, SRC, SINK>(args, row0, tid, xin, meta_ok, meta_kid, vst);
+        // the first layer's weights, requested before the barrier (not across
+        // the input stage, whose registers are at their peak)
+        if constexpr (XPF) ring_load<P0, 32, C::NBP>(w0, nb0, lane, ring0);
         __syncthreads();
 
         // ---- layer 0 (32 inputs), then hidden layers 1..n_hidden-1. Each wave
@@ -453,14 +654,34 @@ mlp_tiles_kernel(TileArgs args)
                 const int nbp0 = nb0 + ps * C::NBP;
                 const bool final_pass = ps + 1 == C::NSPLIT;
                 v16f acc[C::NBP][C::MBW];
+                const RH *wl = reinterpret_cast<const RH *>(net.w[l]);
+                if constexpr (!XPF) {
+                    if (l == 0)
+                        ring_load<P0, 32, C::NBP>(w0, nbp0, lane, ring0);
+                    else
+                        ring_load<P, W, C::NBP>(wl, nbp0, lane, ringh);
+                }
                 if (l == 0)
-                    layer_mma<P0, 32, C::NBP, C::MBW>(
-                        reinterpret_cast<const typename G0::Vec *>(net.w[0]), xin, C::XS, nbp0,
-                        mb0, lane, acc, bias);
+                    layer_mma<P0, 32, C::NBP, C::MBW>(w0, xin, C::XS, nbp0, mb0, lane, acc, bias,
+                                                      ring0);
                 else
-                    layer_mma<P, W, C::NBP, C::MBW>(
-                        reinterpret_cast<const typename G::Vec *>(net.w[l]), act, C::AS, nbp0,
-                        mb0, lane, acc, scaled ? nullptr : bias);
+                    layer_mma<P, W, C::NBP, C::MBW>(wl, act, C::AS, nbp0, mb0, lane, acc,
+                                                    scaled ? nullptr : bias, ringh);
+                // request the next call's first weight groups before the epilogue
+                if (!XPF) {
+                } else if (!final_pass) {
+                    if (l == 0)
+                        ring_load<P0, 32, C::NBP>(w0, nbp0 + C::NBP, lane, ring0);
+                    else
+                        ring_load<P, W, C::NBP>(wl, nbp0 + C::NBP, lane, ringh);
+                } else if (!last) {
+                    ring_load<P, W, C::NBP>(reinterpret_cast<const RH *>(net.w[l + 1]), nb0, lane,
+                                            ringh);
+                }
+                if constexpr (VPF) {
+                    if (final_pass && last && tile + gridDim.x < ntiles) issue_vdesc(tile + gridDim.x);
+                }
+                __builtin_amdgcn_sched_barrier(0);
                 // training keeps the last hidden layer's outputs too (copied out below)
                 constexpr bool keep_last = SINK == SINK_TRAIN;
                 if (final_pass && (!last || keep_last)) {
@@ -488,7 +709,9 @@ mlp_tiles_kernel(TileArgs args)
                     for (int g = 0; g < 4; ++g) {
                         const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
                         if (scaled) bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
-                        if (last) hw_r[g] = *reinterpret_cast<const v4f *>(net.head_w + nn);
+                        if (last)
+                            hw_r[g] = VPF ? *reinterpret_cast<const v4f *>(hw_lds + nn)
+                                          : *reinterpret_cast<const v4f *>(net.head_w + nn);
                     }
 #pragma unroll
                     for (int j = 0; j < C::MBW; ++j) {
@@ -538,49 +761,188 @@ mlp_tiles_kernel(TileArgs args)
             }
         }
         __syncthreads();
-        // ---- output stage: one thread per row (whole waves, for the shuffles)
-        if (wave < (M + 63) / 64) {
-            const bool inrow = tid < M;
-            const int64_t row = row0 + tid;
-            float p = net.head_b[0];
-            if (inrow) {
+        tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid);
+    }
+}
+
+// Ping-pong schedule of the same pipeline: each wave's rows are split into
+// two halves A and B, and every phase runs the matrix loop of one half while
+// the epilogue (bias already in the accumulators, ReLU, down-cast, LDS store
+// or output-layer dot) of the other half runs beside it:
+//   k(0,A) | k(0,B) e(0,A) || k(1,A) e(0,B) || k(1,B) e(1,A) || ... e(L-1,B)
+// ("||" a barrier). An epilogue writes rows whose input the other phase's
+// matrix loop is not reading, so one barrier per phase suffices, and the two
+// waves sharing a SIMD take the two halves of a phase in opposite order, so
+// one's epilogue runs while the other's multiplies occupy the matrix core.
+// The weights are streamed once per half. Results are bit-identical to
+// mlp_tiles_kernel with the same wave count (same per-element arithmetic and
+// summation order).
+template <int P, int W, int M, int NWAVES, int SRC, int SINK>
+__global__ __launch_bounds__(NWAVES * 64)
+__attribute__((amdgpu_waves_per_eu(tile_waves_per_simd<P, W, M, NWAVES>()))) void
+mlp_pp_kernel(TileArgs args)
+{
+    static_assert(SINK != SINK_TRAIN, "the training forward uses mlp_tiles_kernel");
+    constexpr bool VPF = SRC == SRC_DESC && tile_vdesc_prefetch<P, W, M, NWAVES>();
+    using C = TileCfg<P, W, M, NWAVES, 1, VPF>;
+    using G = typename C::G;
+    static_assert(C::MBW % 2 == 0, "each wave's rows split into two halves");
+    constexpr int MH = C::MBW / 2;
+    constexpr int NBW = C::NBW;
+    constexpr int P0 = FirstP<P>::value;
+    using G0 = Geo<P0>;
+    using R0 = typename G0::Vec;
+    using RH = typename G::Vec;
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *xin = lds;                                   // [M][XS]
+    unsigned char *act = xin + (size_t)M * C::XS;               // [M][AS]
+    float *hpart = reinterpret_cast<float *>(act + C::ACT_BYTES);       // [WN][M]
+    int *meta_ok = reinterpret_cast<int *>(hpart + C::WN * M);  // [M]
+    int *meta_kid = meta_ok + M;                                // [M]
+    unsigned char *vst = lds + C::LDS_BASE;                     // [M][64 B] (VPF)
+    float *hw_lds = reinterpret_cast<float *>(vst + C::VST_BYTES);  // [W] (VPF)
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wn = wave % C::WN, wm = wave / C::WN;
+    const int nb0 = wn * NBW, mb0 = wm * C::MBW;
+    const int half = lane >> 5, col = lane & 31;
+    const NetView &net = args.net;
+    const int64_t n = args.n_rows;
+    const int64_t ntiles = (n + M - 1) / M;
+    // waves w and w + 4 share a SIMD: they take each phase's halves in
+    // opposite order
+    const bool mma_first = ((wave >> 2) & 1) == 0;
+    const R0 *w0 = reinterpret_cast<const R0 *>(net.w[0]);
+
+    auto issue_vdesc = [&](int64_t t) {
+        const int64_t r0 = t * M;
+        for (int c0 = wave * 64; c0 < M * 4; c0 += C::THREADS) {
+            const int c = c0 + lane;
+            if (r0 + c / 4 < n)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(args.vdesc + r0 * VD + 2 * c),
+                    (__attribute__((address_space(3))) void *)(vst + (size_t)c0 * 16), 16, 0, 0);
+        }
+    };
+    if constexpr (VPF) {
+        for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = net.head_w[i];
+        if ((int64_t)blockIdx.x < ntiles) issue_vdesc(blockIdx.x);
+    }
+
+    // matrix loop of layer l over m-blocks mb .. mb + MH - 1
+    auto mma_half = [&](int l, int mb, v16f (&acc)[NBW][MH]) {
+        if (l == 0) {
+            R0 ring[ring_depth<P0, 32>()][NBW];
+            ring_load<P0, 32, NBW>(w0, nb0, lane, ring);
+            layer_mma<P0, 32, NBW, MH>(w0, xin, C::XS, nb0, mb, lane, acc, net.b[0], ring);
+        } else {
+            const RH *wl = reinterpret_cast<const RH *>(net.w[l]);
+            RH ring[ring_depth<P, W>()][NBW];
+            ring_load<P, W, NBW>(wl, nb0, lane, ring);
+            const bool scaled = P == PREC_FP8;
+            layer_mma<P, W, NBW, MH>(wl, act, C::AS, nb0, mb, lane, acc,
+                                     scaled ? nullptr : net.b[l], ring);
+        }
+    };
+    // epilogue of layer l over m-blocks mb .. mb + MH - 1: next activations
+    // to LDS, or for the last layer the output-layer partial dot into srow
+    auto epi_half = [&](int l, int mb, v16f (&acc)[NBW][MH], float (&srow)[MH]) {
+        const bool last = l + 1 == net.n_hidden;
+        const bool scaled = P == PREC_FP8 && l > 0;
+        const float qs = scaled ? net.qscale[l] : 1.0f;
+        const float qinv = net.qinv[l];
+        const float *bias = net.b[l];
 #pragma unroll
-                for (int q = 0; q < C::WN; ++q) p += hpart[q * M + tid];
+        for (int i = 0; i < NBW; ++i) {
+            v4f bias_r[4], hw_r[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                if (scaled) bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
+                if (last)
+                    hw_r[g] = VPF ? *reinterpret_cast<const v4f *>(hw_lds + nn)
+                                  : *reinterpret_cast<const v4f *>(net.head_w + nn);
             }
-            const bool ok = inrow && meta_ok[tid] != 0;
-            if constexpr (SINK == SINK_PRED || SINK == SINK_TRAIN) {
-                if (inrow && row < n) args.pred[row] = p;
-            } else {
-                if (inrow && row < n && args.pred) args.pred[row] = ok ? p : __builtin_nanf("");
-                const bool take = ok && !__builtin_isnan(p);
-                uint64_t key = ~0ull;
-                if (take) {
-                    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
-                    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-                    key = ((uint64_t)u << 32) | (uint32_t)row;
-                }
-                // segmented min over runs of equal kernel id within the wave
-                // (inclusive scan with segment-head flags), then one atomic
-                // per run from its last lane
-                const int kid = take ? meta_kid[tid] : -1;
-                const int prev = __shfl_up(kid, 1, 64);
-                int head = (lane == 0) || (prev != kid);
 #pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint64_t kup = __shfl_up(key, off, 64);
-                    const int hup = __shfl_up(head, off, 64);
-                    if (lane >= off && !head) {
-                        key = kup < key ? kup : key;
-                        head = hup;
+            for (int j = 0; j < MH; ++j) {
+                const int m = (mb + j) * 32 + col;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
+                    v4f v;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
+                                               : acc[i][j][4 * g + e];
+                        v[e] = z > 0.0f ? z : 0.0f;
+                    }
+                    if (last) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) srow[j] += v[e] * hw_r[g][e];
+                    } else {
+                        store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
                     }
                 }
-                const int next = __shfl_down(kid, 1, 64);
-                const bool last = (lane == 63) || (next != kid);
-                if (last && kid >= 0 && kid < args.n_k && key != ~0ull)
-                    atomicMin(reinterpret_cast<unsigned long long *>(args.keys + kid),
-                              (unsigned long long)key);
             }
         }
+    };
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row0 = tile * M;
+        if constexpr (VPF) __builtin_amdgcn_s_waitcnt(0);  // this tile's rows are in LDS
+        __syncthreads();  // previous tile's readers of xin / meta / hpart are done
+        tile_input<C, P, M, SRC, SINK>(args, row0, tid, xin, meta_ok, meta_kid, vst);
+        __syncthreads();
+
+        const int mbA = mb0, mbB = mb0 + MH;
+        v16f accA[NBW][MH], accB[NBW][MH];
+        float srowA[MH], srowB[MH];
+#pragma unroll
+        for (int j = 0; j < MH; ++j) {
+            srowA[j] = 0.0f;
+            srowB[j] = 0.0f;
+        }
+        const int L = net.n_hidden;
+        mma_half(0, mbA, accA);
+        for (int l = 0; l < L; ++l) {
+            const bool last = l + 1 == L;
+            // k(l,B) beside e(l,A); e(l,A) overwrites rows A, whose input
+            // k(l,A) finished reading before the last barrier
+            if (mma_first) {
+                mma_half(l, mbB, accB);
+                epi_half(l, mbA, accA, srowA);
+            } else {
+                epi_half(l, mbA, accA, srowA);
+                mma_half(l, mbB, accB);
+            }
+            if constexpr (VPF) {
+                if (last && tile + gridDim.x < ntiles) issue_vdesc(tile + gridDim.x);
+            }
+            if (last) break;
+            __syncthreads();  // rows A of layer l are complete
+            // k(l+1,A) beside e(l,B)
+            if (mma_first) {
+                mma_half(l + 1, mbA, accA);
+                epi_half(l, mbB, accB, srowB);
+            } else {
+                epi_half(l, mbB, accB, srowB);
+                mma_half(l + 1, mbA, accA);
+            }
+            __syncthreads();  // rows B of layer l are complete; k(l+1,A) is done with rows A
+        }
+        epi_half(L - 1, mbB, accB, srowB);
+#pragma unroll
+        for (int j = 0; j < MH; ++j) {
+            float sa = srowA[j], sb = srowB[j];
+            sa += __shfl_xor(sa, 32, 64);  // the two lane halves hold different neurons
+            sb += __shfl_xor(sb, 32, 64);
+            if (half == 0) {
+                hpart[wn * M + (mbA + j) * 32 + col] = sa;
+                hpart[wn * M + (mbB + j) * 32 + col] = sb;
+            }
+        }
+        __syncthreads();
+        tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid);
     }
 }
 

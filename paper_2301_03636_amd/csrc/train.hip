@@ -61,6 +61,8 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     using G = typename C::G;
     using T = typename CT<P>::T;
     constexpr int CE = 16 / (int)sizeof(T);  // elements per 16-byte run
+    constexpr int RG = M / CE;                // row groups of a tile
+    static_assert(RG % 8 == 0, "row groups come in eights");
     typedef int v4i_ __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *act = lds;  // [M][AS]
@@ -77,26 +79,30 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
         __syncthreads();
-        // seed: gradient at the last hidden layer's pre-activation; one thread
-        // per 16-byte run of neurons of one row (lanes take consecutive rows)
+        // seed: gradient at the last hidden layer's pre-activation. A thread
+        // takes one neuron of CE consecutive rows (one 16-byte vector of the
+        // transposed layouts); eight consecutive threads take eight
+        // consecutive row groups of one neuron (one 128-byte line)
         {
             const T *Hl = H + (int64_t)(L - 1) * W * ld;
             T *Gl = GT + (int64_t)(L - 1) * W * ld;
-            for (int c = tid; c < M * (W / CE); c += C::THREADS) {
-                const int m = c % M, nc = c / M;
-                const int64_t row = row0 + m;
-                const float d = row < n ? a.dy[row] : 0.0f;
-                v4i_ raw;
-                T *vals = reinterpret_cast<T *>(&raw);
+            for (int c = tid; c < W * RG; c += C::THREADS) {
+                const int t = c >> 3, j = t % W, m0 = ((t / W) * 8 + (c & 7)) * CE;
+                const int64_t r0 = row0 + m0;
+                const v4i_ hraw = *reinterpret_cast<const v4i_ *>(Hl + (int64_t)j * ld + r0);
+                const T *hv = reinterpret_cast<const T *>(&hraw);
+                const float hw = a.head_w[j];
+                v4i_ graw;
+                T *gv = reinterpret_cast<T *>(&graw);
 #pragma unroll
                 for (int e = 0; e < CE; ++e) {
-                    const int j = nc * CE + e;
-                    const float h = (float)Hl[(int64_t)j * ld + row];
-                    const T g = (T)(h > 0.0f ? d * a.head_w[j] : 0.0f);
-                    vals[e] = g;
-                    Gl[(int64_t)j * ld + row] = g;
+                    const int64_t row = r0 + e;
+                    const float d = row < n ? a.dy[row] : 0.0f;
+                    const T g = (T)((float)hv[e] > 0.0f ? d * hw : 0.0f);
+                    gv[e] = g;
+                    *reinterpret_cast<T *>(act + (size_t)(m0 + e) * C::AS + j * sizeof(T)) = g;
                 }
-                *reinterpret_cast<v4i_ *>(act + (size_t)m * C::AS + nc * 16) = raw;
+                *reinterpret_cast<v4i_ *>(Gl + (int64_t)j * ld + r0) = graw;
             }
         }
         __syncthreads();
@@ -122,23 +128,25 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
                 }
             __syncthreads();
             // ... then the ReLU mask of h_{l-1}, written back for the next
-            // layer and out, transposed, for the weight gradients
+            // layer and out, transposed, for the weight gradients (the same
+            // thread mapping as the seed)
             const T *Hp = H + (int64_t)(l - 1) * W * ld;
             T *Gp = GT + (int64_t)(l - 1) * W * ld;
-            for (int c = tid; c < M * (W / CE); c += C::THREADS) {
-                const int m = c % M, nc = c / M;
-                const int64_t row = row0 + m;
-                v4i_ raw = *reinterpret_cast<const v4i_ *>(act + (size_t)m * C::AS + nc * 16);
-                T *vals = reinterpret_cast<T *>(&raw);
+            for (int c = tid; c < W * RG; c += C::THREADS) {
+                const int t = c >> 3, k = t % W, m0 = ((t / W) * 8 + (c & 7)) * CE;
+                const int64_t r0 = row0 + m0;
+                const v4i_ hraw = *reinterpret_cast<const v4i_ *>(Hp + (int64_t)k * ld + r0);
+                const T *hv = reinterpret_cast<const T *>(&hraw);
+                v4i_ graw;
+                T *gv = reinterpret_cast<T *>(&graw);
 #pragma unroll
                 for (int e = 0; e < CE; ++e) {
-                    const int k = nc * CE + e;
-                    const float h = (float)Hp[(int64_t)k * ld + row];
-                    const T g = h > 0.0f ? vals[e] : (T)0.0f;
-                    vals[e] = g;
-                    Gp[(int64_t)k * ld + row] = g;
+                    T *cell = reinterpret_cast<T *>(act + (size_t)(m0 + e) * C::AS + k * sizeof(T));
+                    const T g = (float)hv[e] > 0.0f ? *cell : (T)0.0f;
+                    gv[e] = g;
+                    if (l > 1) *cell = g;
                 }
-                if (l > 1) *reinterpret_cast<v4i_ *>(act + (size_t)m * C::AS + nc * 16) = raw;
+                *reinterpret_cast<v4i_ *>(Gp + (int64_t)k * ld + r0) = graw;
             }
             __syncthreads();
         }
@@ -150,19 +158,32 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
 // the batch contiguous), split over the batch into `splits` chunks whose fp32
 // partial tiles are summed in a fixed order by wgrad_reduce_kernel. A
 // workgroup of 4 waves owns a 128 x 128 output tile, each wave 64 x 64.
+//
+// The batch is consumed in chunks of CH = 8 KV rows. Within a chunk, lane
+// half h holds batch rows h * 4 KV + v * KV + e of its operand row for the
+// matrix-core step v = 0..3 (both operands use the same assignment, which is
+// all the dot product needs), so each lane reads 4 KV contiguous elements
+// (64 bytes) of a row per chunk and the two halves cover its 128-byte line:
+// every line is fetched once, in one burst. Chunks are double-buffered in
+// registers. The waves of the first k-tile also sum their g^T rows, the bias
+// gradient's partials (one per split, reduced in the same fixed order).
 template <int P>
 __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__restrict__ A, int na,
                                                     const typename CT<P>::T *__restrict__ B, int nb,
                                                     int64_t ld, int64_t kchunk,
-                                                    float *__restrict__ partial)
+                                                    float *__restrict__ partial,
+                                                    float *__restrict__ partial_b)
 {
     using G = Geo<P>;
     using V = typename G::Vec;
+    using T = typename CT<P>::T;
+    constexpr int KV = G::KV, CH = 8 * KV;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, col = lane & 31;
     const int n0 = blockIdx.x * 128 + (wave & 1) * 64;   // rows of A (outputs)
     const int k0 = blockIdx.y * 128 + (wave >> 1) * 64;  // rows of B (inputs)
     const int64_t b0 = (int64_t)blockIdx.z * kchunk;
+    const bool bias_sums = blockIdx.y == 0 && (wave >> 1) == 0;
     bool va[2], vb[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -174,31 +195,59 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v16f{0};
-    const typename CT<P>::T *ap[2], *bp[2];
+    float rsum[2] = {0.0f, 0.0f};
+    const T *ap[2], *bp[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        ap[i] = A + (int64_t)(n0 + 32 * i + col) * ld + b0 + half * G::KV;
-        bp[i] = B + (int64_t)(k0 + 32 * i + col) * ld + b0 + half * G::KV;
+        // rows past na / nb are never dereferenced (va / vb); point them at row 0
+        ap[i] = A + (int64_t)(va[i] ? n0 + 32 * i + col : 0) * ld + b0 + half * 4 * KV;
+        bp[i] = B + (int64_t)(vb[i] ? k0 + 32 * i + col : 0) * ld + b0 + half * 4 * KV;
     }
-    for (int64_t kb = 0; kb < kchunk; kb += G::KG) {
-        V x[2], y[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            x[i] = va[i] ? *reinterpret_cast<const V *>(ap[i] + kb) : V{0};
-            y[i] = vb[i] ? *reinterpret_cast<const V *>(bp[i] + kb) : V{0};
-        }
+    auto load = [&](int64_t c, V (&x)[2][4], V (&y)[2][4]) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                if (!(va[i] && vb[j])) continue;
-                if constexpr (P == PREC_FP32) {
-#pragma unroll
-                    for (int t = 0; t < G::KV; ++t) acc[i][j] = mma(x[i][t], y[j][t], acc[i][j]);
-                } else {
-                    acc[i][j] = mma(x[i], y[j], acc[i][j]);
-                }
+            for (int v = 0; v < 4; ++v) {
+                x[i][v] = va[i] ? *reinterpret_cast<const V *>(ap[i] + c * CH + v * KV) : V{0};
+                y[i][v] = vb[i] ? *reinterpret_cast<const V *>(bp[i] + c * CH + v * KV) : V{0};
             }
+    };
+    auto compute = [&](const V (&x)[2][4], const V (&y)[2][4]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (!(va[i] && vb[j])) continue;
+                    if constexpr (P == PREC_FP32) {
+#pragma unroll
+                        for (int t = 0; t < KV; ++t) acc[i][j] = mma(x[i][v][t], y[j][v][t], acc[i][j]);
+                    } else {
+                        acc[i][j] = mma(x[i][v], y[j][v], acc[i][j]);
+                    }
+                }
+        if (bias_sums) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int e = 0; e < KV; ++e) rsum[i] += (float)x[i][v][e];
+        }
+    };
+    const int64_t chunks = kchunk / CH;
+    V xa[2][4], ya[2][4], xb[2][4], yb[2][4];
+    load(0, xa, ya);
+    for (int64_t c = 0; c < chunks; c += 2) {
+        if (c + 1 < chunks) load(c + 1, xb, yb);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(xa, ya);
+        if (c + 1 < chunks) {
+            if (c + 2 < chunks) load(c + 2, xa, ya);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(xb, yb);
+        }
     }
     // D[n][k]: lane holds column k = col, rows n = 8*(r/4) + 4*half + r%4
     float *out = partial + (int64_t)blockIdx.z * na * nb;
@@ -214,17 +263,32 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
                 out[(int64_t)nn * nb + kk] = acc[i][j][r];
             }
         }
+    if (bias_sums) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const float t = rsum[i] + __shfl_xor(rsum[i], 32, 64);  // the two batch halves
+            if (half == 0 && va[i]) partial_b[(int64_t)blockIdx.z * na + n0 + 32 * i + col] = t;
+        }
+    }
 }
 
-// grads[off + n * in + k] = sum over splits of partial[s][n][k], n < out, k < in
-__global__ void wgrad_reduce_kernel(const float *__restrict__ partial, int splits, int na, int nb,
-                                    int out, int in, float *__restrict__ grads)
+// grads[off + n * in + k] = sum over splits of partial[s][n][k] (n < out,
+// k < in), then grads[off + out * in + n] = sum over splits of partial_b[s][n]
+__global__ void wgrad_reduce_kernel(const float *__restrict__ partial,
+                                    const float *__restrict__ partial_b, int splits, int na,
+                                    int nb, int out, int in, float *__restrict__ grads)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)out * in) return;
-    const int nn = (int)(idx / in), kk = (int)(idx % in);
+    const int64_t nw = (int64_t)out * in;
+    if (idx >= nw + out) return;
     float s = 0.0f;
-    for (int q = 0; q < splits; ++q) s += partial[((int64_t)q * na + nn) * nb + kk];
+    if (idx < nw) {
+        const int nn = (int)(idx / in), kk = (int)(idx % in);
+        for (int q = 0; q < splits; ++q) s += partial[((int64_t)q * na + nn) * nb + kk];
+    } else {
+        const int nn = (int)(idx - nw);
+        for (int q = 0; q < splits; ++q) s += partial_b[(int64_t)q * na + nn];
+    }
     grads[idx] = s;
 }
 
@@ -371,13 +435,15 @@ static size_t elem_bytes(const advisor_model *m) { return m->precision == PREC_F
 
 static int64_t ld_for(int64_t n) { return ((n + 255) / 256) * 256; }
 
-// Batch splits of the weight-gradient product: enough workgroups to fill the
-// chip, each chunk a multiple of 64 rows (ld is a multiple of 256).
+// Batch splits of the weight-gradient product: about three workgroups per
+// CU (their waves hide each other's load latency), each chunk a multiple of
+// 64 rows (ld is a multiple of 256, so a chunk holds a multiple of WG_PF
+// k-groups of 16 bf16 or 8 fp32 rows).
 static int splits_for(int na, int nb, int64_t ld)
 {
     const int tiles = ((na + 127) / 128) * ((nb + 127) / 128);
     int s = 1;
-    while (tiles * s < 256 && s < 64) s *= 2;
+    while (tiles * s < 3 * device_cus() && s < 64) s *= 2;
     while (s > 1 && (ld / 64) % s != 0) s /= 2;
     return s;
 }
@@ -422,7 +488,8 @@ static int ensure_ws(advisor_model *m, int64_t n, bool with_saved)
             pf = std::max(pf, (size_t)64 * na * nb);
         }
         w->partial_floats = pf;
-        ADV_HIP(hipMalloc(&w->partial, sizeof(float) * pf));
+        // weight partials, then 64 splits x tile width bias partials
+        ADV_HIP(hipMalloc(&w->partial, sizeof(float) * (pf + (size_t)64 * tw)));
     }
     const int64_t ld = ld_for(n);
     if (ld > w->ld || (with_saved && !w->saved)) {
@@ -563,29 +630,25 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         const unsigned char *Ab = reinterpret_cast<const unsigned char *>(w->gt) + (size_t)l * tw * ld * eb;
         const unsigned char *Bb = l == 0 ? xs : hs + (size_t)(l - 1) * tw * ld * eb;
         dim3 grid((na + 127) / 128, (nb + 127) / 128, splits);
+        float *partial_b = w->partial + w->partial_floats;
         if (m->precision == PREC_FP32)
             hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, grid, dim3(256), 0, s,
                                reinterpret_cast<const float *>(Ab), na,
-                               reinterpret_cast<const float *>(Bb), nb, ld, kchunk, w->partial);
+                               reinterpret_cast<const float *>(Bb), nb, ld, kchunk, w->partial,
+                               partial_b);
         else
             hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, grid, dim3(256), 0, s,
                                reinterpret_cast<const __bf16 *>(Ab), na,
-                               reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, w->partial);
+                               reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, w->partial,
+                               partial_b);
         ADV_LAUNCHED("wgrad_kernel");
+        // weights then biases of the layer (the bias gradient is the sum of
+        // g^T's rows over the batch; rows past n are zero)
         float *gw = grads + m->layer_off[l];
-        const int64_t ne = (int64_t)out * in;
+        const int64_t ne = (int64_t)out * in + out;
         hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
-                           w->partial, splits, na, nb, out, in, gw);
-        float *gb = gw + ne;
-        if (m->precision == PREC_FP32)
-            hipLaunchKernelGGL(rowdot_kernel<float>, dim3(out), dim3(RS_THREADS), 0, s,
-                               reinterpret_cast<const float *>(Ab), ld, out, n,
-                               (const float *)nullptr, gb);
-        else
-            hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3(out), dim3(RS_THREADS), 0, s,
-                               reinterpret_cast<const __bf16 *>(Ab), ld, out, n,
-                               (const float *)nullptr, gb);
-        ADV_LAUNCHED("wgrad reduce / bias gradient");
+                           w->partial, partial_b, splits, na, nb, out, in, gw);
+        ADV_LAUNCHED("wgrad_reduce_kernel");
     }
     return ADVISOR_OK;
 }

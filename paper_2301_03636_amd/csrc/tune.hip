@@ -17,7 +17,7 @@
 
 namespace adv {
 
-constexpr int N_SHAPES = 3;  // tile shapes per (precision, width), see mlp.hip
+constexpr int N_SHAPES = 4;  // tile shapes per (precision, width), see mlp.hip
 
 static std::mutex g_tune_mu;
 

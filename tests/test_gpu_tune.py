@@ -1,7 +1,7 @@
 """Tile-shape autotuner: picks a built shape, records it in the cache file, a
 new model of the same shape reads it back, and shapes with the same wave
-count give bit-identical predictions (the four-wave shape differs only in the
-order of the output layer's fp32 sum)."""
+count give bit-identical predictions, including the ping-pong schedule (the
+four-wave shape differs only in the order of the output layer's fp32 sum)."""
 import json
 import os
 
@@ -29,18 +29,20 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch, precision, widths):
     m.set_params(p, mu, sd)
     K, V, O = to_dev(kd), to_dev(vd), to_dev(off)
     preds = {}
-    for v in (0, 1, 2):
+    for v in (0, 1, 2, 3):
         adv.advisor_model_set_tile_variant(m.handle, v)
         preds[v] = host(m.predict(to_dev(f)))
         b = host(m.rank(K, V, O))
         assert b.tolist() == segment_argmin(np.where(inv == 1, np.nan, preds[v]), off).tolist()
-    # same wave count: the same bits whatever the rows per tile
+    # same wave count: the same bits whatever the rows per tile or the
+    # schedule (shape 3 is the ping-pong schedule of shape 0)
     assert np.array_equal(preds[0].view(np.int32), preds[1].view(np.int32))
+    assert np.array_equal(preds[0].view(np.int32), preds[3].view(np.int32))
     assert np.max(np.abs(preds[2] - preds[0]) / np.maximum(np.abs(preds[0]), 1.0)) <= 1e-5
     chosen, times = adv.advisor_autotune(m.handle, K, V, O, reps=3)
-    say("autotune %s %s: chose %d, times %s" % (precision, widths, chosen, times[:3]))
-    assert chosen in (0, 1, 2) and times[chosen] > 0
-    assert times[chosen] == min(t for t in times[:3] if t > 0)
+    say("autotune %s %s: chose %d, times %s" % (precision, widths, chosen, times[:4]))
+    assert chosen in (0, 1, 2, 3) and times[chosen] > 0
+    assert times[chosen] == min(t for t in times[:4] if t > 0)
     assert adv.advisor_model_get_tile_variant(m.handle) == chosen
     text = cache.read_text()
     entries = json.loads(text)
