@@ -61,10 +61,10 @@ def roofline_peak(widths, precision):
 
 
 def kernel_source_hash():
-    """Hash of the sources the fused tile kernel is built from; a stored
-    traffic measurement only applies to the kernel it was taken on."""
+    """Hash of the sources of the fused tile kernel and its launch shapes; a
+    stored traffic measurement only applies to the kernel it was taken on."""
     h = hashlib.sha256()
-    for f in ("mlp_tile.h", "features.h", "mlp.hip", "internal.h"):
+    for f in ("mlp_tile.h", "features.h", "mlp.hip"):
         with open(os.path.join(ROOT, "paper_2301_03636_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -157,7 +157,8 @@ def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds, gpu_best_by_p
     }, agree, per_variant
 
 
-def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_variant, seconds):
+def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_variant, seconds,
+                      refine_k):
     """Argmin agreement with the oracle for a network trained by the
     library's own training step on the synthetic runtime model (the targets
     of the gain test), which is what a user of the method ranks with. A
@@ -196,22 +197,37 @@ def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_varian
     K, V, O = to_dev(kd[ks]), to_dev(vsub), to_dev(sub_off)
     agree, regret = {}, {}
     has = best_cpu >= 0
+    hi = adv.Model(widths, "fp32")
+    hi.set_params(w, mu, sd)
     for p in precs:
         g = adv.Model(widths, p)
         g.set_params(w, mu, sd)
         if p == "fp8":
             g.calibrate_fp8(F)
-        best_gpu = g.rank(K, V, O).cpu().numpy()
+        picks = {p: g.rank(K, V, O).cpu().numpy()}
+        rk = refine_k_for(p, refine_k)
+        if p != "fp32" and rk > 0:
+            picks[p + "_refined"] = g.rank_refined(hi, K, V, O, top_k=rk).cpu().numpy()
         g.close()
-        agree[p] = float(np.mean(best_gpu == best_cpu))
-        # how much worse the GPU's pick is by the oracle's own prediction
-        # (ln us): a disagreement between near-tied variants costs ~0
-        gap = pred_cpu[best_gpu[has]] - pred_cpu[best_cpu[has]]
-        regret[p] = {"mean": float(gap.mean()), "max": float(gap.max()),
-                     "frac_below_0.01": float(np.mean(gap < 0.01))}
+        for name, best_gpu in picks.items():
+            agree[name] = float(np.mean(best_gpu == best_cpu))
+            # how much worse the GPU's pick is by the oracle's own prediction
+            # (ln us): a disagreement between near-tied variants costs ~0
+            gap = pred_cpu[best_gpu[has]] - pred_cpu[best_cpu[has]]
+            regret[name] = {"mean": float(gap.mean()), "max": float(gap.max()),
+                            "frac_below_0.01": float(np.mean(gap < 0.01))}
+    hi.close()
     return agree, {"train_steps": 400, "batch": 8192, "final_loss": final_loss,
                    "sample_kernels": int(ks.size), "sample_variants": int(rws.size),
                    "pick_gap_ln_us_by_oracle_prediction": regret}
+
+
+def refine_k_for(precision, requested):
+    """Candidates per kernel for the fp32 re-ranking: 8 after bf16, 16 after
+    fp8 (fp8's 3-bit mantissas scatter near-tied predictions further)."""
+    if requested is not None:
+        return requested
+    return {"bf16": 8, "fp8": 16}.get(precision, 0)
 
 
 def train_flops_per_sample(widths):
@@ -270,6 +286,10 @@ def main():
     ap.add_argument("--train-steps", type=int, default=20,
                     help="timed training steps (batch 65536, bf16 32-512x4-1); 0 to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--refine-k", type=int, default=None,
+                    help="also time bf16/fp8 ranking refined by an fp32 model on each kernel's "
+                         "top-k candidates (advisor_rank_refined; default 8 for bf16, 16 for "
+                         "fp8); 0 to skip")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the "
                          "HBM byte counters of a profiler run) and exit")
@@ -331,6 +351,24 @@ def main():
                           value=nv / (ms / 1e3),
                           tflops=fl * nv / (kern_ms / 1e3) / 1e12,
                           tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:4]])
+        rk = refine_k_for(p, args.refine_k)
+        if p != "fp32" and rk > 0:
+            # the same ranking with each kernel's top-k re-ranked in fp32 (eager calls)
+            hi = adv.Model(widths, "fp32")
+            hi.set_params(params, mu, sd)
+            bref = torch.empty(nk, dtype=torch.int64, device=d)
+            nsteps = args.steps if p == prec else max(5, args.steps // 2)
+            for _ in range(args.warmup):
+                m.rank_refined(hi, kdd, vdd, offd, top_k=rk, best_out=bref)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                m.rank_refined(hi, kdd, vdd, offd, top_k=rk, best_out=bref)
+            torch.cuda.synchronize()
+            rms = (time.perf_counter() - t0) * 1e3 / nsteps
+            best_by_prec[p + "_refined"] = bref.cpu().numpy()
+            results[p]["refined"] = dict(top_k=rk, ms_per_step=rms, value=nv / (rms / 1e3))
+            hi.close()
         m.close()
     del feat_cal, inv_cal
 
@@ -364,7 +402,7 @@ def main():
         cb, agree, per_variant = cpu_baseline_leg(kd, vd, off, widths, params, mu, sd,
                                                   args.cpu_seconds, best_by_prec)
         agree_t, tinfo = trained_agreement(adv, torch, T, kd, vd, off, widths, list(results),
-                                           per_variant, args.cpu_seconds / 2)
+                                           per_variant, args.cpu_seconds / 2, args.refine_k)
         cb["argmin_agreement_trained_network"] = dict(agree_t, **tinfo)
         out["cpu_baseline"] = cb
     else:
@@ -374,7 +412,10 @@ def main():
             "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
             "tile_shape": r["tile_shape"], "autotune_ms": r["tune_ms"],
             "argmin_agreement_vs_oracle_sample": agree.get(p),
-            "argmin_agreement_trained_network": agree_t.get(p)}
+            "argmin_agreement_trained_network": agree_t.get(p),
+            "refined_by_fp32": None if "refined" not in r else dict(
+                r["refined"], argmin_agreement_vs_oracle_sample=agree.get(p + "_refined"),
+                argmin_agreement_trained_network=agree_t.get(p + "_refined"))}
         for p, r in results.items()}
     if args.train_steps > 0:
         out["train"] = train_leg(adv, torch, d, args.train_steps, args.warmup)

@@ -198,6 +198,28 @@ int advisor_rank(const advisor_model *model, const int64_t *kdesc, const int64_t
                  int64_t *best_out, float *pred_out, void *stream);
 
 /*
+ * Precision-refined ranking (the prediction flow of section 3, N = 1, with
+ * the argmin decided in two precisions). `model` (any precision) ranks every
+ * variant as advisor_rank does; then, per kernel, its top_k variants by
+ * `model`'s predictions (lowest index first on ties; NaN and ineligible
+ * variants never enter) are ranked again by `refine`, and best_out[k]
+ * receives the one `refine` predicts fastest (lowest variant index on ties),
+ * or -1 if the kernel has no eligible variant. When `refine`'s own argmin of
+ * the kernel is among those candidates, the result equals advisor_rank with
+ * `refine`; a bf16 or fp8 first pass with an fp32 `refine` of the same
+ * weights resolves near-ties as fp32 does at the cost of top_k fp32
+ * predictions per kernel. top_k in {1, 2, 4, 8, 16}; n_kernels * 16 < 2^31.
+ * Arguments as for advisor_rank; pred_out (may be NULL) receives `model`'s
+ * predictions. The two models must live on the current device. `model` owns
+ * a workspace that grows on demand (synchronous allocation); calls on one
+ * model must not overlap.
+ */
+int advisor_rank_refined(advisor_model *model, const advisor_model *refine,
+                         const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
+                         int64_t n_kernels, int64_t n_variants, int top_k, int64_t *best_out,
+                         float *pred_out, void *stream);
+
+/*
  * The per-kernel argmin alone (the selection step of section 3, N = 1) on
  * given predictions: pred (device, float [n_variants]), offsets (device,
  * int64 [n_kernels + 1]) -> best_out (device, int64 [n_kernels]), with the
@@ -253,7 +275,7 @@ int advisor_model_load_params(advisor_model *model, const float *w_master, void 
 int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
 
 /*
- * Tile-shape autotuner. The fused kernel is built in up to three tile shapes
+ * Tile-shape autotuner. The fused kernel is built in up to four tile shapes
  * per (precision, width) (rows per tile, waves, passes); advisor_autotune
  * times each on the given ranking workload (2 warm-up calls, then `reps`
  * timed advisor_rank calls on the stream, device buffers as for

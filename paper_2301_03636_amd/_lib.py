@@ -55,6 +55,7 @@ def lib():
             "advisor_predict": ([P, P, i64, P, P], i32),
             "advisor_rank": ([P, P, P, P, i64, i64, P, P, P], i32),
             "advisor_rank_preds": ([P, P, i64, i64, P, P], i32),
+            "advisor_rank_refined": ([P, P, P, P, P, i64, i64, i32, P, P, P], i32),
             "advisor_mlp_saved_bytes": ([P, i64], i64),
             "advisor_mlp_forward": ([P, P, i64, P, P, P], i32),
             "advisor_mlp_backward": ([P, P, P, i64, P, P], i32),
@@ -245,6 +246,22 @@ def advisor_rank(h, kdesc, vdesc, offsets, best_out=None, pred_out=None, want_pr
     _check(lib().advisor_rank(h, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
                               _ptr(best_out), _ptr(pred_out), _stream()), "advisor_rank")
     return (best_out, pred_out) if want_pred or pred_out is not None else best_out
+
+
+def advisor_rank_refined(h, refine, kdesc, vdesc, offsets, top_k=8, best_out=None,
+                         pred_out=None):
+    for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
+        _dev(t, torch.int64, nm)
+    nk = offsets.shape[0] - 1
+    nv = vdesc.shape[0]
+    if best_out is None:
+        best_out = torch.empty(nk, dtype=torch.int64, device=vdesc.device)
+    _dev(best_out, torch.int64, "best_out")
+    _dev(pred_out, torch.float32, "pred_out")
+    _check(lib().advisor_rank_refined(h, refine, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
+                                      int(top_k), _ptr(best_out), _ptr(pred_out), _stream()),
+           "advisor_rank_refined")
+    return best_out
 
 
 def advisor_rank_preds(pred, offsets, best_out=None):

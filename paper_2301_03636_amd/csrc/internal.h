@@ -41,6 +41,7 @@ int device_cus();
 
 // Training workspace release (train.hip).
 void free_train_ws(advisor_model *m);
+void free_refine_ws(advisor_model *m);
 
 // One-time launch set-up (dynamic LDS limits, occupancy) of every kernel a
 // model of this precision and tile width uses, so that later calls can be
@@ -99,6 +100,7 @@ struct advisor_model {
     float qinv[ADVISOR_MAX_LAYERS] = {0};    // fp8: 1 / ascale of the next layer
     bool fp8_calibrated = false;
     void *train_ws = nullptr;  // training workspace (train.hip), grown on demand
+    void *refine_ws = nullptr; // refined-ranking workspace (refine.hip), grown on demand
     int tile_variant = 0;      // tile shape used by rank/predict (autotuned)
     bool wt_valid = false;     // transposed packs (backward) match the master weights
 };

@@ -152,6 +152,7 @@ extern "C" void advisor_model_destroy(advisor_model *m)
     (void)hipSetDevice(m->device);
     (void)hipDeviceSynchronize();
     free_train_ws(m);
+    free_refine_ws(m);
     void *ptrs[] = {m->master, m->adam_m, m->adam_v, m->mu, m->sigma, m->bias, m->head,
                     m->d_layer_off, m->d_widths, m->d_step};
     for (void *p : ptrs)

@@ -49,6 +49,7 @@ struct BwdArgs {
     const void *wt[MAX_LAYERS];
     const void *save_h;     // h_l^T, layer l at l * W * ld
     void *gt;               // g_l^T, layer l at l * W * ld
+    float *head_part;       // [ld / M][M / (8 CE)][W + 1] output-layer gradient partials
     int64_t ld;
     int64_t n;
     int n_hidden;
@@ -94,15 +95,32 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
                 const float hw = a.head_w[j];
                 v4i_ graw;
                 T *gv = reinterpret_cast<T *>(&graw);
+                float sdh = 0.0f, sd = 0.0f;  // output-layer gradient partials
 #pragma unroll
                 for (int e = 0; e < CE; ++e) {
                     const int64_t row = r0 + e;
                     const float d = row < n ? a.dy[row] : 0.0f;
-                    const T g = (T)((float)hv[e] > 0.0f ? d * hw : 0.0f);
+                    const float h = (float)hv[e];
+                    const T g = (T)(h > 0.0f ? d * hw : 0.0f);
                     gv[e] = g;
                     *reinterpret_cast<T *>(act + (size_t)(m0 + e) * C::AS + j * sizeof(T)) = g;
+                    sdh += d * h;
+                    sd += d;
                 }
                 *reinterpret_cast<v4i_ *>(Gl + (int64_t)j * ld + r0) = graw;
+                // sum over the 8 row groups of this line (8 consecutive lanes);
+                // one partial per (tile, line block, neuron), reduced in order
+                // by head_reduce_kernel
+#pragma unroll
+                for (int off = 1; off < 8; off <<= 1) {
+                    sdh += __shfl_xor(sdh, off, 64);
+                    sd += __shfl_xor(sd, off, 64);
+                }
+                if ((c & 7) == 0) {
+                    float *hp = a.head_part + ((int64_t)tile * (RG / 8) + (c >> 3) / W) * (W + 1);
+                    hp[j] = sdh;
+                    if (j == 0) hp[W] = sd;
+                }
             }
         }
         __syncthreads();
@@ -292,40 +310,27 @@ __global__ void wgrad_reduce_kernel(const float *__restrict__ partial,
     grads[idx] = s;
 }
 
-// One workgroup per output row r: out[r] = sum_{b < n} v[r][b] * w[b] (w may
-// be null: plain row sums). Threads stride over 16-byte runs of the row,
-// then a fixed tree in LDS combines them, so the result is deterministic.
-constexpr int RS_THREADS = 256;
-
-template <typename T>
-__global__ __launch_bounds__(RS_THREADS) void rowdot_kernel(const T *__restrict__ v, int64_t ld,
-                                                            int rows, int64_t n,
-                                                            const float *__restrict__ w,
-                                                            float *__restrict__ out)
+// Output-layer gradient from the backward seed's partials, one workgroup
+// per output: for j < in, out[j] = sum over blocks of part[.][j]
+// (dW_out = sum_b dy h_{L-1}); out[in] = sum of part[.][W] (db_out =
+// sum_b dy). Strided per-thread sums, then a fixed tree: deterministic.
+constexpr int HR_THREADS = 256;
+__global__ __launch_bounds__(HR_THREADS) void head_reduce_kernel(const float *__restrict__ part,
+                                                                 int64_t blocks, int W, int in,
+                                                                 float *__restrict__ out)
 {
-    __shared__ float sh[RS_THREADS];
-    constexpr int CE = 16 / (int)sizeof(T);
-    typedef int v4i_ __attribute__((ext_vector_type(4)));
-    const int r = blockIdx.x;
-    if (r >= rows) return;
-    const T *p = v + (int64_t)r * ld;
+    __shared__ float sh[HR_THREADS];
+    const int j = blockIdx.x;
+    const int col = j < in ? j : W;
     float s = 0.0f;
-    const int64_t nfull = (n / CE) * CE;
-    for (int64_t b = (int64_t)threadIdx.x * CE; b < nfull; b += (int64_t)RS_THREADS * CE) {
-        const v4i_ raw = *reinterpret_cast<const v4i_ *>(p + b);
-        const T *x = reinterpret_cast<const T *>(&raw);
-#pragma unroll
-        for (int e = 0; e < CE; ++e) s += (float)x[e] * (w ? w[b + e] : 1.0f);
-    }
-    if (threadIdx.x == 0)
-        for (int64_t b = nfull; b < n; ++b) s += (float)p[b] * (w ? w[b] : 1.0f);
+    for (int64_t b = threadIdx.x; b < blocks; b += HR_THREADS) s += part[b * (W + 1) + col];
     sh[threadIdx.x] = s;
     __syncthreads();
-    for (int k = RS_THREADS / 2; k > 0; k >>= 1) {
+    for (int k = HR_THREADS / 2; k > 0; k >>= 1) {
         if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[r] = sh[0];
+    if (threadIdx.x == 0) out[j] = sh[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -421,6 +426,7 @@ struct TrainWs {
     void *saved = nullptr;    // x^T + h_l^T (used by advisor_train_step)
     void *gt = nullptr;       // g_l^T
     float *partial = nullptr; // wgrad partial tiles
+    float *head_part = nullptr;  // output-layer gradient partials of the backward seed
     float *pred = nullptr;
     float *dy = nullptr;
     float *grads = nullptr;
@@ -434,6 +440,14 @@ static std::mutex g_ws_mu;
 static size_t elem_bytes(const advisor_model *m) { return m->precision == PREC_FP32 ? 4 : 2; }
 
 static int64_t ld_for(int64_t n) { return ((n + 255) / 256) * 256; }
+
+// Blocks of output-layer gradient partials the backward seed leaves for a
+// batch stride ld: one per 8 row groups of 16 bytes (ld / 64 for bf16,
+// ld / 32 for fp32), whatever the tile height.
+static int64_t head_blocks(const advisor_model *m, int64_t ld)
+{
+    return ld / (8 * (16 / (int64_t)elem_bytes(m)));
+}
 
 // Batch splits of the weight-gradient product: about three workgroups per
 // CU (their waves hide each other's load latency), each chunk a multiple of
@@ -460,7 +474,7 @@ void free_train_ws(advisor_model *m)
 {
     TrainWs *w = train_ws(m);
     if (!w) return;
-    void *ptrs[] = {w->saved, w->gt, w->partial, w->pred, w->dy, w->grads, w->red};
+    void *ptrs[] = {w->saved, w->gt, w->partial, w->pred, w->dy, w->grads, w->red, w->head_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int l = 0; l < MAX_LAYERS; ++l)
@@ -494,10 +508,12 @@ static int ensure_ws(advisor_model *m, int64_t n, bool with_saved)
     const int64_t ld = ld_for(n);
     if (ld > w->ld || (with_saved && !w->saved)) {
         const int64_t newld = std::max(ld, w->ld);
-        for (void **p : {&w->saved, &w->gt, (void **)&w->pred, (void **)&w->dy})
+        for (void **p : {&w->saved, &w->gt, (void **)&w->pred, (void **)&w->dy, (void **)&w->head_part})
             if (*p) { (void)hipFree(*p); *p = nullptr; }
         const size_t eb = elem_bytes(m);
         ADV_HIP(hipMalloc(&w->gt, (size_t)m->n_hidden * m->tile_w * newld * eb));
+        ADV_HIP(hipMalloc((void **)&w->head_part,
+                          sizeof(float) * (size_t)head_blocks(m, newld) * (m->tile_w + 1)));
         ADV_HIP(hipMalloc((void **)&w->pred, sizeof(float) * newld));
         ADV_HIP(hipMalloc((void **)&w->dy, sizeof(float) * newld));
         ADV_HIP(hipMalloc(&w->saved, (size_t)(NFEAT + (int64_t)m->n_hidden * m->tile_w) * newld * eb));
@@ -595,24 +611,13 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
     }
     const unsigned char *xs = reinterpret_cast<const unsigned char *>(saved);
     const unsigned char *hs = xs + (size_t)NFEAT * ld * eb;
-    // output layer: dW_out[j] = sum_b dy[b] h_{L-1}[b][j], db_out = sum_b dy[b]
-    float *g_head = grads + m->layer_off[L];
-    const int in_last = m->widths[L];
-    if (m->precision == PREC_FP32)
-        hipLaunchKernelGGL(rowdot_kernel<float>, dim3(in_last), dim3(RS_THREADS), 0, s,
-                           reinterpret_cast<const float *>(hs + (size_t)(L - 1) * tw * ld * eb), ld,
-                           in_last, n, dy, g_head);
-    else
-        hipLaunchKernelGGL(rowdot_kernel<__bf16>, dim3(in_last), dim3(RS_THREADS), 0, s,
-                           reinterpret_cast<const __bf16 *>(hs + (size_t)(L - 1) * tw * ld * eb), ld,
-                           in_last, n, dy, g_head);
-    hipLaunchKernelGGL(rowdot_kernel<float>, dim3(1), dim3(RS_THREADS), 0, s, dy, n, 1, n,
-                       (const float *)nullptr, g_head + in_last);
-    ADV_LAUNCHED("output-layer gradient");
-    // chain of input gradients through the hidden layers
+    // chain of input gradients through the hidden layers; its seed pass also
+    // leaves the partials of the output layer's gradient,
+    // dW_out[j] = sum_b dy[b] h_{L-1}[b][j] and db_out = sum_b dy[b]
     BwdArgs a{};
     a.dy = dy;
     a.head_w = m->head;
+    a.head_part = w->head_part;
     for (int l = 1; l < L; ++l) a.wt[l] = w->wt[l];
     a.save_h = hs;
     a.gt = w->gt;
@@ -621,6 +626,14 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
     a.n_hidden = L;
     int rc = dispatch_bwd(m, a, s);
     if (rc) return rc;
+    {
+        float *g_head = grads + m->layer_off[L];
+        const int in_last = m->widths[L];
+        const int64_t blocks = head_blocks(m, ld);
+        hipLaunchKernelGGL(head_reduce_kernel, dim3((unsigned)(in_last + 1)), dim3(HR_THREADS), 0, s,
+                           w->head_part, blocks, tw, in_last, g_head);
+        ADV_LAUNCHED("head_reduce_kernel");
+    }
     // weight and bias gradients per hidden layer
     for (int l = 0; l < L; ++l) {
         const int na = tw, nb = l == 0 ? NFEAT : tw;

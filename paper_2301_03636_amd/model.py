@@ -39,6 +39,12 @@ class Model:
     def rank(self, kdesc, vdesc, offsets, best_out=None, pred_out=None, want_pred=False):
         return _lib.advisor_rank(self.handle, kdesc, vdesc, offsets, best_out, pred_out, want_pred)
 
+    def rank_refined(self, refine, kdesc, vdesc, offsets, top_k=8, best_out=None, pred_out=None):
+        """Rank with this model, then re-rank each kernel's top_k candidates
+        with `refine` (e.g. an fp32 model of the same weights)."""
+        return _lib.advisor_rank_refined(self.handle, refine.handle, kdesc, vdesc, offsets, top_k,
+                                         best_out, pred_out)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.advisor_model_destroy(self.handle)

@@ -78,6 +78,7 @@ def test_entry_points_reject_null_model():
     L = _lib.lib()
     assert L.advisor_predict(None, None, 4, None, None) == EINVAL
     assert L.advisor_rank(None, None, None, None, 1, 4, None, None, None) == EINVAL
+    assert L.advisor_rank_refined(None, None, None, None, None, 1, 4, 8, None, None, None) == EINVAL
     assert L.advisor_model_set_params(None, None, None, None) == EINVAL
     assert L.advisor_model_param_count(None) == -1
     L.advisor_model_destroy(None)
