@@ -173,102 +173,172 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
 
 // ---------------------------------------------------------------------------
 // Weight gradient dW[n][k] = sum_b g^T[n][b] h^T[k][b] (both operands with
-// the batch contiguous), split over the batch into `splits` chunks whose fp32
+// the batch contiguous), split over the batch into `splits` ranges whose fp32
 // partial tiles are summed in a fixed order by wgrad_reduce_kernel. A
 // workgroup of 4 waves owns a 128 x 128 output tile, each wave 64 x 64.
 //
-// The batch is consumed in chunks of CH = 8 KV rows. Within a chunk, lane
-// half h holds batch rows h * 4 KV + v * KV + e of its operand row for the
-// matrix-core step v = 0..3 (both operands use the same assignment, which is
-// all the dot product needs), so each lane reads 4 KV contiguous elements
-// (64 bytes) of a row per chunk and the two halves cover its 128-byte line:
-// every line is fetched once, in one burst. Chunks are double-buffered in
-// registers. The waves of the first k-tile also sum their g^T rows, the bias
+// The batch is consumed in chunks of CH = 8 KV rows (one 128-byte line of
+// each operand row). Per chunk the workgroup copies its 128 rows of g^T and
+// of h^T into row-padded LDS (eight threads per line, so each line is
+// fetched once per workgroup) and every wave reads its fragments from there:
+// lane half h takes batch rows h * 4 KV + v * KV + e of its operand row for
+// the matrix-core step v = 0..3 (both operands use the same assignment,
+// which is all the dot product needs). Two LDS buffers alternate, so the
+// copy of the next chunk never waits for the multiplies of this one. The
+// waves of the first column tile also sum their g^T rows: the bias
 // gradient's partials (one per split, reduced in the same fixed order).
+// 72 KB of LDS per workgroup: two workgroups per CU.
 template <int P>
 __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__restrict__ A, int na,
                                                     const typename CT<P>::T *__restrict__ B, int nb,
-                                                    int64_t ld, int64_t kchunk,
+                                                    int64_t ld, int64_t kchunk, int tiles_n,
+                                                    int tiles_k, int splits,
                                                     float *__restrict__ partial,
                                                     float *__restrict__ partial_b)
 {
     using G = Geo<P>;
     using V = typename G::Vec;
     using T = typename CT<P>::T;
+    typedef int v4i_ __attribute__((ext_vector_type(4)));
     constexpr int KV = G::KV, CH = 8 * KV;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int ROWB = CH * (int)sizeof(T);      // bytes of a row per chunk (128)
+    constexpr int SEGS = ROWB / 16;                // 16-byte segments per row (8)
+    constexpr int RS = ROWB + 16;                  // padded LDS row stride
+    constexpr int TILE = 128 * RS;                 // one operand tile in LDS
+    static_assert(SEGS == 8, "a chunk row is one 128-byte line");
+    extern __shared__ __align__(16) unsigned char lds[];  // [2][A, B][128][RS]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
     const int half = lane >> 5, col = lane & 31;
-    const int n0 = blockIdx.x * 128 + (wave & 1) * 64;   // rows of A (outputs)
-    const int k0 = blockIdx.y * 128 + (wave >> 1) * 64;  // rows of B (inputs)
-    const int64_t b0 = (int64_t)blockIdx.z * kchunk;
-    const bool bias_sums = blockIdx.y == 0 && (wave >> 1) == 0;
+    const int wn = wave & 1, wk = wave >> 1;
+    // One-dimensional grid of tiles x splits. Workgroups go to the eight
+    // XCDs round-robin by id; when the splits divide by 8, XCD x gets splits
+    // [x S/8, (x + 1) S/8) for every tile, so each XCD reads its batch range
+    // of the operands from HBM once and serves the other tiles' re-reads of
+    // the same rows from its own L2.
+    int tile, split;
+    {
+        const int wg = blockIdx.x, tiles = tiles_n * tiles_k;
+        if (splits % 8 == 0) {
+            const int xcd = wg & 7, slot = wg >> 3;
+            split = xcd * (splits >> 3) + slot / tiles;
+            tile = slot % tiles;
+        } else {
+            split = wg / tiles;
+            tile = wg % tiles;
+        }
+    }
+    const int n0 = (tile % tiles_n) * 128, k0 = (tile / tiles_n) * 128;
+    const int64_t b0 = (int64_t)split * kchunk;
+    const bool bias_sums = k0 == 0 && wk == 0;
     bool va[2], vb[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        va[i] = n0 + 32 * i < na;
-        vb[i] = k0 + 32 * i < nb;
+        va[i] = n0 + wn * 64 + 32 * i < na;
+        vb[i] = k0 + wk * 64 + 32 * i < nb;
     }
+    // copy duty: thread covers segment tid % 8 of rows tid / 8 + 32 p, p < 4,
+    // of A and of B. Rows past na / nb (whole 32-row groups, never multiplied
+    // into a stored output) load row 0 instead, so every load is issued
+    // unconditionally and the wait before each copy into LDS can leave the
+    // younger chunks' loads in flight.
+    const int seg = tid & 7, r0 = tid >> 3;
+    const T *pa[4], *pb[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int an = n0 + r0 + 32 * p, bk = k0 + r0 + 32 * p;
+        pa[p] = A + (int64_t)(an < na ? an : 0) * ld + b0 + seg * (16 / (int)sizeof(T));
+        pb[p] = B + (int64_t)(bk < nb ? bk : 0) * ld + b0 + seg * (16 / (int)sizeof(T));
+    }
+    auto fetch = [&](int64_t c, v4i_ (&ra)[4], v4i_ (&rb)[4]) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            ra[p] = *reinterpret_cast<const v4i_ *>(pa[p] + c * CH);
+            rb[p] = *reinterpret_cast<const v4i_ *>(pb[p] + c * CH);
+        }
+    };
+    auto stash = [&](int buf, const v4i_ (&ra)[4], const v4i_ (&rb)[4]) {
+        unsigned char *base = lds + (size_t)buf * 2 * TILE;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int r = r0 + 32 * p;
+            *reinterpret_cast<v4i_ *>(base + (size_t)r * RS + seg * 16) = ra[p];
+            *reinterpret_cast<v4i_ *>(base + TILE + (size_t)r * RS + seg * 16) = rb[p];
+        }
+    };
     v16f acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v16f{0};
     float rsum[2] = {0.0f, 0.0f};
-    const T *ap[2], *bp[2];
+    // All four products of a wave run even where a 32-row group lies past
+    // na or nb: those LDS rows hold copies of row 0 (finite values) and the
+    // results are never stored, and one straight-line body keeps the
+    // accumulators in place.
+    auto compute = [&](int buf) {
+        const unsigned char *ab = lds + (size_t)buf * 2 * TILE;
+        const unsigned char *bb = ab + TILE;
+        V x[4][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        // rows past na / nb are never dereferenced (va / vb); point them at row 0
-        ap[i] = A + (int64_t)(va[i] ? n0 + 32 * i + col : 0) * ld + b0 + half * 4 * KV;
-        bp[i] = B + (int64_t)(vb[i] ? k0 + 32 * i + col : 0) * ld + b0 + half * 4 * KV;
-    }
-    auto load = [&](int64_t c, V (&x)[2][4], V (&y)[2][4]) {
+        for (int v = 0; v < 4; ++v) {
+            V y[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                x[i][v] = va[i] ? *reinterpret_cast<const V *>(ap[i] + c * CH + v * KV) : V{0};
-                y[i][v] = vb[i] ? *reinterpret_cast<const V *>(bp[i] + c * CH + v * KV) : V{0};
+            for (int i = 0; i < 2; ++i) {
+                x[v][i] = *reinterpret_cast<const V *>(ab + (size_t)(wn * 64 + 32 * i + col) * RS + (half * 4 + v) * 16);
+                y[i] = *reinterpret_cast<const V *>(bb + (size_t)(wk * 64 + 32 * i + col) * RS + (half * 4 + v) * 16);
             }
-    };
-    auto compute = [&](const V (&x)[2][4], const V (&y)[2][4]) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    if (!(va[i] && vb[j])) continue;
                     if constexpr (P == PREC_FP32) {
 #pragma unroll
-                        for (int t = 0; t < KV; ++t) acc[i][j] = mma(x[i][v][t], y[j][v][t], acc[i][j]);
+                        for (int t = 0; t < KV; ++t) acc[i][j] = mma(x[v][i][t], y[j][t], acc[i][j]);
                     } else {
-                        acc[i][j] = mma(x[i][v], y[j][v], acc[i][j]);
+                        acc[i][j] = mma(x[v][i], y[j], acc[i][j]);
                     }
                 }
+        }
         if (bias_sums) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int v = 0; v < 4; ++v)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int e = 0; e < KV; ++e) rsum[i] += (float)x[i][v][e];
+                    for (int e = 0; e < KV; ++e) rsum[i] += (float)x[v][i][e];
         }
     };
+    // Three chunks are in flight in registers while one is multiplied out of
+    // LDS: stage (c + 1) % 3 holds chunk c + 1 during step c, is copied into
+    // the other LDS buffer after the multiplies (its previous contents were
+    // last read before the barrier that ended step c - 1), and is refilled
+    // with chunk c + 4. The loop runs whole groups of three steps; a step
+    // past the last chunk multiplies nothing, and chunk indices past the
+    // last load the last chunk again, so every step issues the same loads
+    // unconditionally and the compiler's wait before each copy leaves the
+    // two younger chunks in flight.
     const int64_t chunks = kchunk / CH;
-    V xa[2][4], ya[2][4], xb[2][4], yb[2][4];
-    load(0, xa, ya);
-    for (int64_t c = 0; c < chunks; c += 2) {
-        if (c + 1 < chunks) load(c + 1, xb, yb);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(xa, ya);
-        if (c + 1 < chunks) {
-            if (c + 2 < chunks) load(c + 2, xa, ya);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(xb, yb);
-        }
+    auto clampc = [&](int64_t c) { return c < chunks ? c : chunks - 1; };
+    v4i_ sa[3][4], sb[3][4];
+    fetch(0, sa[0], sb[0]);
+    stash(0, sa[0], sb[0]);
+    fetch(clampc(1), sa[1], sb[1]);
+    fetch(clampc(2), sa[2], sb[2]);
+    fetch(clampc(3), sa[0], sb[0]);
+    __syncthreads();
+    auto step = [&](int64_t c, v4i_ (&ra)[4], v4i_ (&rb)[4]) {
+        if (c < chunks) compute((int)(c & 1));
+        stash((int)((c + 1) & 1), ra, rb);
+        fetch(clampc(c + 4), ra, rb);
+        __syncthreads();
+    };
+    for (int64_t c = 0; c < chunks; c += 3) {
+        step(c, sa[1], sb[1]);
+        step(c + 1, sa[2], sb[2]);
+        step(c + 2, sa[0], sb[0]);
     }
-    // D[n][k]: lane holds column k = col, rows n = 8*(r/4) + 4*half + r%4
-    float *out = partial + (int64_t)blockIdx.z * na * nb;
+    float *out = partial + (int64_t)split * na * nb;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -276,19 +346,22 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
             if (!(va[i] && vb[j])) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int nn = n0 + 32 * i + 8 * (r / 4) + 4 * half + (r % 4);
-                const int kk = k0 + 32 * j + col;
+                const int nn = n0 + wn * 64 + 32 * i + 8 * (r / 4) + 4 * half + (r % 4);
+                const int kk = k0 + wk * 64 + 32 * j + col;
                 out[(int64_t)nn * nb + kk] = acc[i][j][r];
             }
         }
     if (bias_sums) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const float t = rsum[i] + __shfl_xor(rsum[i], 32, 64);  // the two batch halves
-            if (half == 0 && va[i]) partial_b[(int64_t)blockIdx.z * na + n0 + 32 * i + col] = t;
+            const float t = rsum[i] + __shfl_xor(rsum[i], 32, 64);
+            if (half == 0 && va[i])
+                partial_b[(int64_t)split * na + n0 + wn * 64 + 32 * i + col] = t;
         }
     }
 }
+
+constexpr size_t WGRAD_LDS_BYTES = 2 * 2 * 128 * (128 + 16);
 
 // grads[off + n * in + k] = sum over splits of partial[s][n][k] (n < out,
 // k < in), then grads[off + out * in + n] = sum over splits of partial_b[s][n]
@@ -449,15 +522,14 @@ static int64_t head_blocks(const advisor_model *m, int64_t ld)
     return ld / (8 * (16 / (int64_t)elem_bytes(m)));
 }
 
-// Batch splits of the weight-gradient product: about three workgroups per
-// CU (their waves hide each other's load latency), each chunk a multiple of
-// 64 rows (ld is a multiple of 256, so a chunk holds a multiple of WG_PF
-// k-groups of 16 bf16 or 8 fp32 rows).
+// Batch splits of the weight-gradient product: enough workgroups for two
+// per CU (all resident at once, which is what the LDS footprint allows),
+// each split a multiple of 64 rows (whole chunks of both precisions).
 static int splits_for(int na, int nb, int64_t ld)
 {
     const int tiles = ((na + 127) / 128) * ((nb + 127) / 128);
     int s = 1;
-    while (tiles * s < 3 * device_cus() && s < 64) s *= 2;
+    while (tiles * s < 2 * device_cus() && s < 64) s *= 2;
     while (s > 1 && (ld / 64) % s != 0) s /= 2;
     return s;
 }
@@ -576,8 +648,25 @@ static int launch_bwd(const BwdArgs &a, hipStream_t s)
     return ADVISOR_OK;
 }
 
+// dynamic-LDS limit of the weight-gradient kernels, once per process
+static int prepare_wgrad()
+{
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(wgrad_kernel<PREC_FP32>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)WGRAD_LDS_BYTES);
+        if (err == hipSuccess)
+            err = hipFuncSetAttribute(reinterpret_cast<const void *>(wgrad_kernel<PREC_BF16>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)WGRAD_LDS_BYTES);
+    });
+    return err == hipSuccess ? ADVISOR_OK : hip_fail(err, "wgrad kernel set-up");
+}
+
 int prepare_train_kernels(int precision, int tile_w)
 {
+    if (int rc = prepare_wgrad()) return rc;
 #define ADV_B(P, WW) if (precision == P && tile_w == WW) return BwdLaunch<P, WW>::setup();
     ADV_B(PREC_FP32, 64) ADV_B(PREC_FP32, 128) ADV_B(PREC_FP32, 256) ADV_B(PREC_FP32, 512)
     ADV_B(PREC_FP32, 1024) ADV_B(PREC_BF16, 64) ADV_B(PREC_BF16, 128) ADV_B(PREC_BF16, 256)
@@ -642,18 +731,19 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         const int64_t kchunk = ld / splits;
         const unsigned char *Ab = reinterpret_cast<const unsigned char *>(w->gt) + (size_t)l * tw * ld * eb;
         const unsigned char *Bb = l == 0 ? xs : hs + (size_t)(l - 1) * tw * ld * eb;
-        dim3 grid((na + 127) / 128, (nb + 127) / 128, splits);
+        const int tn = (na + 127) / 128, tk = (nb + 127) / 128;
+        const dim3 grid((unsigned)(tn * tk * splits));
         float *partial_b = w->partial + w->partial_floats;
         if (m->precision == PREC_FP32)
-            hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, grid, dim3(256), 0, s,
+            hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, grid, dim3(256), WGRAD_LDS_BYTES, s,
                                reinterpret_cast<const float *>(Ab), na,
-                               reinterpret_cast<const float *>(Bb), nb, ld, kchunk, w->partial,
-                               partial_b);
+                               reinterpret_cast<const float *>(Bb), nb, ld, kchunk, tn, tk, splits,
+                               w->partial, partial_b);
         else
-            hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, grid, dim3(256), 0, s,
+            hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, grid, dim3(256), WGRAD_LDS_BYTES, s,
                                reinterpret_cast<const __bf16 *>(Ab), na,
-                               reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, w->partial,
-                               partial_b);
+                               reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, tn, tk, splits,
+                               w->partial, partial_b);
         ADV_LAUNCHED("wgrad_kernel");
         // weights then biases of the layer (the bias gradient is the sum of
         // g^T's rows over the batch; rows past n are zero)
