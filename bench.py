@@ -111,13 +111,89 @@ def time_rank(adv, torch, model, kdd, vdd, offd, best, steps, warmup):
     for _ in range(warmup):
         plan.launch()
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         plan.launch()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plan.close()
-    return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    pct = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
+           "p90": float(np.percentile(per, 90))}
+    return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches, pct
+
+
+def time_with_transfers(adv, torch, model, kd, vd, off, kdd, vdd, offd, best, steps, warmup):
+    """The same ranking with the descriptors handed over in pinned host
+    memory: each step copies kdesc, vdesc and offsets to the device, ranks
+    (graph replay) and copies `best` back, all on one stream."""
+    pin = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (kd, vd, off)]
+    best_h = torch.empty(best.shape, dtype=best.dtype).pin_memory()
+    plan = adv.Plan.rank(model, kdd, vdd, offd, best)
+
+    def step():
+        for dev, host in zip((kdd, vdd, offd), pin):
+            dev.copy_(host, non_blocking=True)
+        plan.launch()
+        best_h.copy_(best, non_blocking=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for dev, host in zip((kdd, vdd, offd), pin):
+        dev.copy_(host, non_blocking=True)
+    e[1].record()
+    best_h.copy_(best, non_blocking=True)
+    e[2].record()
+    torch.cuda.synchronize()
+    plan.close()
+    h2d_bytes = sum(int(a.nbytes) for a in (kd, vd, off))
+    h2d_ms, d2h_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    return {"ms_per_step": ms, "value": vd.shape[0] / (ms / 1e3), "h2d_bytes": h2d_bytes,
+            "h2d_ms": h2d_ms, "h2d_gbs": h2d_bytes / (h2d_ms / 1e3) / 1e9, "d2h_ms": d2h_ms}
+
+
+def stage_kernels(adv, torch, kdd, vdd, offd, steps):
+    """advisor_featurize and advisor_rank_preds alone on the workload, each
+    priced against HBM bandwidth with its algorithmic bytes: featurize reads
+    64 B of vdesc per variant (kdesc rows are amortized over a kernel's
+    variants: 128 B per kernel) and writes 256 B of features and a 1-byte
+    flag; the argmin reads a 4-byte prediction per variant and 8 B of
+    offsets and writes 8 B of `best` per kernel."""
+    nv, nk = vdd.shape[0], offd.shape[0] - 1
+    feat = torch.empty((nv, 32), dtype=torch.int64, device=vdd.device)
+    inv = torch.empty(nv, dtype=torch.uint8, device=vdd.device)
+    pred = torch.empty(nv, dtype=torch.float32, device=vdd.device).normal_()
+    best = torch.empty(nk, dtype=torch.int64, device=vdd.device)
+    out = {}
+    for name, fn, nbytes in (
+            ("featurize", lambda: adv.advisor_featurize(kdd, vdd, feat_out=feat, invalid_out=inv),
+             nv * (64 + 256 + 1) + nk * 128),
+            ("rank_preds", lambda: adv.advisor_rank_preds(pred, offd, best_out=best),
+             nv * 4 + nk * 16 + 8)):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = nbytes / (ms / 1e3) / 1e9
+        out[name] = {"ms": ms, "bytes": nbytes, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
+                     "frac": gbs / PEAK_HBM_GBS}
+    del feat, inv, pred, best
+    return out
 
 
 def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds, gpu_best_by_prec):
@@ -290,6 +366,10 @@ def main():
                     help="also time bf16/fp8 ranking refined by an fp32 model on each kernel's "
                          "top-k candidates (advisor_rank_refined; default 8 for bf16, 16 for "
                          "fp8); 0 to skip")
+    ap.add_argument("--no-transfers", dest="transfers", action="store_false",
+                    help="skip the leg that hands the descriptors over in pinned host memory")
+    ap.add_argument("--no-stages", dest="stages", action="store_false",
+                    help="skip timing advisor_featurize and advisor_rank_preds alone")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the "
                          "HBM byte counters of a profiler run) and exit")
@@ -342,15 +422,20 @@ def main():
         # tile shape chosen by the library's autotuner on this workload
         shape, shape_ms = adv.advisor_autotune(m.handle, kdd, vdd, offd, reps=3)
         best = torch.empty(nk, dtype=torch.int64, device=d)
-        ms, kern_ms, launches = time_rank(adv, torch, m, kdd, vdd, offd, best,
-                                          args.steps if p == prec else max(5, args.steps // 2),
-                                          args.warmup)
+        ms, kern_ms, launches, pct = time_rank(adv, torch, m, kdd, vdd, offd, best,
+                                               args.steps if p == prec else max(5, args.steps // 2),
+                                               args.warmup)
         best_by_prec[p] = best.cpu().numpy()
         fl = sum(layer_flops(widths))
         results[p] = dict(ms_per_step=ms, kernel_ms=kern_ms, launches=launches,
-                          value=nv / (ms / 1e3),
+                          value=nv / (ms / 1e3), replay_ms=pct,
                           tflops=fl * nv / (kern_ms / 1e3) / 1e12,
-                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:4]])
+                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:4]],
+                          mfma_peak_measured=adv.advisor_mfma_peak(p, iters=100000))
+        if p == prec and args.transfers:
+            results[p]["with_transfers"] = time_with_transfers(
+                adv, torch, m, kd, vd, off, kdd, vdd, offd, best, max(5, args.steps // 2),
+                args.warmup)
         rk = refine_k_for(p, args.refine_k)
         if p != "fp32" and rk > 0:
             # the same ranking with each kernel's top-k re-ranked in fp32 (eager calls)
@@ -395,8 +480,14 @@ def main():
                      "traffic": traffic,
                      "kernel": "mlp_tiles_kernel (fused featurize+MLP+argmin)",
                      "kernel_ms": main_r["kernel_ms"],
-                     "flops_per_variant": sum(layer_flops(widths))},
+                     "flops_per_variant": sum(layer_flops(widths)),
+                     "replay_ms": main_r["replay_ms"],
+                     "mfma_peak_measured": main_r["mfma_peak_measured"]},
     }
+    if "with_transfers" in main_r:
+        out["with_transfers"] = main_r["with_transfers"]
+    if args.stages:
+        out["stages"] = stage_kernels(adv, torch, kdd, vdd, offd, max(5, args.steps // 2))
     agree_t = {}
     if not args.no_cpu_baseline:
         cb, agree, per_variant = cpu_baseline_leg(kd, vd, off, widths, params, mu, sd,
@@ -411,6 +502,7 @@ def main():
         p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
             "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
             "tile_shape": r["tile_shape"], "autotune_ms": r["tune_ms"],
+            "replay_ms": r["replay_ms"], "mfma_peak_measured": r["mfma_peak_measured"],
             "argmin_agreement_vs_oracle_sample": agree.get(p),
             "argmin_agreement_trained_network": agree_t.get(p),
             "refined_by_fp32": None if "refined" not in r else dict(

@@ -330,6 +330,19 @@ void advisor_plan_destroy(advisor_plan *plan);
 int advisor_profile_enable(int on);
 int advisor_profile_read(int64_t *launches, double *total_ms);
 
+/*
+ * Measurement aid (not part of the method): the sustained matrix-core rate
+ * of the current device for `precision` (ADVISOR_FP32: 32x32x2 fp32,
+ * ADVISOR_BF16: 32x32x16 bf16, ADVISOR_FP8_E4M3: 32x32x64 e4m3, the ops the
+ * tile kernels issue). workgroups_per_cu (1..8) workgroups of 4 waves per
+ * compute unit each run `iters` (1..2^24) rounds of 8 independent ops on
+ * register operands; the timed launch follows a short warm-up one on
+ * `stream`. *tflops_out receives dense TFLOP/s. Allocates a small buffer,
+ * synchronizes the stream, EINVAL on bad arguments.
+ */
+int advisor_mfma_peak(int precision, int64_t iters, int workgroups_per_cu, double *tflops_out,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

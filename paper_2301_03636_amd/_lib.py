@@ -75,6 +75,7 @@ def lib():
             "advisor_model_get_tile_variant": ([P], i32),
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
+            "advisor_mfma_peak": ([i32, i64, i32, C.POINTER(C.c_double), P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -290,6 +291,16 @@ def advisor_profile_read():
     ms = C.c_double(0.0)
     _check(lib().advisor_profile_read(C.byref(n), C.byref(ms)), "advisor_profile_read")
     return n.value, ms.value
+
+
+def advisor_mfma_peak(precision, iters=20000, workgroups_per_cu=2) -> float:
+    """Sustained dense matrix-core TFLOP/s of the current device for
+    'fp32', 'bf16' or 'fp8' (register operands, no memory traffic)."""
+    code = {"fp32": 0, "bf16": 1, "fp8": 2}[precision]
+    out = C.c_double(0.0)
+    _check(lib().advisor_mfma_peak(code, int(iters), int(workgroups_per_cu), C.byref(out),
+                                   _stream()), "advisor_mfma_peak")
+    return out.value
 
 
 # --------------------------------------------------------------------------- training

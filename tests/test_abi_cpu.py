@@ -96,3 +96,14 @@ def test_python_binding_names_match_c():
             continue
         assert hasattr(_lib, n), n
     assert adv.PRECISIONS == {"fp32": 0, "bf16": 1, "fp8": 2}
+
+
+def test_mfma_peak_argument_checks():
+    L = _lib.lib()
+    out = C.c_double(0.0)
+    assert L.advisor_mfma_peak(0, 10, 1, None, None) == EINVAL
+    assert L.advisor_mfma_peak(7, 10, 1, C.byref(out), None) == EINVAL
+    assert L.advisor_mfma_peak(1, 0, 1, C.byref(out), None) == EINVAL
+    assert L.advisor_mfma_peak(1, (1 << 24) + 1, 1, C.byref(out), None) == EINVAL
+    assert L.advisor_mfma_peak(2, 10, 0, C.byref(out), None) == EINVAL
+    assert L.advisor_mfma_peak(2, 10, 9, C.byref(out), None) == EINVAL
