@@ -402,34 +402,150 @@ __device__ __forceinline__ void store4(unsigned char *row, int n, v4f v, float q
     store_held<P>(row, n, pack4<P>(v, qinv));
 }
 
+// Transposed access to a tile's activations: an LDS tile is row-major
+// ([M][W], rows of stride AS), the saved layouts are neuron-major
+// (dst[n * ld + row], rows contiguous). The work unit of a thread is four
+// consecutive neurons of two row groups (CE = 16 / element-size rows each) of
+// one 128-byte line block (8 row groups): per row one 8-byte (bf16) or
+// 16-byte (fp32) LDS access holds the four neurons, and each neuron's CE rows
+// leave as one 16-byte vector. Lane bits 0-1 pick the row group within half
+// a line block (the second row group of the unit is 4 further on), bits 2-5
+// the neuron quad, so an LDS access of a wave meets each bank no more often
+// than its width forces, and four consecutive lanes store 64 contiguous bytes
+// of each neuron.
+template <int P, int W, int M, int THREADS>
+struct TUnits {
+    using T = typename std::conditional<P == PREC_FP32, float, __bf16>::type;
+    static constexpr int CE = 16 / (int)sizeof(T);  // rows of a row group
+    static constexpr int RG = M / CE;               // row groups of a tile
+    static constexpr int LINES = RG / 8;            // 128-byte line blocks per neuron
+    static constexpr int QH = W / 64;               // neuron quads per 16 lanes
+    static constexpr int UNITS = LINES * QH * 64;   // = RG * W / 8, whole waves
+    static_assert(M % CE == 0 && RG % 8 == 0, "row groups come in line blocks of eight");
+    static_assert(W % 64 == 0, "sixteen neuron quads per wave");
+    static_assert(UNITS % THREADS == 0 || THREADS % UNITS == 0, "units split over whole waves");
+    // unit c (c < UNITS): first row group, neuron quad, line block
+    __device__ static void decode(int c, int &rg, int &nq, int &line)
+    {
+        const int v = c >> 6;
+        line = v / QH;
+        nq = (v % QH) * 16 + ((c >> 2) & 15);
+        rg = line * 8 + (c & 3);
+    }
+};
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+// Four neurons nq*4 .. nq*4+3 of rows m0 .. m0+CE-1 from a row-major LDS
+// tile into one 16-byte vector per neuron (rows in order).
+template <int P>
+__device__ __forceinline__ void lds_gather4(const unsigned char *act, int as, int m0, int nq,
+                                            v4i_t (&out)[4])
+{
+    if constexpr (P == PREC_FP32) {
+        v4i_t r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            r[e] = *reinterpret_cast<const v4i_t *>(act + (size_t)(m0 + e) * as + nq * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out[q][e] = r[e][q];
+    } else {
+        typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
+        v2u_ r[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            r[e] = *reinterpret_cast<const v2u_ *>(act + (size_t)(m0 + e) * as + nq * 8);
+        // dword p of neuron q's vector = rows 2p (low half) and 2p + 1
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const v2u_ a = r[2 * p], b = r[2 * p + 1];
+            out[0][p] = (int)((a[0] & 0xffffu) | (b[0] << 16));
+            out[1][p] = (int)((a[0] >> 16) | (b[0] & 0xffff0000u));
+            out[2][p] = (int)((a[1] & 0xffffu) | (b[1] << 16));
+            out[3][p] = (int)((a[1] >> 16) | (b[1] & 0xffff0000u));
+        }
+    }
+}
+
+// The inverse of lds_gather4: four neuron vectors back into the rows.
+template <int P>
+__device__ __forceinline__ void lds_scatter4(unsigned char *act, int as, int m0, int nq,
+                                             const v4i_t (&in)[4])
+{
+    if constexpr (P == PREC_FP32) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v4i_t r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = in[q][e];
+            *reinterpret_cast<v4i_t *>(act + (size_t)(m0 + e) * as + nq * 16) = r;
+        }
+    } else {
+        typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const unsigned n0 = (unsigned)in[0][p], n1 = (unsigned)in[1][p];
+            const unsigned n2 = (unsigned)in[2][p], n3 = (unsigned)in[3][p];
+            v2u_ a, b;  // rows 2p and 2p + 1
+            a[0] = (n0 & 0xffffu) | (n1 << 16);
+            a[1] = (n2 & 0xffffu) | (n3 << 16);
+            b[0] = (n0 >> 16) | (n1 & 0xffff0000u);
+            b[1] = (n2 >> 16) | (n3 & 0xffff0000u);
+            *reinterpret_cast<v2u_ *>(act + (size_t)(m0 + 2 * p) * as + nq * 8) = a;
+            *reinterpret_cast<v2u_ *>(act + (size_t)(m0 + 2 * p + 1) * as + nq * 8) = b;
+        }
+    }
+}
+
+// Zero the elements of rows >= n_rows in a neuron vector of rows r0 ...
+template <int P>
+__device__ __forceinline__ v4i_t zero_rows_past(v4i_t v, int64_t r0, int64_t n_rows)
+{
+    if (r0 + 16 / (P == PREC_FP32 ? 4 : 2) <= n_rows) return v;
+    if constexpr (P == PREC_FP32) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (r0 + e >= n_rows) v[e] = 0;
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            unsigned w = (unsigned)v[p];
+            if (r0 + 2 * p >= n_rows) w &= 0xffff0000u;
+            if (r0 + 2 * p + 1 >= n_rows) w &= 0x0000ffffu;
+            v[p] = (int)w;
+        }
+    }
+    return v;
+}
+
 // Copy a tile's activations [M][W] (LDS rows of stride AS) to the transposed
-// global layout dst[n * ld + row0 + m] (rows >= n_rows as zero). A thread
-// gathers one neuron of CE consecutive rows from LDS and stores them as one
-// 16-byte vector. Eight consecutive threads take eight consecutive row groups
-// of one neuron, so a wave's store covers eight whole 128-byte lines.
+// global layout dst[n * ld + row0 + m] (rows >= n_rows as zero), by the
+// units of TUnits.
 template <int P, int W, int M, int THREADS, int AS>
 __device__ __forceinline__ void copy_act_transposed(const unsigned char *act, void *dst,
                                                     int64_t ld, int64_t row0, int64_t n_rows,
                                                     int tid)
 {
-    using T = typename std::conditional<P == PREC_FP32, float, __bf16>::type;
-    typedef int v4i_ __attribute__((ext_vector_type(4)));
-    constexpr int CE = 16 / (int)sizeof(T);
-    constexpr int RG = M / CE;  // row groups per neuron
-    static_assert(M % CE == 0, "row groups");
+    using U = TUnits<P, W, M, THREADS>;
+    using T = typename U::T;
     T *d = reinterpret_cast<T *>(dst);
-    static_assert(RG % 8 == 0, "row groups come in eights");
-    for (int c = tid; c < W * RG; c += THREADS) {
-        // 8 consecutive threads: 8 row groups (one 128-byte line) of a neuron
-        const int t = c >> 3, nn = t % W, m0 = ((t / W) * 8 + (c & 7)) * CE;
-        v4i_ raw;
-        T *vals = reinterpret_cast<T *>(&raw);
+    for (int c0 = tid; c0 < U::UNITS; c0 += THREADS) {
+        int c = c0;
+        asm volatile("" : "+v"(c));  // address math here, not hoisted out of the tile loop
+        int rg, nq, line;
+        U::decode(c, rg, nq, line);
 #pragma unroll
-        for (int e = 0; e < CE; ++e) {
-            const T v = *reinterpret_cast<const T *>(act + (size_t)(m0 + e) * AS + nn * sizeof(T));
-            vals[e] = row0 + m0 + e < n_rows ? v : (T)0.0f;
+        for (int s = 0; s < 2; ++s) {
+            const int m0 = (rg + 4 * s) * U::CE;
+            v4i_t v[4];
+            lds_gather4<P>(act, AS, m0, nq, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<v4i_t *>(d + (int64_t)(nq * 4 + q) * ld + row0 + m0) =
+                    zero_rows_past<P>(v[q], row0 + m0, n_rows);
         }
-        *reinterpret_cast<v4i_ *>(d + (int64_t)nn * ld + row0 + m0) = raw;
     }
 }
 

@@ -64,6 +64,12 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     constexpr int CE = 16 / (int)sizeof(T);  // elements per 16-byte run
     constexpr int RG = M / CE;                // row groups of a tile
     static_assert(RG % 8 == 0, "row groups come in eights");
+    // seed and mask passes work in the transposed units of TUnits: UPT units
+    // per thread (or one for the first UNITS threads), UB of them with their
+    // loads in flight together
+    using TU = TUnits<P, W, M, C::THREADS>;
+    constexpr int UPT = TU::UNITS >= C::THREADS ? TU::UNITS / C::THREADS : 1;
+    constexpr int UB = 1;
     typedef int v4i_ __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *act = lds;  // [M][AS]
@@ -80,46 +86,85 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
         __syncthreads();
-        // seed: gradient at the last hidden layer's pre-activation. A thread
-        // takes one neuron of CE consecutive rows (one 16-byte vector of the
-        // transposed layouts); eight consecutive threads take eight
-        // consecutive row groups of one neuron (one 128-byte line)
+        // seed: gradient at the last hidden layer's pre-activation,
+        // g[m][j] = dy[m] w_out[j] [h[m][j] > 0], into LDS (row-major) and out
+        // transposed, with the output layer's gradient partials
+        // sum_m dy[m] h[m][j] and sum_m dy[m] per line block of rows. dy holds
+        // ld rows (those past n are read and then replaced by zero).
         {
             const T *Hl = H + (int64_t)(L - 1) * W * ld;
             T *Gl = GT + (int64_t)(L - 1) * W * ld;
-            for (int c = tid; c < W * RG; c += C::THREADS) {
-                const int t = c >> 3, j = t % W, m0 = ((t / W) * 8 + (c & 7)) * CE;
-                const int64_t r0 = row0 + m0;
-                const v4i_ hraw = *reinterpret_cast<const v4i_ *>(Hl + (int64_t)j * ld + r0);
-                const T *hv = reinterpret_cast<const T *>(&hraw);
-                const float hw = a.head_w[j];
-                v4i_ graw;
-                T *gv = reinterpret_cast<T *>(&graw);
-                float sdh = 0.0f, sd = 0.0f;  // output-layer gradient partials
+            for (int i0 = 0; i0 < UPT; i0 += UB) {
+                v4i_ hraw[UB][2][4], draw[UB][2][CE / 4];
+                v4f hw4[UB];
 #pragma unroll
-                for (int e = 0; e < CE; ++e) {
-                    const int64_t row = r0 + e;
-                    const float d = row < n ? a.dy[row] : 0.0f;
-                    const float h = (float)hv[e];
-                    const T g = (T)(h > 0.0f ? d * hw : 0.0f);
-                    gv[e] = g;
-                    *reinterpret_cast<T *>(act + (size_t)(m0 + e) * C::AS + j * sizeof(T)) = g;
-                    sdh += d * h;
-                    sd += d;
-                }
-                *reinterpret_cast<v4i_ *>(Gl + (int64_t)j * ld + r0) = graw;
-                // sum over the 8 row groups of this line (8 consecutive lanes);
-                // one partial per (tile, line block, neuron), reduced in order
-                // by head_reduce_kernel
+                for (int u = 0; u < UB; ++u) {
+                    int c = tid + (i0 + u) * C::THREADS;
+                    // recompute the unit's addresses here rather than keep
+                    // them live through the layer loop's multiplies
+                    asm volatile("" : "+v"(c));
+                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;  // whole waves
+                    int rg, nq, line;
+                    TU::decode(c, rg, nq, line);
 #pragma unroll
-                for (int off = 1; off < 8; off <<= 1) {
-                    sdh += __shfl_xor(sdh, off, 64);
-                    sd += __shfl_xor(sd, off, 64);
+                    for (int sidx = 0; sidx < 2; ++sidx) {
+                        const int64_t r0 = row0 + (rg + 4 * sidx) * CE;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            hraw[u][sidx][q] = *reinterpret_cast<const v4i_ *>(Hl + (int64_t)(nq * 4 + q) * ld + r0);
+#pragma unroll
+                        for (int q = 0; q < CE / 4; ++q)
+                            draw[u][sidx][q] = *reinterpret_cast<const v4i_ *>(a.dy + r0 + 4 * q);
+                    }
+                    hw4[u] = *reinterpret_cast<const v4f *>(a.head_w + nq * 4);
                 }
-                if ((c & 7) == 0) {
-                    float *hp = a.head_part + ((int64_t)tile * (RG / 8) + (c >> 3) / W) * (W + 1);
-                    hp[j] = sdh;
-                    if (j == 0) hp[W] = sd;
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    int c = tid + (i0 + u) * C::THREADS;
+                    // recompute the unit's addresses here rather than keep
+                    // them live through the layer loop's multiplies
+                    asm volatile("" : "+v"(c));
+                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;
+                    int rg, nq, line;
+                    TU::decode(c, rg, nq, line);
+                    float sdh[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sd = 0.0f;
+#pragma unroll
+                    for (int sidx = 0; sidx < 2; ++sidx) {
+                        const int m0 = (rg + 4 * sidx) * CE;
+                        const int64_t r0 = row0 + m0;
+                        const float *dv = reinterpret_cast<const float *>(&draw[u][sidx][0]);
+                        v4i_ gvec[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const T *hv = reinterpret_cast<const T *>(&hraw[u][sidx][q]);
+                            T *gv = reinterpret_cast<T *>(&gvec[q]);
+#pragma unroll
+                            for (int e = 0; e < CE; ++e) {
+                                const float d = r0 + e < n ? dv[e] : 0.0f;
+                                const float h = (float)hv[e];
+                                gv[e] = (T)(h > 0.0f ? d * hw4[u][q] : 0.0f);
+                                sdh[q] += d * h;
+                            }
+                            *reinterpret_cast<v4i_ *>(Gl + (int64_t)(nq * 4 + q) * ld + r0) = gvec[q];
+                        }
+#pragma unroll
+                        for (int e = 0; e < CE; ++e) sd += r0 + e < n ? dv[e] : 0.0f;
+                        lds_scatter4<P>(act, C::AS, m0, nq, gvec);
+                    }
+                    // the four lanes of a line block's other row groups; one
+                    // partial per (tile, line block, neuron), reduced in order
+                    // by head_reduce_kernel
+#pragma unroll
+                    for (int off = 1; off < 4; off <<= 1) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) sdh[q] += __shfl_xor(sdh[q], off, 64);
+                        sd += __shfl_xor(sd, off, 64);
+                    }
+                    if ((c & 3) == 0) {
+                        float *hp = a.head_part + ((int64_t)tile * (RG / 8) + line) * (W + 1);
+                        *reinterpret_cast<v4f *>(hp + nq * 4) = v4f{sdh[0], sdh[1], sdh[2], sdh[3]};
+                        if (nq == 0) hp[W] = sd;
+                    }
                 }
             }
         }
@@ -146,25 +191,54 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
                 }
             __syncthreads();
             // ... then the ReLU mask of h_{l-1}, written back for the next
-            // layer and out, transposed, for the weight gradients (the same
-            // thread mapping as the seed)
+            // layer and out, transposed, for the weight gradients (the units
+            // and batching of the seed)
             const T *Hp = H + (int64_t)(l - 1) * W * ld;
             T *Gp = GT + (int64_t)(l - 1) * W * ld;
-            for (int c = tid; c < W * RG; c += C::THREADS) {
-                const int t = c >> 3, k = t % W, m0 = ((t / W) * 8 + (c & 7)) * CE;
-                const int64_t r0 = row0 + m0;
-                const v4i_ hraw = *reinterpret_cast<const v4i_ *>(Hp + (int64_t)k * ld + r0);
-                const T *hv = reinterpret_cast<const T *>(&hraw);
-                v4i_ graw;
-                T *gv = reinterpret_cast<T *>(&graw);
+            for (int i0 = 0; i0 < UPT; i0 += UB) {
+                v4i_ hraw[UB][2][4];
 #pragma unroll
-                for (int e = 0; e < CE; ++e) {
-                    T *cell = reinterpret_cast<T *>(act + (size_t)(m0 + e) * C::AS + k * sizeof(T));
-                    const T g = (float)hv[e] > 0.0f ? *cell : (T)0.0f;
-                    gv[e] = g;
-                    if (l > 1) *cell = g;
+                for (int u = 0; u < UB; ++u) {
+                    int c = tid + (i0 + u) * C::THREADS;
+                    // recompute the unit's addresses here rather than keep
+                    // them live through the layer loop's multiplies
+                    asm volatile("" : "+v"(c));
+                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;
+                    int rg, nq, line;
+                    TU::decode(c, rg, nq, line);
+#pragma unroll
+                    for (int sidx = 0; sidx < 2; ++sidx)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            hraw[u][sidx][q] = *reinterpret_cast<const v4i_ *>(
+                                Hp + (int64_t)(nq * 4 + q) * ld + row0 + (rg + 4 * sidx) * CE);
                 }
-                *reinterpret_cast<v4i_ *>(Gp + (int64_t)k * ld + r0) = graw;
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    int c = tid + (i0 + u) * C::THREADS;
+                    // recompute the unit's addresses here rather than keep
+                    // them live through the layer loop's multiplies
+                    asm volatile("" : "+v"(c));
+                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;
+                    int rg, nq, line;
+                    TU::decode(c, rg, nq, line);
+#pragma unroll
+                    for (int sidx = 0; sidx < 2; ++sidx) {
+                        const int m0 = (rg + 4 * sidx) * CE;
+                        v4i_ gvec[4];
+                        lds_gather4<P>(act, C::AS, m0, nq, gvec);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const T *hv = reinterpret_cast<const T *>(&hraw[u][sidx][q]);
+                            T *gv = reinterpret_cast<T *>(&gvec[q]);
+#pragma unroll
+                            for (int e = 0; e < CE; ++e)
+                                if (!((float)hv[e] > 0.0f)) gv[e] = (T)0.0f;
+                            *reinterpret_cast<v4i_ *>(Gp + (int64_t)(nq * 4 + q) * ld + row0 + m0) = gvec[q];
+                        }
+                        if (l > 1) lds_scatter4<P>(act, C::AS, m0, nq, gvec);
+                    }
+                }
             }
             __syncthreads();
         }
@@ -821,7 +895,12 @@ extern "C" int advisor_mlp_backward(advisor_model *m, const float *dy, const voi
     std::lock_guard<std::mutex> lock(g_ws_mu);
     rc = ensure_ws(m, n, false);
     if (rc) return rc;
-    return backward_core(m, dy, saved, n, grads_out, as_stream(stream));
+    // the backward kernel reads dy in 16-byte vectors over the padded batch:
+    // stage the caller's n values in the workspace copy (ld rows)
+    TrainWs *w = train_ws(m);
+    hipStream_t s = as_stream(stream);
+    ADV_HIP(hipMemcpyAsync(w->dy, dy, sizeof(float) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    return backward_core(m, w->dy, saved, n, grads_out, s);
 }
 
 extern "C" int advisor_train_step(advisor_model *m, const int64_t *feat, const double *y, int64_t n,
