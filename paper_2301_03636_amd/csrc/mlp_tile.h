@@ -693,14 +693,25 @@ mlp_tiles_kernel(TileArgs args)
     unsigned char *vst = lds + C::LDS_BASE;                     // [M][64 B] (VPF)
     float *hw_lds = reinterpret_cast<float *>(vst + C::VST_BYTES);  // [W] (VPF)
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid0 = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid0 >> 6);
     const int wn = wave % C::WN, wm = wave / C::WN;
     const int nb0 = wn * C::NBW, mb0 = wm * C::MBW;
-    const int half = lane >> 5, col = lane & 31;
     const NetView &net = args.net;
     const int64_t n = args.n_rows;
     // the training forward covers every row of the saved buffers (zeros past n)
     const int64_t ntiles = SINK == SINK_TRAIN ? args.save_ld / M : (n + M - 1) / M;
+    // Per-thread values are re-derived from an opaque copy of the thread
+    // index at the top of every tile and layer (opaque_tid): the addresses
+    // built from them are then computed where they are used instead of being
+    // hoisted out of the tile loop, where they would sit in registers (or
+    // spill) through every layer's multiplies.
+    auto opaque_tid = [&]() {
+        int t = tid0;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
+    int tid = tid0, lane = tid0 & 63, half = lane >> 5, col = lane & 31;
 
     // weight rings of the first layer and of the hidden layers: each call of
     // layer_mma finds its first k-groups already requested, by the call before
@@ -741,6 +752,8 @@ mlp_tiles_kernel(TileArgs args)
         const int64_t row0 = tile * M;
         if constexpr (VPF) __builtin_amdgcn_s_waitcnt(0);  // this tile's rows are in LDS
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
+        tid = opaque_tid();
+        lane = tid & 63, half = lane >> 5, col = lane & 31;
         tile_input<C, P, M, SRC, SINK>(args, row0, tid, xin, meta_ok, meta_kid, vst);
         // the first layer's weights, requested before the barrier (not across
         // the input stage, whose registers are at their peak)
@@ -754,6 +767,8 @@ mlp_tiles_kernel(TileArgs args)
         // has read the layer's input, and all outputs then go to LDS in its
         // place.
         for (int l = 0; l < net.n_hidden; ++l) {
+            tid = opaque_tid();
+            lane = tid & 63, half = lane >> 5, col = lane & 31;
             const bool last = l + 1 == net.n_hidden;
             const float *bias = net.b[l];
             // fp8 layers scale the products before the bias; every other layer
@@ -877,6 +892,8 @@ mlp_tiles_kernel(TileArgs args)
             }
         }
         __syncthreads();
+        tid = opaque_tid();
+        lane = tid & 63;
         tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid);
     }
 }
@@ -918,10 +935,17 @@ mlp_pp_kernel(TileArgs args)
     unsigned char *vst = lds + C::LDS_BASE;                     // [M][64 B] (VPF)
     float *hw_lds = reinterpret_cast<float *>(vst + C::VST_BYTES);  // [W] (VPF)
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid0 = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid0 >> 6);
     const int wn = wave % C::WN, wm = wave / C::WN;
     const int nb0 = wn * NBW, mb0 = wm * C::MBW;
-    const int half = lane >> 5, col = lane & 31;
+    // re-derived per tile from an opaque copy (see mlp_tiles_kernel)
+    auto opaque_tid = [&]() {
+        int t = tid0;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
+    int tid = tid0, lane = tid0 & 63, half = lane >> 5, col = lane & 31;
     const NetView &net = args.net;
     const int64_t n = args.n_rows;
     const int64_t ntiles = (n + M - 1) / M;
@@ -1007,6 +1031,8 @@ mlp_pp_kernel(TileArgs args)
         const int64_t row0 = tile * M;
         if constexpr (VPF) __builtin_amdgcn_s_waitcnt(0);  // this tile's rows are in LDS
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
+        tid = opaque_tid();
+        lane = tid & 63, half = lane >> 5, col = lane & 31;
         tile_input<C, P, M, SRC, SINK>(args, row0, tid, xin, meta_ok, meta_kid, vst);
         __syncthreads();
 
@@ -1058,6 +1084,8 @@ mlp_pp_kernel(TileArgs args)
             }
         }
         __syncthreads();
+        tid = opaque_tid();
+        lane = tid & 63;
         tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid);
     }
 }
