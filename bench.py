@@ -37,6 +37,7 @@ import workload  # noqa: E402
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
 PEAK_HBM_GBS = 8000.0
 DEFAULT_PRECISION = {1: "fp32", 2: "fp32", 3: "bf16", 5: "fp8"}
+DEFAULT_ALSO = {1: "", 2: "bf16", 3: "fp32", 5: "bf16,fp32"}
 WORKLOAD_NAME = {
     1: "single kernel x 256 variants, 32-64-64-1",
     2: "4096 kernels x U[16,1024] variants (2.1M), 32-256x3-1",
@@ -356,8 +357,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--also", default="bf16",
-                    help="comma-separated extra precisions timed on the same inputs ('' for none)")
+    ap.add_argument("--also", default=None,
+                    help="comma-separated extra precisions timed on the same inputs ('' for none; "
+                         "default: the other two of fp32, bf16 and fp8 that the workload's "
+                         "network has, i.e. bf16 for the 256-wide network, fp32 for the "
+                         "512-wide one, bf16 and fp32 for the 1024-wide one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--train-steps", type=int, default=20,
                     help="timed training steps (batch 65536, bf16 32-512x4-1); 0 to skip")
@@ -413,7 +417,8 @@ def main():
 
     results = {}
     best_by_prec = {}
-    precs = [prec] + [p for p in args.also.split(",") if p and p != prec]
+    also = args.also if args.also is not None else DEFAULT_ALSO[cfg]
+    precs = [prec] + [p for p in also.split(",") if p and p != prec]
     for p in precs:
         m = adv.Model(widths, p)
         m.set_params(params, mu, sd)
