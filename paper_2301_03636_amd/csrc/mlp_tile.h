@@ -591,7 +591,11 @@ __device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, i
     const NetView &net = args.net;
     const int64_t n = args.n_rows;
     {
-        const int r = tid % M, part = tid / M;
+        // with M a multiple of 64 a wave's threads share one part: make that
+        // known to the compiler, so picking the part's features below is a
+        // scalar branch instead of a per-lane select over all 32 features
+        const int r = tid % M;
+        const int part = M % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M;
         const int64_t row = row0 + r;
         const bool inrow = row < n;
         uint64_t fsel[C::FPP];
@@ -614,9 +618,18 @@ __device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, i
             // this thread's FPP features (part is not a compile-time value)
 #pragma unroll
             for (int q = 0; q < C::FPP; ++q) fsel[q] = 0;
+            if constexpr (M % 64 == 0) {
 #pragma unroll
-            for (int j = 0; j < NFEAT; ++j)
-                if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
+                for (int p = 0; p < C::PARTS; ++p)
+                    if (part == p) {
+#pragma unroll
+                        for (int q = 0; q < C::FPP; ++q) fsel[q] = f.f[p * C::FPP + q];
+                    }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NFEAT; ++j)
+                    if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
+            }
             if (part == 0) {
                 meta_ok[r] = ok ? 1 : 0;
                 meta_kid[r] = kid;
