@@ -31,7 +31,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("widths", [(32, 64, 64, 1), (32, 256, 256, 256, 1), (32, 48, 24, 40, 1),
-                                    (32, 8, 1)])
+                                    (32, 8, 1), (32, 512, 512, 1), (32, 1024, 1)])
 def test_backward_fp32_matches_oracle(widths):
     f, y, mu, sd = _batch(1500, 301)
     p = workload.he_init(widths, 302, bias_scale=0.1)
@@ -52,6 +52,29 @@ def test_backward_fp32_matches_oracle(widths):
         k = widths[i + 1] * widths[i] + widths[i + 1]
         assert _rel(g[off:off + k], g_ref[off:off + k]) <= 1e-3
         off += k
+
+
+@pytest.mark.parametrize("widths", [(32, 64, 64, 1), (32, 256, 256, 1), (32, 1024, 1024, 1)])
+def test_backward_bf16_close_to_oracle(widths):
+    """bf16 activations and weights (8-bit mantissas) through forward and
+    backward, a ragged batch (1500 rows, padded to 1536 inside), every tile
+    width class of the backward kernel (64: fewer transposed units than
+    threads; 1024: 64-row tiles)."""
+    f, y, mu, sd = _batch(1500, 341)
+    p = workload.he_init(widths, 342, bias_scale=0.1)
+    m = adv.Model(widths, "bf16")
+    m.set_params(p, mu, sd)
+    yhat, saved = adv.advisor_mlp_forward(m.handle, to_dev(f))
+    n = f.shape[0]
+    dy = (2.0 * (yhat.double() - to_dev(y)) / n).float()
+    g = host(adv.advisor_mlp_backward(m.handle, dy, saved, n))
+    x = oracle.normalize(f, mu, sd)
+    loss_ref, g_ref = oracle.loss_grad(widths, p.astype(np.float64), x, y)
+    err = _rel(g, g_ref)
+    say("backward bf16 %s: rel grad err %.2e" % (widths, err))
+    assert np.isfinite(g).all()
+    # a few bf16 roundings (unit roundoff 2^-9) per product; measured ~2e-3
+    assert err <= 1e-2
 
 
 def _one_step(precision, widths, n, seed):
