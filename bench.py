@@ -296,7 +296,32 @@ def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_varian
     hi.close()
     return agree, {"train_steps": 400, "batch": 8192, "final_loss": final_loss,
                    "sample_kernels": int(ks.size), "sample_variants": int(rws.size),
-                   "pick_gap_ln_us_by_oracle_prediction": regret}
+                   "pick_gap_ln_us_by_oracle_prediction": regret,
+                   "top2_gap_ln_us_histogram": top2_gap_histogram(pred_cpu, best_cpu, sub_off)}
+
+
+def top2_gap_histogram(pred, best, off):
+    """Per kernel, the oracle's margin between its best and second-best
+    variant (ln us): how many kernels a low-precision ranking can only get
+    right by resolving a near-tie. Counts per bin [lo, hi)."""
+    edges = [0.0, 1e-6, 1e-4, 1e-3, 1e-2, 1e-1, np.inf]
+    gaps = []
+    for k in range(off.size - 1):
+        if best[k] < 0 or off[k + 1] - off[k] < 2:
+            continue
+        seg = pred[off[k]:off[k + 1]]
+        seg = seg[np.isfinite(seg)]
+        if seg.size < 2:
+            continue
+        two = np.partition(seg, 1)[:2]
+        gaps.append(float(two[1] - two[0]))
+    counts, _ = np.histogram(np.asarray(gaps), bins=edges)
+    names = ["0", "<1e-6", "<1e-4", "<1e-3", "<1e-2", "<1e-1", ">=1e-1"]
+    exact0 = int(np.sum(np.asarray(gaps) == 0.0))
+    out = {"exact_tie": exact0}
+    out.update({n: int(c) for n, c in zip(names[1:], counts)})
+    out["<1e-6"] -= exact0  # the first bin [0, 1e-6) includes the exact ties
+    return out
 
 
 def refine_k_for(precision, requested):
