@@ -127,6 +127,10 @@ struct TileArgs {
     void *save_x;
     void *save_h;
     int64_t save_ld;
+    // and, when not null, the ReLU masks of hidden layers 0 .. n_hidden-2:
+    // word [(l * W / 32 + b) * save_ld + row] has bit t set when neuron
+    // 32 b + t of layer l is positive (as stored) for that row
+    uint32_t *save_mask;
 };
 
 // Store one value of a saved activation (transposed layout) in precision P.
@@ -886,6 +890,7 @@ mlp_tiles_kernel(TileArgs args)
 #pragma unroll
                     for (int j = 0; j < C::MBW; ++j) {
                         const int m = (mb0 + j) * 32 + col;
+                        uint32_t mbits = 0;  // training: ReLU mask of this lane's 16 neurons
 #pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
@@ -895,6 +900,24 @@ mlp_tiles_kernel(TileArgs args)
                                 const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
                                                        : acc[i][j][4 * g + e];
                                 v[e] = z > 0.0f ? z : 0.0f;
+                            }
+                            if constexpr (SINK == SINK_TRAIN) {
+                                // from the value as stored (non-negative: any
+                                // non-zero bit pattern is positive)
+                                const typename Held<P>::T hv = pack4<P>(v, qinv);
+                                typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    bool pos;
+                                    if constexpr (P == PREC_FP32) {
+                                        pos = hv[e] > 0.0f;
+                                    } else {
+                                        // the four bf16 values as two words, low half first
+                                        const v2u_ u = __builtin_bit_cast(v2u_, hv);
+                                        pos = ((u[e >> 1] >> (16 * (e & 1))) & 0x7fffu) != 0;
+                                    }
+                                    mbits |= (pos ? 1u : 0u) << (8 * g + 4 * half + e);
+                                }
                             }
                             if (last) {
                                 // output layer: fixed order over blocks, groups, elements
@@ -907,6 +930,13 @@ mlp_tiles_kernel(TileArgs args)
                                 else
                                     held[final_pass ? 0 : ps][i][g][j] = pack4<P>(v, qinv);
                             }
+                        }
+                        if constexpr (SINK == SINK_TRAIN) {
+                            // the two lane halves hold the block's other 16 neurons
+                            const uint32_t word = mbits | (uint32_t)__shfl_xor((int)mbits, 32, 64);
+                            if (!last && args.save_mask != nullptr && half == 0)
+                                args.save_mask[((int64_t)l * (W / 32) + nbp0 + i) * args.save_ld +
+                                               row0 + m] = word;
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);

@@ -50,6 +50,7 @@ struct BwdArgs {
     const void *save_h;     // h_l^T, layer l at l * W * ld
     void *gt;               // g_l^T, layer l at l * W * ld
     float *head_part;       // [ld / M][M / (8 CE)][W + 1] output-layer gradient partials
+    const uint32_t *mask;   // ReLU masks of h_0 .. h_{L-2} recorded by the forward
     int64_t ld;
     int64_t n;
     int n_hidden;
@@ -173,8 +174,18 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
         for (int l = L - 1; l >= 1; --l) {
             layer_mma<P, W, C::NBW, C::MBW>(reinterpret_cast<const typename G::Vec *>(a.wt[l]),
                                             act, C::AS, nb0, mb0, lane, acc);
+            // the ReLU mask of h_{l-1} for this lane's outputs, as the forward
+            // recorded it: one word per (32-neuron block, row), this lane's
+            // neurons at bits 8 g + 4 half + e
+            uint32_t mw[C::NBW][C::MBW];
+#pragma unroll
+            for (int i = 0; i < C::NBW; ++i)
+#pragma unroll
+                for (int j = 0; j < C::MBW; ++j)
+                    mw[i][j] = a.mask[((int64_t)(l - 1) * (W / 32) + nb0 + i) * ld + row0 +
+                                      (mb0 + j) * 32 + col];
             __syncthreads();  // every wave has read g_l
-            // raw input gradients (sum_n g_l W_l) to LDS ...
+            // g_{l-1} = (sum_n g_l W_l) masked, to LDS for the next layer ...
 #pragma unroll
             for (int i = 0; i < C::NBW; ++i)
 #pragma unroll
@@ -185,61 +196,15 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
                         const int m = (mb0 + j) * 32 + col;
                         v4f v;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * g + e];
+                        for (int e = 0; e < 4; ++e)
+                            v[e] = (mw[i][j] >> (8 * g + 4 * half + e)) & 1u ? acc[i][j][4 * g + e] : 0.0f;
                         store4<P>(act + (size_t)m * C::AS, kk, v, 1.0f);
                     }
                 }
             __syncthreads();
-            // ... then the ReLU mask of h_{l-1}, written back for the next
-            // layer and out, transposed, for the weight gradients (the units
-            // and batching of the seed)
-            const T *Hp = H + (int64_t)(l - 1) * W * ld;
-            T *Gp = GT + (int64_t)(l - 1) * W * ld;
-            for (int i0 = 0; i0 < UPT; i0 += UB) {
-                v4i_ hraw[UB][2][4];
-#pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    int c = tid + (i0 + u) * C::THREADS;
-                    // recompute the unit's addresses here rather than keep
-                    // them live through the layer loop's multiplies
-                    asm volatile("" : "+v"(c));
-                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;
-                    int rg, nq, line;
-                    TU::decode(c, rg, nq, line);
-#pragma unroll
-                    for (int sidx = 0; sidx < 2; ++sidx)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            hraw[u][sidx][q] = *reinterpret_cast<const v4i_ *>(
-                                Hp + (int64_t)(nq * 4 + q) * ld + row0 + (rg + 4 * sidx) * CE);
-                }
-#pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    int c = tid + (i0 + u) * C::THREADS;
-                    // recompute the unit's addresses here rather than keep
-                    // them live through the layer loop's multiplies
-                    asm volatile("" : "+v"(c));
-                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;
-                    int rg, nq, line;
-                    TU::decode(c, rg, nq, line);
-#pragma unroll
-                    for (int sidx = 0; sidx < 2; ++sidx) {
-                        const int m0 = (rg + 4 * sidx) * CE;
-                        v4i_ gvec[4];
-                        lds_gather4<P>(act, C::AS, m0, nq, gvec);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const T *hv = reinterpret_cast<const T *>(&hraw[u][sidx][q]);
-                            T *gv = reinterpret_cast<T *>(&gvec[q]);
-#pragma unroll
-                            for (int e = 0; e < CE; ++e)
-                                if (!((float)hv[e] > 0.0f)) gv[e] = (T)0.0f;
-                            *reinterpret_cast<v4i_ *>(Gp + (int64_t)(nq * 4 + q) * ld + row0 + m0) = gvec[q];
-                        }
-                        if (l > 1) lds_scatter4<P>(act, C::AS, m0, nq, gvec);
-                    }
-                }
-            }
+            // ... and out, transposed, for the weight gradients
+            copy_act_transposed<P, W, M, C::THREADS, C::AS>(
+                act, GT + (int64_t)(l - 1) * W * ld, ld, row0, n, tid);
             __syncthreads();
         }
     }
@@ -608,11 +573,28 @@ static int splits_for(int na, int nb, int64_t ld)
     return s;
 }
 
-size_t saved_bytes(const advisor_model *m, int64_t n)
+// Saved forward state for a batch stride ld: x^T and h_l^T (compute
+// precision), then the ReLU mask words of h_0 .. h_{L-2} (one 32-bit word per
+// 32-neuron block and row).
+static size_t saved_mask_offset(const advisor_model *m, int64_t ld)
 {
-    const int64_t ld = ld_for(n);
     return (size_t)(NFEAT + (int64_t)m->n_hidden * m->tile_w) * ld * elem_bytes(m);
 }
+
+static size_t saved_bytes_ld(const advisor_model *m, int64_t ld)
+{
+    const int64_t masked = m->n_hidden > 1 ? m->n_hidden - 1 : 0;
+    return saved_mask_offset(m, ld) + (size_t)masked * (m->tile_w / 32) * ld * sizeof(uint32_t);
+}
+
+static uint32_t *saved_masks(const advisor_model *m, const void *saved, int64_t ld)
+{
+    if (m->n_hidden < 2) return nullptr;
+    return reinterpret_cast<uint32_t *>(const_cast<unsigned char *>(
+        reinterpret_cast<const unsigned char *>(saved) + saved_mask_offset(m, ld)));
+}
+
+size_t saved_bytes(const advisor_model *m, int64_t n) { return saved_bytes_ld(m, ld_for(n)); }
 
 TrainWs *train_ws(advisor_model *m) { return reinterpret_cast<TrainWs *>(m->train_ws); }
 
@@ -662,7 +644,7 @@ static int ensure_ws(advisor_model *m, int64_t n, bool with_saved)
                           sizeof(float) * (size_t)head_blocks(m, newld) * (m->tile_w + 1)));
         ADV_HIP(hipMalloc((void **)&w->pred, sizeof(float) * newld));
         ADV_HIP(hipMalloc((void **)&w->dy, sizeof(float) * newld));
-        ADV_HIP(hipMalloc(&w->saved, (size_t)(NFEAT + (int64_t)m->n_hidden * m->tile_w) * newld * eb));
+        ADV_HIP(hipMalloc(&w->saved, saved_bytes_ld(m, newld)));
         w->ld = newld;
     }
     return ADVISOR_OK;
@@ -783,6 +765,7 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
     a.head_part = w->head_part;
     for (int l = 1; l < L; ++l) a.wt[l] = w->wt[l];
     a.save_h = hs;
+    a.mask = saved_masks(m, saved, ld);
     a.gt = w->gt;
     a.ld = ld;
     a.n = n;
@@ -881,6 +864,7 @@ extern "C" int advisor_mlp_forward(advisor_model *m, const int64_t *feat, int64_
     a.save_ld = ld;
     a.save_x = saved;
     a.save_h = reinterpret_cast<unsigned char *>(saved) + (size_t)NFEAT * ld * elem_bytes(m);
+    a.save_mask = saved_masks(m, saved, ld);
     return launch_train_forward(m, a, as_stream(stream));
 }
 
@@ -929,6 +913,7 @@ extern "C" int advisor_train_step(advisor_model *m, const int64_t *feat, const d
     a.save_ld = ld;
     a.save_x = w->saved;
     a.save_h = reinterpret_cast<unsigned char *>(w->saved) + (size_t)NFEAT * ld * elem_bytes(m);
+    a.save_mask = saved_masks(m, w->saved, ld);
     rc = launch_train_forward(m, a, s);
     if (rc) return rc;
     // float64 MSE and dL/dyhat
