@@ -904,20 +904,24 @@ mlp_tiles_kernel(TileArgs args)
                             if constexpr (SINK == SINK_TRAIN) {
                                 // from the value as stored (non-negative: any
                                 // non-zero bit pattern is positive)
+                                // the stored values are >= 0 (never -0): positive
+                                // exactly when their bit pattern is non-zero, and
+                                // min(bits, 1) is that bit
                                 const typename Held<P>::T hv = pack4<P>(v, qinv);
-                                typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
+                                uint32_t nib;
+                                if constexpr (P == PREC_FP32) {
+                                    nib = 0;
 #pragma unroll
-                                for (int e = 0; e < 4; ++e) {
-                                    bool pos;
-                                    if constexpr (P == PREC_FP32) {
-                                        pos = hv[e] > 0.0f;
-                                    } else {
-                                        // the four bf16 values as two words, low half first
-                                        const v2u_ u = __builtin_bit_cast(v2u_, hv);
-                                        pos = ((u[e >> 1] >> (16 * (e & 1))) & 0x7fffu) != 0;
-                                    }
-                                    mbits |= (pos ? 1u : 0u) << (8 * g + 4 * half + e);
+                                    for (int e = 0; e < 4; ++e)
+                                        nib |= min(__float_as_uint(hv[e]), 1u) << e;
+                                } else {
+                                    // the four bf16 values as two words, low half first
+                                    typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
+                                    const v2u_ u = __builtin_bit_cast(v2u_, hv);
+                                    nib = min(u[0] & 0xffffu, 1u) | (min(u[0] >> 16, 1u) << 1) |
+                                          (min(u[1] & 0xffffu, 1u) << 2) | (min(u[1] >> 16, 1u) << 3);
                                 }
+                                mbits |= nib << (8 * g + 4 * half);
                             }
                             if (last) {
                                 // output layer: fixed order over blocks, groups, elements

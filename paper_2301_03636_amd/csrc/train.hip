@@ -414,12 +414,46 @@ __global__ void wgrad_reduce_kernel(const float *__restrict__ partial,
     float s = 0.0f;
     if (idx < nw) {
         const int nn = (int)(idx / in), kk = (int)(idx % in);
-        for (int q = 0; q < splits; ++q) s += partial[((int64_t)q * na + nn) * nb + kk];
+        const float *p = partial + (int64_t)nn * nb + kk;
+        const int64_t step = (int64_t)na * nb;
+#pragma unroll 8
+        for (int q = 0; q < splits; ++q) s += p[q * step];
     } else {
         const int nn = (int)(idx - nw);
+#pragma unroll 8
         for (int q = 0; q < splits; ++q) s += partial_b[(int64_t)q * na + nn];
     }
     grads[idx] = s;
+}
+
+// The same sums four consecutive weights at a time (16-byte loads and
+// stores) where the layer's row lengths allow it (in and nb multiples of 4).
+__global__ void wgrad_reduce4_kernel(const float *__restrict__ partial,
+                                     const float *__restrict__ partial_b, int splits, int na,
+                                     int nb, int out, int in, float *__restrict__ grads)
+{
+    const int64_t idx4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nw4 = (int64_t)out * in / 4;
+    if (idx4 < nw4) {
+        const int64_t idx = idx4 * 4;
+        const int nn = (int)(idx / in), kk = (int)(idx % in);
+        const v4f *p = reinterpret_cast<const v4f *>(partial + (int64_t)nn * nb + kk);
+        const int64_t step = (int64_t)na * nb / 4;
+        v4f s = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 8
+        for (int q = 0; q < splits; ++q) {
+            const v4f t = p[q * step];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s[e] += t[e];
+        }
+        *reinterpret_cast<v4f *>(grads + idx) = s;
+    } else if (idx4 < nw4 + out) {
+        const int nn = (int)(idx4 - nw4);
+        float s = 0.0f;
+#pragma unroll 8
+        for (int q = 0; q < splits; ++q) s += partial_b[(int64_t)q * na + nn];
+        grads[nw4 * 4 + nn] = s;
+    }
 }
 
 // Output-layer gradient from the backward seed's partials, one workgroup
@@ -806,8 +840,14 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         // g^T's rows over the batch; rows past n are zero)
         float *gw = grads + m->layer_off[l];
         const int64_t ne = (int64_t)out * in + out;
-        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
-                           w->partial, partial_b, splits, na, nb, out, in, gw);
+        if (in % 4 == 0 && nb % 4 == 0 && ((uintptr_t)gw & 15) == 0) {
+            const int64_t ne4 = (int64_t)out * in / 4 + out;
+            hipLaunchKernelGGL(wgrad_reduce4_kernel, dim3((unsigned)((ne4 + 255) / 256)), dim3(256), 0,
+                               s, w->partial, partial_b, splits, na, nb, out, in, gw);
+        } else {
+            hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
+                               w->partial, partial_b, splits, na, nb, out, in, gw);
+        }
         ADV_LAUNCHED("wgrad_reduce_kernel");
     }
     return ADVISOR_OK;
