@@ -237,7 +237,11 @@ int advisor_rank_preds(const float *pred, const int64_t *offsets, int64_t n_kern
  * that grows (synchronous hipMalloc) to the largest batch seen.
  *
  * advisor_mlp_saved_bytes: size of the buffer advisor_mlp_forward fills for a
- * batch of n rows (the transposed inputs and hidden activations), or -1.
+ * batch of n rows (the transposed inputs and hidden activations and the
+ * hidden layers' ReLU masks; its layout is the library's), or -1.
+ *
+ * advisor_mlp_backward stages dy in the model's workspace (a copy of n
+ * floats on the stream) before its kernels read it.
  */
 int64_t advisor_mlp_saved_bytes(const advisor_model *model, int64_t n);
 
