@@ -595,16 +595,44 @@ __device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, i
     const NetView &net = args.net;
     const int64_t n = args.n_rows;
     {
-        // with M a multiple of 64 a wave's threads share one part: make that
-        // known to the compiler, so picking the part's features below is a
-        // scalar branch instead of a per-lane select over all 32 features
+        // with M a multiple of 64 a wave's threads share one part: made known
+        // to the compiler, the part becomes a scalar branch below
         const int r = tid % M;
         const int part = M % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / M) : tid / M;
         const int64_t row = row0 + r;
         const bool inrow = row < n;
         uint64_t fsel[C::FPP];
         bool ok = inrow;
-        if constexpr (SRC == SRC_DESC) {
+        if constexpr (SRC == SRC_DESC && M % 64 == 0) {
+            // one copy of the feature code per part: each copy keeps only the
+            // arithmetic its FPP features need (the 64-bit division of the
+            // launch-wave count, for one, lives in a single part), and only
+            // part 0 checks the kernel segment it records in meta_ok (the
+            // other parts' inputs of a row that fails it are never used)
+            int kid = -1;
+#pragma unroll
+            for (int q = 0; q < C::FPP; ++q) fsel[q] = 0;
+#pragma unroll
+            for (int p = 0; p < C::PARTS; ++p)
+                if (part == p && inrow) {
+                    const int64_t *vrow = VPF ? reinterpret_cast<const int64_t *>(vst + (size_t)r * 64)
+                                              : args.vdesc + row * VD;
+                    Feat f;
+                    ok = featurize_one(args.kdesc, vrow, args.n_k, f);
+#pragma unroll
+                    for (int q = 0; q < C::FPP; ++q) fsel[q] = f.f[p * C::FPP + q];
+                    if (p == 0) {
+                        const int64_t k = vrow[0];
+                        kid = (int)k;  // in [0, n_k) when ok, and n_k < 2^31
+                        if (SINK == SINK_RANK && ok)  // the variant must sit in its kernel's segment
+                            ok = args.offsets[k] <= row && row < args.offsets[k + 1];
+                    }
+                }
+            if (part == 0) {
+                meta_ok[r] = ok ? 1 : 0;
+                meta_kid[r] = kid;
+            }
+        } else if constexpr (SRC == SRC_DESC) {
             Feat f;
             int kid = -1;
             if (inrow) {
@@ -622,18 +650,9 @@ __device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, i
             // this thread's FPP features (part is not a compile-time value)
 #pragma unroll
             for (int q = 0; q < C::FPP; ++q) fsel[q] = 0;
-            if constexpr (M % 64 == 0) {
 #pragma unroll
-                for (int p = 0; p < C::PARTS; ++p)
-                    if (part == p) {
-#pragma unroll
-                        for (int q = 0; q < C::FPP; ++q) fsel[q] = f.f[p * C::FPP + q];
-                    }
-            } else {
-#pragma unroll
-                for (int j = 0; j < NFEAT; ++j)
-                    if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
-            }
+            for (int j = 0; j < NFEAT; ++j)
+                if (j / C::FPP == part) fsel[j % C::FPP] = f.f[j];
             if (part == 0) {
                 meta_ok[r] = ok ? 1 : 0;
                 meta_kid[r] = kid;
