@@ -285,6 +285,11 @@ def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_varian
         rk = refine_k_for(p, refine_k)
         if p != "fp32" and rk > 0:
             picks[p + "_refined"] = g.rank_refined(hi, K, V, O, top_k=rk).cpu().numpy()
+            if p == "fp8":
+                mid = adv.Model(widths, "bf16")
+                mid.set_params(w, mu, sd)
+                picks["fp8_refined_bf16"] = g.rank_refined(mid, K, V, O, top_k=rk).cpu().numpy()
+                mid.close()
         g.close()
         for name, best_gpu in picks.items():
             agree[name] = float(np.mean(best_gpu == best_cpu))
@@ -484,6 +489,21 @@ def main():
             best_by_prec[p + "_refined"] = bref.cpu().numpy()
             results[p]["refined"] = dict(top_k=rk, ms_per_step=rms, value=nv / (rms / 1e3))
             hi.close()
+            if p == "fp8":
+                # the cheaper second stage: the fp8 model's top-k re-ranked in bf16
+                mid = adv.Model(widths, "bf16")
+                mid.set_params(params, mu, sd)
+                for _ in range(args.warmup):
+                    m.rank_refined(mid, kdd, vdd, offd, top_k=rk, best_out=bref)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(nsteps):
+                    m.rank_refined(mid, kdd, vdd, offd, top_k=rk, best_out=bref)
+                torch.cuda.synchronize()
+                rms = (time.perf_counter() - t0) * 1e3 / nsteps
+                best_by_prec["fp8_refined_bf16"] = bref.cpu().numpy()
+                results[p]["refined_bf16"] = dict(top_k=rk, ms_per_step=rms, value=nv / (rms / 1e3))
+                mid.close()
         m.close()
     del feat_cal, inv_cal
 
@@ -537,7 +557,10 @@ def main():
             "argmin_agreement_trained_network": agree_t.get(p),
             "refined_by_fp32": None if "refined" not in r else dict(
                 r["refined"], argmin_agreement_vs_oracle_sample=agree.get(p + "_refined"),
-                argmin_agreement_trained_network=agree_t.get(p + "_refined"))}
+                argmin_agreement_trained_network=agree_t.get(p + "_refined")),
+            "refined_by_bf16": None if "refined_bf16" not in r else dict(
+                r["refined_bf16"], argmin_agreement_vs_oracle_sample=agree.get(p + "_refined_bf16"),
+                argmin_agreement_trained_network=agree_t.get(p + "_refined_bf16"))}
         for p, r in results.items()}
     if args.train_steps > 0:
         out["train"] = train_leg(adv, torch, d, args.train_steps, args.warmup)
