@@ -186,3 +186,36 @@ def test_rank_empty_and_tiny():
     best_ref, _ = oracle.rank(kd, vd, off, widths, p, mu, sd)
     best = m.rank(to_dev(kd), to_dev(vd), to_dev(off))
     assert host(best).tolist() == best_ref.tolist()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_rank_segments_spanning_many_tiles(precision):
+    """Kernels whose variants span thousands of tiles (and tiles holding the
+    ends of several kernels): the fused argmin, folded per tile and run and
+    merged by atomics across workgroups, must equal the exact segment argmin
+    of the same call's own predictions, with the winner inside its segment."""
+    widths = (32, 64, 64, 1)
+    rng = np.random.default_rng(91)
+    counts = np.array([700000, 1, 0, 3, 300001, 129, 0, 64], dtype=np.int64)
+    nk = counts.size
+    kd, vd, _ = workload.make_descriptors(nk, 16, 17, 92)
+    # variant rows drawn from a small pool, so exact ties recur across tiles
+    pool = np.concatenate([vd[vd[:, 0] == k][:8] for k in range(nk)])
+    rows = []
+    for k, c in enumerate(counts):
+        mine = pool[pool[:, 0] == k]
+        rows.append(mine[rng.integers(0, mine.shape[0], c)])
+    V = np.concatenate(rows)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    m, p, mu, sd = _model(widths, precision, 93, kd, V)
+    pred = torch.empty(V.shape[0], dtype=torch.float32, device="cuda")
+    best_t, _ = m.rank(to_dev(kd), to_dev(V), to_dev(off), pred_out=pred)
+    best = host(best_t)
+    ref = segment_argmin(host(pred), off)
+    say("%s rank over segments of up to %d variants: %s" % (precision, counts.max(), best.tolist()))
+    assert best.tolist() == ref.tolist()
+    for k in range(nk):
+        if best[k] >= 0:
+            assert off[k] <= best[k] < off[k + 1]
+        else:
+            assert counts[k] == 0 or np.isnan(host(pred)[off[k]:off[k + 1]]).all()
