@@ -65,12 +65,11 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
     constexpr int CE = 16 / (int)sizeof(T);  // elements per 16-byte run
     constexpr int RG = M / CE;                // row groups of a tile
     static_assert(RG % 8 == 0, "row groups come in eights");
-    // seed and mask passes work in the transposed units of TUnits: UPT units
-    // per thread (or one for the first UNITS threads), UB of them with their
-    // loads in flight together
+    // the seed pass works in the transposed units of TUnits: UPT units per
+    // thread (or one for the first UNITS threads, whole waves), each with
+    // all its loads issued before any is used
     using TU = TUnits<P, W, M, C::THREADS>;
     constexpr int UPT = TU::UNITS >= C::THREADS ? TU::UNITS / C::THREADS : 1;
-    constexpr int UB = 1;
     typedef int v4i_ __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *act = lds;  // [M][AS]
@@ -95,77 +94,63 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
         {
             const T *Hl = H + (int64_t)(L - 1) * W * ld;
             T *Gl = GT + (int64_t)(L - 1) * W * ld;
-            for (int i0 = 0; i0 < UPT; i0 += UB) {
-                v4i_ hraw[UB][2][4], draw[UB][2][CE / 4];
-                v4f hw4[UB];
+            for (int i = 0; i < UPT; ++i) {
+                int c = tid + i * C::THREADS;
+                // recompute the unit's addresses here rather than keep them
+                // live through the layer loop's multiplies
+                asm volatile("" : "+v"(c));
+                if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;  // whole waves
+                int rg, nq, line;
+                TU::decode(c, rg, nq, line);
+                v4i_ hraw[2][4], draw[2][CE / 4];
 #pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    int c = tid + (i0 + u) * C::THREADS;
-                    // recompute the unit's addresses here rather than keep
-                    // them live through the layer loop's multiplies
-                    asm volatile("" : "+v"(c));
-                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;  // whole waves
-                    int rg, nq, line;
-                    TU::decode(c, rg, nq, line);
+                for (int sidx = 0; sidx < 2; ++sidx) {
+                    const int64_t r0 = row0 + (rg + 4 * sidx) * CE;
 #pragma unroll
-                    for (int sidx = 0; sidx < 2; ++sidx) {
-                        const int64_t r0 = row0 + (rg + 4 * sidx) * CE;
+                    for (int q = 0; q < 4; ++q)
+                        hraw[sidx][q] = *reinterpret_cast<const v4i_ *>(Hl + (int64_t)(nq * 4 + q) * ld + r0);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            hraw[u][sidx][q] = *reinterpret_cast<const v4i_ *>(Hl + (int64_t)(nq * 4 + q) * ld + r0);
-#pragma unroll
-                        for (int q = 0; q < CE / 4; ++q)
-                            draw[u][sidx][q] = *reinterpret_cast<const v4i_ *>(a.dy + r0 + 4 * q);
-                    }
-                    hw4[u] = *reinterpret_cast<const v4f *>(a.head_w + nq * 4);
+                    for (int q = 0; q < CE / 4; ++q)
+                        draw[sidx][q] = *reinterpret_cast<const v4i_ *>(a.dy + r0 + 4 * q);
                 }
+                const v4f hw4 = *reinterpret_cast<const v4f *>(a.head_w + nq * 4);
+                float sdh[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sd = 0.0f;
 #pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    int c = tid + (i0 + u) * C::THREADS;
-                    // recompute the unit's addresses here rather than keep
-                    // them live through the layer loop's multiplies
-                    asm volatile("" : "+v"(c));
-                    if (TU::UNITS < C::THREADS && c >= TU::UNITS) break;
-                    int rg, nq, line;
-                    TU::decode(c, rg, nq, line);
-                    float sdh[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sd = 0.0f;
+                for (int sidx = 0; sidx < 2; ++sidx) {
+                    const int m0 = (rg + 4 * sidx) * CE;
+                    const int64_t r0 = row0 + m0;
+                    const float *dv = reinterpret_cast<const float *>(&draw[sidx][0]);
+                    v4i_ gvec[4];
 #pragma unroll
-                    for (int sidx = 0; sidx < 2; ++sidx) {
-                        const int m0 = (rg + 4 * sidx) * CE;
-                        const int64_t r0 = row0 + m0;
-                        const float *dv = reinterpret_cast<const float *>(&draw[u][sidx][0]);
-                        v4i_ gvec[4];
+                    for (int q = 0; q < 4; ++q) {
+                        const T *hv = reinterpret_cast<const T *>(&hraw[sidx][q]);
+                        T *gv = reinterpret_cast<T *>(&gvec[q]);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const T *hv = reinterpret_cast<const T *>(&hraw[u][sidx][q]);
-                            T *gv = reinterpret_cast<T *>(&gvec[q]);
-#pragma unroll
-                            for (int e = 0; e < CE; ++e) {
-                                const float d = r0 + e < n ? dv[e] : 0.0f;
-                                const float h = (float)hv[e];
-                                gv[e] = (T)(h > 0.0f ? d * hw4[u][q] : 0.0f);
-                                sdh[q] += d * h;
-                            }
-                            *reinterpret_cast<v4i_ *>(Gl + (int64_t)(nq * 4 + q) * ld + r0) = gvec[q];
+                        for (int e = 0; e < CE; ++e) {
+                            const float d = r0 + e < n ? dv[e] : 0.0f;
+                            const float h = (float)hv[e];
+                            gv[e] = (T)(h > 0.0f ? d * hw4[q] : 0.0f);
+                            sdh[q] += d * h;
                         }
-#pragma unroll
-                        for (int e = 0; e < CE; ++e) sd += r0 + e < n ? dv[e] : 0.0f;
-                        lds_scatter4<P>(act, C::AS, m0, nq, gvec);
+                        *reinterpret_cast<v4i_ *>(Gl + (int64_t)(nq * 4 + q) * ld + r0) = gvec[q];
                     }
-                    // the four lanes of a line block's other row groups; one
-                    // partial per (tile, line block, neuron), reduced in order
-                    // by head_reduce_kernel
 #pragma unroll
-                    for (int off = 1; off < 4; off <<= 1) {
+                    for (int e = 0; e < CE; ++e) sd += r0 + e < n ? dv[e] : 0.0f;
+                    lds_scatter4<P>(act, C::AS, m0, nq, gvec);
+                }
+                // the four lanes of a line block's other row groups; one
+                // partial per (tile, line block, neuron), reduced in order by
+                // head_reduce_kernel
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) sdh[q] += __shfl_xor(sdh[q], off, 64);
-                        sd += __shfl_xor(sd, off, 64);
-                    }
-                    if ((c & 3) == 0) {
-                        float *hp = a.head_part + ((int64_t)tile * (RG / 8) + line) * (W + 1);
-                        *reinterpret_cast<v4f *>(hp + nq * 4) = v4f{sdh[0], sdh[1], sdh[2], sdh[3]};
-                        if (nq == 0) hp[W] = sd;
-                    }
+                for (int off = 1; off < 4; off <<= 1) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sdh[q] += __shfl_xor(sdh[q], off, 64);
+                    sd += __shfl_xor(sd, off, 64);
+                }
+                if ((c & 3) == 0) {
+                    float *hp = a.head_part + ((int64_t)tile * (RG / 8) + line) * (W + 1);
+                    *reinterpret_cast<v4f *>(hp + nq * 4) = v4f{sdh[0], sdh[1], sdh[2], sdh[3]};
+                    if (nq == 0) hp[W] = sd;
                 }
             }
         }
