@@ -374,10 +374,40 @@ def train_leg(adv, torch, d, steps, warmup):
     m.close()
     fps = train_flops_per_sample(widths)
     tflops = fps * B / (ms / 1e3) / 1e12
+    nbytes = train_bytes_per_step(widths, B, m_params=sum(
+        widths[i] * widths[i + 1] + widths[i + 1] for i in range(len(widths) - 1)))
     return {"workload": "batch 65536 of 4096 kernels, 32-512x4-1, bf16, Adam",
             "steps_per_s": 1e3 / ms, "samples_per_s": B / (ms / 1e3), "ms_per_step": ms,
             "flops_per_sample": fps, "tflops": tflops, "peak": PEAK_TFLOPS["bf16"],
-            "roofline_frac": tflops / PEAK_TFLOPS["bf16"], "loss_last": float(loss.item())}
+            "roofline_frac": tflops / PEAK_TFLOPS["bf16"],
+            "hbm_bytes_per_step": nbytes, "hbm_gbs": nbytes / (ms / 1e3) / 1e9,
+            "hbm_frac": nbytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "loss_last": float(loss.item())}
+
+
+def train_bytes_per_step(widths, batch, m_params):
+    """HBM bytes one bf16 training step of this design moves (saved state
+    written by the forward and read back, transposed gradients written and
+    read, split-K partials, optimizer state), as a second roofline for the
+    step beside its flops: the step alternates matrix-core and memory phases."""
+    nf, L, W = widths[0], len(widths) - 2, widths[1]
+    eb = 2
+    per_row = (nf * 8                       # features in (int64)
+               + nf * eb + L * W * eb        # saved x^T, h_l^T
+               + (L - 1) * (W // 32) * 4     # ReLU mask words
+               + 4 + 8 + 4 + 4               # pred, y, dy written and read
+               + W * eb + 4                  # seed: h_{L-1}^T and dy in
+               + L * W * eb                  # g_l^T out
+               + (L - 1) * (W // 32) * 4     # masks in
+               + L * W * eb + nf * eb + (L - 1) * W * eb)  # weight gradients: g^T, x^T, h^T in
+    def splits(na, nb, cus=256):  # the library's split rule on a 256-CU device
+        tiles, s = -(-na // 128) * -(-nb // 128), 1
+        while tiles * s < 2 * cus and s < 64:
+            s *= 2
+        return s
+    partials = 2 * 4 * (splits(W, nf) * W * nf + (L - 1) * splits(W, W) * W * W)  # written, read back
+    optimizer = m_params * 4 * 7                               # grad, master, m, v in; master, m, v out
+    return int(per_row * batch + partials + optimizer)
 
 
 def main():
