@@ -323,6 +323,21 @@ int advisor_plan_launch(advisor_plan *plan, void *stream);
 void advisor_plan_destroy(advisor_plan *plan);
 
 /*
+ * Checks that offsets (device, int64 [n_kernels + 1]) segments n_variants
+ * variants: offsets[0] = 0, non-decreasing, offsets[n_kernels] = n_variants
+ * (section 4.1.1 files every variant under one kernel). Returns ADVISOR_OK,
+ * or ADVISOR_ESHAPE with *first_bad (host, may be NULL; -1 when valid) set to
+ * the lowest offending index. Synchronizes the stream and allocates 8 bytes.
+ * The ranking calls never read outside their arrays on malformed offsets
+ * (they clamp), but their results are then meaningless; setting the
+ * environment variable ADVISOR_DEBUG_OFFSETS=1 makes advisor_rank,
+ * advisor_rank_preds and advisor_rank_refined run this check first (not
+ * while the stream is being captured) and fail with its status.
+ */
+int advisor_validate_offsets(const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
+                             int64_t *first_bad, void *stream);
+
+/*
  * Measurement aid (not part of the method): while enabled, every launch of
  * the fused tile kernel (advisor_rank, advisor_predict) is bracketed by a
  * pair of HIP events recorded on the caller's stream. advisor_profile_read

@@ -76,6 +76,7 @@ def lib():
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
             "advisor_mfma_peak": ([i32, i64, i32, C.POINTER(C.c_double), P], i32),
+            "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -263,6 +264,19 @@ def advisor_rank_refined(h, refine, kdesc, vdesc, offsets, top_k=8, best_out=Non
                                       int(top_k), _ptr(best_out), _ptr(pred_out), _stream()),
            "advisor_rank_refined")
     return best_out
+
+
+def advisor_validate_offsets(offsets, n_variants):
+    """-1 when offsets (device int64 [n_k + 1]) segments n_variants rows,
+    else the lowest offending index (the library also reports ADVISOR_ESHAPE,
+    which this wrapper turns into the index rather than an exception)."""
+    _dev(offsets, torch.int64, "offsets")
+    bad = C.c_int64(-1)
+    rc = lib().advisor_validate_offsets(_ptr(offsets), offsets.shape[0] - 1, int(n_variants),
+                                        C.byref(bad), _stream())
+    if rc not in (0, -2):
+        _check(rc, "advisor_validate_offsets")
+    return bad.value
 
 
 def advisor_rank_preds(pred, offsets, best_out=None):

@@ -52,6 +52,9 @@ int prepare_train_kernels(int precision, int tile_w);
 // True while `s` is being captured into a graph.
 bool stream_capturing(hipStream_t s);
 
+// Whether the ranking calls check their offsets first (select.hip).
+bool debug_offsets(hipStream_t s);
+
 // Whether tile shape V is built for this precision and width (mlp.hip).
 bool tile_shape_exists(int precision, int W, int V);
 

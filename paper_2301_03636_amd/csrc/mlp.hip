@@ -313,6 +313,9 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
     if (!kdesc || !offsets || !best_out || (n_variants > 0 && !vdesc))
         return fail(ADVISOR_EINVAL, "advisor_rank: null pointer");
     hipStream_t s = as_stream(stream);
+    if (debug_offsets(s)) {
+        if (int rc2 = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, stream)) return rc2;
+    }
     const unsigned kb = (unsigned)((n_kernels + 255) / 256);
     hipLaunchKernelGGL(keys_init_kernel, dim3(kb), dim3(256), 0, s,
                        reinterpret_cast<uint64_t *>(best_out), n_kernels);

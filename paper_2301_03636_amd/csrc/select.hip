@@ -3,6 +3,9 @@
 // bandwidth-bound and use no matrix cores.
 #include <algorithm>
 
+#include <cstdlib>
+#include <string>
+
 #include "features.h"
 
 namespace adv {
@@ -169,9 +172,61 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
     }
 }
 
+// The kernel segments are well formed when offsets[0] = 0, offsets[n_k] =
+// n_v and offsets[i] <= offsets[i + 1]; first_bad gets the lowest index
+// whose entry breaks that (a 64-bit vector atomic min, starting at ~0).
+__global__ void offsets_check_kernel(const int64_t *__restrict__ off, int64_t n_k, int64_t n_v,
+                                     unsigned long long *__restrict__ first_bad)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n_k; i += stride) {
+        const int64_t v = off[i];
+        const bool bad = (i == 0 && v != 0) || (i == n_k && v != n_v) || (i < n_k && v > off[i + 1]);
+        if (bad) atomicMin(first_bad, (unsigned long long)i);
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v) { *p = v; }
+
+// Opt-in checking of the segments before a ranking call: the environment
+// variable ADVISOR_DEBUG_OFFSETS set to a non-empty value other than "0"
+// (read at every call; skipped while the stream is being captured).
+bool debug_offsets(hipStream_t s)
+{
+    const char *e = getenv("ADVISOR_DEBUG_OFFSETS");
+    return e && e[0] && !(e[0] == '0' && e[1] == 0) && !stream_capturing(s);
+}
+
 }  // namespace adv
 
 using namespace adv;
+
+extern "C" int advisor_validate_offsets(const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
+                                        int64_t *first_bad, void *stream)
+{
+    clear_error();
+    if (first_bad) *first_bad = -1;
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (!offsets) return fail(ADVISOR_EINVAL, "advisor_validate_offsets: null offsets");
+    hipStream_t s = as_stream(stream);
+    unsigned long long *d = nullptr;
+    ADV_HIP(hipMalloc((void **)&d, sizeof(unsigned long long)));
+    unsigned long long h = ~0ull;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(1), 0, s, d, ~0ull);
+    const int64_t blocks = std::min<int64_t>((n_kernels + 1 + 255) / 256, 4096);
+    hipLaunchKernelGGL(offsets_check_kernel, dim3((unsigned)blocks), dim3(256), 0, s, offsets,
+                       n_kernels, n_variants, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "offsets check");
+    if (h == ~0ull) return ADVISOR_OK;
+    if (first_bad) *first_bad = (int64_t)h;
+    return fail(ADVISOR_ESHAPE, "offsets are not a segmentation of the variants: first bad entry " +
+                                    std::to_string((long long)h) +
+                                    " (need offsets[0] = 0, non-decreasing, offsets[n_kernels] = n_variants)");
+}
 
 extern "C" int advisor_featurize(const int64_t *kdesc, const int64_t *vdesc, int64_t n_kernels,
                                  int64_t n_variants, int64_t *feat_out, uint8_t *invalid_out,
@@ -233,6 +288,9 @@ extern "C" int advisor_rank_preds(const float *pred, const int64_t *offsets, int
     if (n_kernels == 0) return ADVISOR_OK;
     if (!offsets || !best_out || (n_variants > 0 && !pred))
         return fail(ADVISOR_EINVAL, "advisor_rank_preds: null pointer");
+    if (debug_offsets(as_stream(stream))) {
+        if (int rc = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, stream)) return rc;
+    }
     const int64_t blocks = std::min<int64_t>((n_kernels + AM_WAVES - 1) / AM_WAVES, 1 << 20);
     hipLaunchKernelGGL(argmin_preds_kernel, dim3((unsigned)blocks), dim3(AM_WAVES * 64), 0,
                        as_stream(stream), pred, offsets, n_kernels, n_variants, best_out);

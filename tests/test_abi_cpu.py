@@ -107,3 +107,11 @@ def test_mfma_peak_argument_checks():
     assert L.advisor_mfma_peak(1, (1 << 24) + 1, 1, C.byref(out), None) == EINVAL
     assert L.advisor_mfma_peak(2, 10, 0, C.byref(out), None) == EINVAL
     assert L.advisor_mfma_peak(2, 10, 9, C.byref(out), None) == EINVAL
+
+
+def test_validate_offsets_argument_checks():
+    L = _lib.lib()
+    bad = C.c_int64(7)
+    assert L.advisor_validate_offsets(None, 3, 10, C.byref(bad), None) == EINVAL
+    assert bad.value == -1
+    assert L.advisor_validate_offsets(C.c_void_p(8), -1, 10, C.byref(bad), None) == ESHAPE

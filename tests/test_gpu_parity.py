@@ -219,3 +219,34 @@ def test_rank_segments_spanning_many_tiles(precision):
             assert off[k] <= best[k] < off[k + 1]
         else:
             assert counts[k] == 0 or np.isnan(host(pred)[off[k]:off[k + 1]]).all()
+
+
+def test_validate_offsets_and_debug_mode(monkeypatch):
+    """The segmentation check names the lowest offending entry; with
+    ADVISOR_DEBUG_OFFSETS set the ranking calls fail on malformed offsets
+    instead of ranking them."""
+    good = np.array([0, 3, 3, 10], dtype=np.int64)
+    assert adv.advisor_validate_offsets(to_dev(good), 10) == -1
+    assert adv.advisor_validate_offsets(to_dev(good), 11) == 3          # last != n_v
+    assert adv.advisor_validate_offsets(to_dev(np.array([1, 3, 3, 10])), 10) == 0
+    assert adv.advisor_validate_offsets(to_dev(np.array([0, 5, 3, 10])), 10) == 1
+    assert adv.advisor_validate_offsets(to_dev(np.zeros(1, dtype=np.int64)), 0) == -1
+    big = np.arange(0, 200001, dtype=np.int64)
+    big[150000] = big[149999] - 1                                       # dips below its left neighbour
+    assert adv.advisor_validate_offsets(to_dev(big), 200000) == 149999
+    widths = (32, 64, 64, 1)
+    kd, vd, off = _desc(3, 4, 9, seed=95)
+    m, p, mu, sd = _model(widths, "fp32", 96, kd, vd)
+    bad_off = off.copy()
+    bad_off[1], bad_off[2] = bad_off[2], bad_off[1]
+    if bad_off[1] == bad_off[2]:
+        bad_off[1] += 1
+    monkeypatch.setenv("ADVISOR_DEBUG_OFFSETS", "1")
+    m.rank(to_dev(kd), to_dev(vd), to_dev(off))                         # valid: ranks
+    with pytest.raises(adv.AdvisorError):
+        m.rank(to_dev(kd), to_dev(vd), to_dev(bad_off))
+    with pytest.raises(adv.AdvisorError):
+        adv.advisor_rank_preds(torch.zeros(vd.shape[0], device="cuda"), to_dev(bad_off))
+    monkeypatch.setenv("ADVISOR_DEBUG_OFFSETS", "0")
+    m.rank(to_dev(kd), to_dev(vd), to_dev(bad_off))                     # unchecked: clamps, no error
+    m.close()
