@@ -564,6 +564,8 @@ def main():
                      "replay_ms": main_r["replay_ms"],
                      "mfma_peak_measured": main_r["mfma_peak_measured"]},
     }
+    # variants/s per replay: p10 of the rate is the p90 of the duration
+    out["value_p10_p50_p90"] = [nv / (main_r["replay_ms"][q] / 1e3) for q in ("p90", "p50", "p10")]
     if "with_transfers" in main_r:
         out["with_transfers"] = main_r["with_transfers"]
     if args.stages:
