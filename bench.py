@@ -169,18 +169,24 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
     64 B of vdesc per variant (kdesc rows are amortized over a kernel's
     variants: 128 B per kernel) and writes 256 B of features and a 1-byte
     flag; the argmin reads a 4-byte prediction per variant and 8 B of
-    offsets and writes 8 B of `best` per kernel."""
+    offsets and writes 8 B of `best` per kernel; the top-10 list reads the
+    same and writes 10 x (8 B index + 4 B prediction) per kernel."""
     nv, nk = vdd.shape[0], offd.shape[0] - 1
     feat = torch.empty((nv, 32), dtype=torch.int64, device=vdd.device)
     inv = torch.empty(nv, dtype=torch.uint8, device=vdd.device)
     pred = torch.empty(nv, dtype=torch.float32, device=vdd.device).normal_()
     best = torch.empty(nk, dtype=torch.int64, device=vdd.device)
+    tidx = torch.empty((nk, 10), dtype=torch.int64, device=vdd.device)
+    tval = torch.empty((nk, 10), dtype=torch.float32, device=vdd.device)
     out = {}
     for name, fn, nbytes in (
             ("featurize", lambda: adv.advisor_featurize(kdd, vdd, feat_out=feat, invalid_out=inv),
              nv * (64 + 256 + 1) + nk * 128),
             ("rank_preds", lambda: adv.advisor_rank_preds(pred, offd, best_out=best),
-             nv * 4 + nk * 16 + 8)):
+             nv * 4 + nk * 16 + 8),
+            ("topn10_preds", lambda: adv.advisor_topn_preds(pred, offd, 10, idx_out=tidx,
+                                                            val_out=tval),
+             nv * 4 + nk * (8 + 10 * 12) + 8)):
         for _ in range(2):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -193,7 +199,7 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
         gbs = nbytes / (ms / 1e3) / 1e9
         out[name] = {"ms": ms, "bytes": nbytes, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
                      "frac": gbs / PEAK_HBM_GBS}
-    del feat, inv, pred, best
+    del feat, inv, pred, best, tidx, tval
     return out
 
 

@@ -65,6 +65,7 @@ enum advisor_precision {
 #define ADVISOR_VD_COLS 8
 #define ADVISOR_MAX_LAYERS 9   /* hidden layers + output layer */
 #define ADVISOR_MAX_WIDTH 1024
+#define ADVISOR_MAX_TOP_N 32   /* longest top-N list of advisor_topn_preds / advisor_rank_topn */
 
 typedef struct advisor_model advisor_model;  /* opaque; owned by the library */
 
@@ -228,6 +229,37 @@ int advisor_rank_refined(advisor_model *model, const advisor_model *refine,
  */
 int advisor_rank_preds(const float *pred, const int64_t *offsets, int64_t n_kernels,
                        int64_t n_variants, int64_t *best_out, void *stream);
+
+/*
+ * The top-N list of the prediction flow (section 3: predicted runtimes are
+ * sorted and the N best variants recommended) on given predictions.
+ * pred (device, float [n_variants]) and offsets (device, int64
+ * [n_kernels + 1]) as for advisor_rank_preds; 1 <= top_n <= 32.
+ * idx_out (device, int64 [n_kernels, top_n], row-major) receives, for each
+ * kernel k, its variants in ascending order of prediction, the lower index
+ * first among equal predictions (-0 equals +0), NaN predictions left out;
+ * past the last eligible variant the row holds -1. idx_out[k, 0] is
+ * advisor_rank_preds' best[k]. val_out (device, float [n_kernels, top_n],
+ * may be NULL) receives the matching predictions, NaN where idx_out is -1.
+ */
+int advisor_topn_preds(const float *pred, const int64_t *offsets, int64_t n_kernels,
+                       int64_t n_variants, int top_n, int64_t *idx_out, float *val_out,
+                       void *stream);
+
+/*
+ * The prediction flow of section 3 with its top-N list: advisor_rank's fused
+ * pass writing every prediction, then advisor_topn_preds on them. idx_out
+ * and val_out as for advisor_topn_preds (eligibility as for advisor_rank:
+ * invalid variants and those whose kernel_id is not k have NaN predictions
+ * and never enter); idx_out[k, 0] equals advisor_rank's best_out[k].
+ * pred_out (device, float [n_variants], may be NULL) receives every
+ * prediction; when it is NULL the model's workspace holds them (it grows on
+ * demand with a synchronous allocation, so calls on one model must not
+ * overlap). Limits as for advisor_rank and advisor_topn_preds.
+ */
+int advisor_rank_topn(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
+                      const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int top_n,
+                      int64_t *idx_out, float *val_out, float *pred_out, void *stream);
 
 /*
  * Training (section 5.3: the network is fit to measured runtimes with a

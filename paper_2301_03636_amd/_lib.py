@@ -77,6 +77,8 @@ def lib():
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
             "advisor_mfma_peak": ([i32, i64, i32, C.POINTER(C.c_double), P], i32),
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
+            "advisor_topn_preds": ([P, P, i64, i64, i32, P, P, P], i32),
+            "advisor_rank_topn": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -289,6 +291,47 @@ def advisor_rank_preds(pred, offsets, best_out=None):
     _check(lib().advisor_rank_preds(_ptr(pred), _ptr(offsets), nk, pred.shape[0], _ptr(best_out),
                                     _stream()), "advisor_rank_preds")
     return best_out
+
+
+def _topn_outputs(nk, top_n, idx_out, val_out, device):
+    if idx_out is None:
+        idx_out = torch.empty((nk, top_n), dtype=torch.int64, device=device)
+    if val_out is None:
+        val_out = torch.empty((nk, top_n), dtype=torch.float32, device=device)
+    _dev(idx_out, torch.int64, "idx_out")
+    _dev(val_out, torch.float32, "val_out")
+    if idx_out.numel() != nk * top_n or val_out.numel() != nk * top_n:
+        raise ValueError("idx_out and val_out must hold n_kernels * top_n elements")
+    return idx_out, val_out
+
+
+def advisor_topn_preds(pred, offsets, top_n, idx_out=None, val_out=None):
+    """(idx [n_k, top_n] int64, val [n_k, top_n] float32): each kernel's
+    variants by ascending prediction, -1 / NaN past the eligible ones."""
+    _dev(pred, torch.float32, "pred")
+    _dev(offsets, torch.int64, "offsets")
+    nk = offsets.shape[0] - 1
+    idx_out, val_out = _topn_outputs(nk, int(top_n), idx_out, val_out, pred.device)
+    _check(lib().advisor_topn_preds(_ptr(pred), _ptr(offsets), nk, pred.shape[0], int(top_n),
+                                    _ptr(idx_out), _ptr(val_out), _stream()),
+           "advisor_topn_preds")
+    return idx_out, val_out
+
+
+def advisor_rank_topn(h, kdesc, vdesc, offsets, top_n, idx_out=None, val_out=None, pred_out=None):
+    """The fused prediction flow with a top-N list per kernel: (idx, val)
+    as for advisor_topn_preds."""
+    for t, name in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
+        _dev(t, torch.int64, name)
+    nk = offsets.shape[0] - 1
+    nv = vdesc.shape[0]
+    idx_out, val_out = _topn_outputs(nk, int(top_n), idx_out, val_out, vdesc.device)
+    if pred_out is not None:
+        _dev(pred_out, torch.float32, "pred_out")
+    _check(lib().advisor_rank_topn(h, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv, int(top_n),
+                                   _ptr(idx_out), _ptr(val_out), _ptr(pred_out), _stream()),
+           "advisor_rank_topn")
+    return idx_out, val_out
 
 
 # --------------------------------------------------------------------------- measurement

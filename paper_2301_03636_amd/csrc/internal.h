@@ -54,6 +54,9 @@ bool stream_capturing(hipStream_t s);
 
 // Whether the ranking calls check their offsets first (select.hip).
 bool debug_offsets(hipStream_t s);
+// segmented top-N on predictions (arguments checked by the caller)
+int launch_topn_preds(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v, int N,
+                      int64_t *idx_out, float *val_out, hipStream_t s);
 
 // Whether tile shape V is built for this precision and width (mlp.hip).
 bool tile_shape_exists(int precision, int W, int V);

@@ -4,6 +4,8 @@
 // could order either way are decided as the second model decides them. The
 // argmin of section 3's prediction flow (N = 1) over a candidate set chosen
 // by the same network in another precision.
+// The file also holds the prediction flow with a top-N list (the fused pass,
+// then the segmented top-N on its predictions), which shares the workspace.
 #include <algorithm>
 
 #include "internal.h"
@@ -227,4 +229,30 @@ extern "C" int advisor_rank_refined(advisor_model *model, const advisor_model *r
                        s, w->best_c, w->cand, n_kernels, best_out);
     ADV_LAUNCHED("refine_map_kernel");
     return ADVISOR_OK;
+}
+
+extern "C" int advisor_rank_topn(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
+                                 const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
+                                 int top_n, int64_t *idx_out, float *val_out, float *pred_out,
+                                 void *stream)
+{
+    clear_error();
+    if (!model) return fail(ADVISOR_EINVAL, "advisor_rank_topn: null model");
+    if (top_n < 1 || top_n > ADVISOR_MAX_TOP_N)
+        return fail(ADVISOR_EINVAL, "top_n must be in [1, 32]");
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels >= (int64_t)1 << 31) return fail(ADVISOR_ESHAPE, "n_kernels must be < 2^31");
+    if (n_kernels == 0) return ADVISOR_OK;
+    if (!kdesc || !offsets || !idx_out || (n_variants > 0 && !vdesc))
+        return fail(ADVISOR_EINVAL, "advisor_rank_topn: null pointer");
+    hipStream_t s = as_stream(stream);
+    int rc = ensure_refine_ws(model, pred_out ? 0 : n_variants, n_kernels, 1);
+    if (rc) return rc;
+    RefineWs *w = reinterpret_cast<RefineWs *>(model->refine_ws);
+    float *pred = pred_out ? pred_out : w->pred;
+    // the fused pass; its argmin lands in the workspace and is not used
+    rc = advisor_rank(model, kdesc, vdesc, offsets, n_kernels, n_variants, w->best_c, pred, s);
+    if (rc) return rc;
+    return launch_topn_preds(pred, offsets, n_kernels, n_variants, top_n, idx_out, val_out, s);
 }

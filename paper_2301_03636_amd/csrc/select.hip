@@ -172,6 +172,84 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
     }
 }
 
+// The top-N list of the prediction flow (section 3: the predicted runtimes
+// are sorted and the N best variants kept). One wave per kernel segment, in a
+// grid-stride loop over kernels: every lane keeps the K smallest keys it has
+// seen (a sorted list held in registers, compile-time indices only, entered
+// only by keys that beat its current K-th), then N rounds of a wave-wide
+// minimum pop the segment's best keys in ascending order (keys are unique, so
+// exactly one lane pops each). Lane r writes rank r: the variant index and
+// its prediction, or -1 and NaN past the end of the eligible variants.
+template <int K>
+__global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
+    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, int N, int64_t *__restrict__ idx_out, float *__restrict__ val_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
+    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + (threadIdx.x >> 6); k < n_k;
+         k += nwaves_total) {
+        const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
+        const int64_t hi = max(lo, min(offsets[k + 1], n_v));
+        uint64_t top[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) top[q] = ~0ull;
+        for (int64_t i = lo + lane; i < hi; i += 64) {
+            const float p = pred[i];
+            if (__builtin_isnan(p)) continue;
+            uint64_t x = pred_key(p, (uint32_t)i);
+            if (x >= top[K - 1]) continue;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const uint64_t t = top[q];
+                const bool less = x < t;
+                top[q] = less ? x : t;
+                x = less ? t : x;
+            }
+        }
+        int64_t mine = -1;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (r >= N) break;  // N is the same for every lane
+            const uint64_t v = wave_min_u64(top[0]);
+            if (v == ~0ull) break;  // the segment has fewer than N eligible variants
+            if (lane == r) mine = (int64_t)(v & 0xffffffffull);
+            if (top[0] == v) {
+#pragma unroll
+                for (int q = 0; q + 1 < K; ++q) top[q] = top[q + 1];
+                top[K - 1] = ~0ull;
+            }
+        }
+        if (lane < N) {
+            const int64_t slot = k * N + lane;
+            idx_out[slot] = mine;
+            if (val_out) val_out[slot] = mine >= 0 ? pred[mine] : __builtin_nanf("");
+        }
+    }
+}
+
+template <int K>
+static void launch_topn(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v,
+                        int N, int64_t *idx_out, float *val_out, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((n_k + AM_WAVES - 1) / AM_WAVES, 1 << 20);
+    hipLaunchKernelGGL(topn_preds_kernel<K>, dim3((unsigned)blocks), dim3(AM_WAVES * 64), 0, s,
+                       pred, offsets, n_k, n_v, N, idx_out, val_out);
+}
+
+int launch_topn_preds(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v,
+                      int N, int64_t *idx_out, float *val_out, hipStream_t s)
+{
+    if (N <= 1) launch_topn<1>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
+    else if (N <= 2) launch_topn<2>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
+    else if (N <= 4) launch_topn<4>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
+    else if (N <= 8) launch_topn<8>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
+    else if (N <= 16) launch_topn<16>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
+    else launch_topn<32>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
+    ADV_LAUNCHED("topn_preds_kernel");
+    return ADVISOR_OK;
+}
+
 // The kernel segments are well formed when offsets[0] = 0, offsets[n_k] =
 // n_v and offsets[i] <= offsets[i + 1]; first_bad gets the lowest index
 // whose entry breaks that (a 64-bit vector atomic min, starting at ~0).
@@ -296,4 +374,25 @@ extern "C" int advisor_rank_preds(const float *pred, const int64_t *offsets, int
                        as_stream(stream), pred, offsets, n_kernels, n_variants, best_out);
     ADV_LAUNCHED("argmin_preds_kernel");
     return ADVISOR_OK;
+}
+
+extern "C" int advisor_topn_preds(const float *pred, const int64_t *offsets, int64_t n_kernels,
+                                  int64_t n_variants, int top_n, int64_t *idx_out, float *val_out,
+                                  void *stream)
+{
+    clear_error();
+    if (top_n < 1 || top_n > ADVISOR_MAX_TOP_N)
+        return fail(ADVISOR_EINVAL, "top_n must be in [1, 32]");
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels >= ((int64_t)1 << 62) / ADVISOR_MAX_TOP_N)
+        return fail(ADVISOR_ESHAPE, "n_kernels too large");
+    if (n_kernels == 0) return ADVISOR_OK;
+    if (!offsets || !idx_out || (n_variants > 0 && !pred))
+        return fail(ADVISOR_EINVAL, "advisor_topn_preds: null pointer");
+    hipStream_t s = as_stream(stream);
+    if (debug_offsets(s)) {
+        if (int rc = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, stream)) return rc;
+    }
+    return launch_topn_preds(pred, offsets, n_kernels, n_variants, top_n, idx_out, val_out, s);
 }

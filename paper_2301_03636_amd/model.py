@@ -39,6 +39,12 @@ class Model:
     def rank(self, kdesc, vdesc, offsets, best_out=None, pred_out=None, want_pred=False):
         return _lib.advisor_rank(self.handle, kdesc, vdesc, offsets, best_out, pred_out, want_pred)
 
+    def rank_topn(self, kdesc, vdesc, offsets, top_n=10, idx_out=None, val_out=None, pred_out=None):
+        """Each kernel's top_n variants by predicted runtime (the paper keeps
+        N of them) and their predictions: (idx, val), each [n_kernels, top_n]."""
+        return _lib.advisor_rank_topn(self.handle, kdesc, vdesc, offsets, top_n, idx_out, val_out,
+                                      pred_out)
+
     def rank_refined(self, refine, kdesc, vdesc, offsets, top_k=8, best_out=None, pred_out=None):
         """Rank with this model, then re-rank each kernel's top_k candidates
         with `refine` (e.g. an fp32 model of the same weights)."""

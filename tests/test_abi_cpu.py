@@ -115,3 +115,16 @@ def test_validate_offsets_argument_checks():
     assert L.advisor_validate_offsets(None, 3, 10, C.byref(bad), None) == EINVAL
     assert bad.value == -1
     assert L.advisor_validate_offsets(C.c_void_p(8), -1, 10, C.byref(bad), None) == ESHAPE
+
+
+def test_topn_argument_checks():
+    L = _lib.lib()
+    v = C.c_void_p(8)
+    assert L.advisor_topn_preds(v, v, 1, 4, 0, v, None, None) == EINVAL
+    assert L.advisor_topn_preds(v, v, 1, 4, 33, v, None, None) == EINVAL
+    assert L.advisor_topn_preds(None, None, 1, 4, 10, None, None, None) == EINVAL
+    assert L.advisor_topn_preds(v, v, -1, 4, 10, v, None, None) == ESHAPE
+    assert L.advisor_topn_preds(v, v, 1, 1 << 32, 10, v, None, None) == ESHAPE
+    assert L.advisor_topn_preds(None, None, 0, 0, 10, None, None, None) == OK
+    assert L.advisor_rank_topn(None, v, v, v, 1, 4, 10, v, None, None, None) == EINVAL
+    assert "null model" in _lib.last_error()
