@@ -136,15 +136,43 @@ __device__ __forceinline__ uint64_t pred_key(float p, uint32_t idx)
     return ((uint64_t)u << 32) | idx;
 }
 
+// One step of a min-reduction over lanes through a DPP lane permutation
+// inside each row of 16 lanes (the 64-bit key moves as two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_min_u64(uint64_t v)
+{
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    const uint64_t o = ((uint64_t)ohi << 32) | olo;
+    return o < v ? o : v;
+}
+
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Minimum over the 64 lanes of a wave, returned to every lane (all lanes must
+// be active): swaps of neighbours and of lane pairs inside each quad, then
+// the mirror images inside each half-row and row leave every lane of a row
+// with the row's minimum; the four rows' minima are read out and compared.
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
-    }
-    return v;
+    v = dpp_min_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_min_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_min_u64<0x141>(v);  // row_half_mirror
+    v = dpp_min_u64<0x140>(v);  // row_mirror
+    const uint64_t a = read_lane_u64(v, 0), b = read_lane_u64(v, 16);
+    const uint64_t c = read_lane_u64(v, 32), d = read_lane_u64(v, 48);
+    const uint64_t ab = a < b ? a : b, cd = c < d ? c : d;
+    return ab < cd ? ab : cd;
 }
+
+// loads in flight per lane in the selection kernels' scans
+constexpr int SEL_UNROLL = 4;
 
 constexpr int AM_WAVES = 4;
 
@@ -160,11 +188,22 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
         const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
         const int64_t hi = max(lo, min(offsets[k + 1], n_v));
         uint64_t key = ~0ull;
-        for (int64_t i = lo + lane; i < hi; i += 64) {
-            const float p = pred[i];
-            if (!__builtin_isnan(p)) {
-                const uint64_t q = pred_key(p, (uint32_t)i);
-                key = q < key ? q : key;
+        for (int64_t base = lo + lane; base < hi; base += 64 * SEL_UNROLL) {
+            float p[SEL_UNROLL];
+#pragma unroll
+            for (int u = 0; u < SEL_UNROLL; ++u) {
+                // unconditional loads at a clamped index (hi > base >= 0),
+                // so all of them are in flight before the first compare
+                const int64_t i = base + 64 * u;
+                const float v = pred[i < hi ? i : hi - 1];
+                p[u] = i < hi ? v : __builtin_nanf("");
+            }
+#pragma unroll
+            for (int u = 0; u < SEL_UNROLL; ++u) {
+                if (!__builtin_isnan(p[u])) {
+                    const uint64_t q = pred_key(p[u], (uint32_t)(base + 64 * u));
+                    key = q < key ? q : key;
+                }
             }
         }
         key = wave_min_u64(key);
@@ -194,17 +233,28 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
         uint64_t top[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) top[q] = ~0ull;
-        for (int64_t i = lo + lane; i < hi; i += 64) {
-            const float p = pred[i];
-            if (__builtin_isnan(p)) continue;
-            uint64_t x = pred_key(p, (uint32_t)i);
-            if (x >= top[K - 1]) continue;
+        for (int64_t base = lo + lane; base < hi; base += 64 * SEL_UNROLL) {
+            float p[SEL_UNROLL];
 #pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const uint64_t t = top[q];
-                const bool less = x < t;
-                top[q] = less ? x : t;
-                x = less ? t : x;
+            for (int u = 0; u < SEL_UNROLL; ++u) {
+                // unconditional loads at a clamped index (hi > base >= 0),
+                // so all of them are in flight before the first compare
+                const int64_t i = base + 64 * u;
+                const float v = pred[i < hi ? i : hi - 1];
+                p[u] = i < hi ? v : __builtin_nanf("");
+            }
+#pragma unroll
+            for (int u = 0; u < SEL_UNROLL; ++u) {
+                if (__builtin_isnan(p[u])) continue;
+                uint64_t x = pred_key(p[u], (uint32_t)(base + 64 * u));
+                if (x >= top[K - 1]) continue;
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const uint64_t t = top[q];
+                    const bool less = x < t;
+                    top[q] = less ? x : t;
+                    x = less ? t : x;
+                }
             }
         }
         int64_t mine = -1;
