@@ -61,6 +61,9 @@ def _load():
         lib.oracle_adam.argtypes = [P, P, P, P, i64, i64, C.c_double, C.c_double, C.c_double,
                                     C.c_double]
         lib.oracle_adam.restype = None
+        lib.oracle_rmsprop.argtypes = [P, P, P, i64, C.c_double, C.c_double, C.c_double,
+                                       C.c_double]
+        lib.oracle_rmsprop.restype = None
         lib.oracle_rank.argtypes = [P, P, P, i64, i64, P, C.c_int, P, P, P, P, P, C.c_int]
         lib.oracle_rank.restype = C.c_int
         lib.oracle_max_threads.argtypes = []
@@ -181,6 +184,29 @@ def adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     gg = _c(g, np.float64)
     _load().oracle_adam(_p(w), _p(m), _p(v), _p(gg), w.size, int(t), lr, b1, b2, eps)
+
+
+def rmse_loss_grad(widths, params, x, y, act="relu"):
+    """The RMSE loss of section 5.3 (eq. rmse: the square root of the mean
+    squared error) and its gradient by the chain rule, d sqrt(L) = dL / (2
+    sqrt(L)), taken as 0 where the error is exactly 0."""
+    mse, g = loss_grad(widths, params, x, y, act)
+    r = float(np.sqrt(mse))
+    return r, (g / (2.0 * r) if r > 0.0 else np.zeros_like(g))
+
+
+def rmsprop(w, v, g, lr=1e-2, alpha=0.99, eps=1e-8, weight_decay=0.0):
+    """In-place RMSprop step with coupled weight decay on float64 arrays w, v."""
+    for a in (w, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    gg = _c(g, np.float64)
+    _load().oracle_rmsprop(_p(w), _p(v), _p(gg), w.size, lr, alpha, eps, weight_decay)
+
+
+def step_lr(epoch, lr0=1e-2, gamma=0.1, every=30):
+    """The learning-rate schedule of section 5.3: lr0, multiplied by gamma
+    after every `every` epochs."""
+    return lr0 * gamma ** (int(epoch) // int(every))
 
 
 def rank(kdesc, vdesc, offsets, widths, params, mu, sigma, n_threads=0, want_pred=True):

@@ -391,6 +391,21 @@ void oracle_adam(double *w, double *m, double *v, const double *g, int64_t n, in
 }
 
 /*
+ * RMSprop (the optimizer section 5.3 selects; Hinton's lecture notes), with
+ * the weight decay of section 5.3 entering as an L2 term of the gradient:
+ * g' = g + wd w; v <- alpha v + (1 - alpha) g'^2; w <- w - lr g' / (sqrt(v) + eps).
+ */
+void oracle_rmsprop(double *w, double *v, const double *g, int64_t n, double lr, double alpha,
+                    double eps, double wd)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double gi = g[i] + wd * w[i];
+        v[i] = alpha * v[i] + (1.0 - alpha) * gi * gi;
+        w[i] -= lr * gi / (sqrt(v[i]) + eps);
+    }
+}
+
+/*
  * The whole prediction flow for many kernels: featurize every variant,
  * standardize, predict, and pick each kernel's best variant. Kernels are
  * independent, so they are spread over threads (n_threads <= 0: the OpenMP

@@ -306,6 +306,94 @@ def test_adam_trains_linear_net_to_lstsq_loss():
     assert loss < best * (1 + 1e-4)
 
 
+def test_rmse_gradient_finite_differences():
+    """The RMSE loss of section 5.3 (eq. rmse) and its gradient against
+    central differences of sqrt(mean squared error) computed from the
+    forward pass alone."""
+    widths = (32, 8, 1)
+    rng = np.random.default_rng(17)
+    p = _net(widths, 18)
+    x = rng.standard_normal((20, 32))
+    y = rng.standard_normal(20)
+    W = p[:256].reshape(8, 32)
+    z = x @ W.T + p[256:264]
+    p[256:264] += np.where(np.abs(z).min(axis=0) < 1e-3, 0.01, 0.0)
+
+    def rmse(q):
+        return np.sqrt(np.mean((oracle.forward(widths, q, x) - y) ** 2))
+
+    r, g = oracle.rmse_loss_grad(widths, p, x, y)
+    assert abs(r - rmse(p)) < 1e-12
+    fd = np.zeros_like(p)
+    for j in range(p.size):
+        h = 1e-6 * max(1.0, abs(p[j]))
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd[j] = (rmse(pp) - rmse(pm)) / (2 * h)
+    assert np.max(np.abs(fd - g) / np.maximum(np.abs(g), 1e-3)) < 1e-6
+
+
+def test_rmse_gradient_zero_at_exact_fit():
+    widths = (32, 1)
+    rng = np.random.default_rng(19)
+    x = rng.standard_normal((10, 32))
+    p = rng.standard_normal(33)
+    y = oracle.forward(widths, p, x, act="identity")  # an exact fit
+    r, g = oracle.rmse_loss_grad(widths, p, x, y, act="identity")
+    assert r == 0.0 and np.all(g == 0.0)
+
+
+def test_rmsprop_first_step_closed_form():
+    """From v = 0 without weight decay the first step is
+    -lr g / (sqrt(1 - alpha) |g| + eps)."""
+    rng = np.random.default_rng(20)
+    g = rng.standard_normal(500)
+    g[:2] = [0.0, -3.0]
+    w = np.zeros(500)
+    v = np.zeros(500)
+    oracle.rmsprop(w, v, g, lr=1e-2, alpha=0.99, eps=1e-8)
+    assert np.allclose(w, -1e-2 * g / (np.sqrt(0.01) * np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+    assert np.allclose(v, 0.01 * g * g, rtol=1e-13, atol=0)
+
+
+def test_rmsprop_two_steps_by_hand():
+    w = np.array([1.0])
+    v = np.zeros(1)
+    # g' = 2 + 0.5 * 1 = 2.5; v = 0.5 * 6.25 = 3.125; w = 1 - 0.1 * 2.5 / sqrt(3.125)
+    oracle.rmsprop(w, v, np.array([2.0]), lr=0.1, alpha=0.5, eps=0.0, weight_decay=0.5)
+    w1 = 1.0 - 0.1 * 2.5 / np.sqrt(3.125)
+    assert np.isclose(w[0], w1, rtol=1e-15) and v[0] == 3.125
+    g2 = -1.0 + 0.5 * w1
+    v2 = 0.5 * 3.125 + 0.5 * g2 * g2
+    oracle.rmsprop(w, v, np.array([-1.0]), lr=0.1, alpha=0.5, eps=0.0, weight_decay=0.5)
+    assert np.isclose(v[0], v2, rtol=1e-15)
+    assert np.isclose(w[0], w1 - 0.1 * g2 / np.sqrt(v2), rtol=1e-15)
+
+
+def test_rmsprop_against_torch_optimizer():
+    """Eight steps with weight decay agree with torch.optim.RMSprop (float64,
+    CPU) fed the same gradients."""
+    rng = np.random.default_rng(21)
+    w0 = rng.standard_normal(300)
+    grads = rng.standard_normal((8, 300))
+    w = w0.copy()
+    v = np.zeros_like(w)
+    t = torch.tensor(w0.copy(), requires_grad=True)
+    opt = torch.optim.RMSprop([t], lr=1e-2, alpha=0.99, eps=1e-8, weight_decay=1e-4)
+    for k in range(8):
+        oracle.rmsprop(w, v, grads[k], lr=1e-2, alpha=0.99, eps=1e-8, weight_decay=1e-4)
+        t.grad = torch.from_numpy(grads[k].copy())
+        opt.step()
+    assert np.allclose(w, t.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_step_lr_schedule():
+    """Section 5.3: 0.01, stepped down by a factor of 10 every 30 epochs."""
+    assert [oracle.step_lr(e) for e in (0, 29)] == [1e-2, 1e-2]
+    assert np.isclose(oracle.step_lr(30), 1e-3) and np.isclose(oracle.step_lr(149), 1e-6)
+
+
 def test_rank_composes_the_steps():
     kd, vd, off = workload.make_descriptors(30, 1, 80, seed=12, depth="mixed", invalid_frac=0.1)
     off[3] = off[4]  # make segment 3 empty (rows move to segment 2)
