@@ -301,6 +301,30 @@ int advisor_train_step(advisor_model *model, const int64_t *feat, const double *
                        float lr, float beta1, float beta2, float eps, double *loss_out,
                        double *gnorm_out, void *stream);
 
+/* Losses of advisor_train_step_rmsprop. */
+enum { ADVISOR_LOSS_MSE = 0, ADVISOR_LOSS_RMSE = 1 };
+
+/* One training step with the optimizer section 5.3 selects: RMSprop
+ * (Hinton's lecture notes) with weight decay as an L2 term of the gradient,
+ *   g' = g + weight_decay * w,  v <- alpha v + (1 - alpha) g'^2,
+ *   w <- w - lr g' / (sqrt(v) + eps),
+ * on every fp32 master parameter (biases included), then the compute copies
+ * are rebuilt. loss selects the loss being minimized: ADVISOR_LOSS_MSE
+ * (1/n) sum (y_hat - y)^2, or ADVISOR_LOSS_RMSE, its square root (eq. rmse;
+ * its gradient is the MSE gradient / (2 RMSE), 0 when the RMSE is 0).
+ * loss_out (device, double [1], may be NULL) receives that loss in float64;
+ * gnorm_out (device, double [1], may be NULL) the float64 2-norm of its
+ * gradient (without the weight-decay term), which advisor_model_grads then
+ * returns. The running average v is the model's second-moment buffer, the
+ * one advisor_model_get_adam / set_adam read and write as Adam's v (Adam's
+ * first moment and step count are left untouched). The learning-rate
+ * schedule of section 5.3 (0.01, divided by 10 every 30 epochs) is the
+ * caller's: lr is read at every call. 0 < lr, 0 <= alpha < 1, eps >= 0,
+ * weight_decay >= 0. Other arguments and limits as for advisor_train_step. */
+int advisor_train_step_rmsprop(advisor_model *model, const int64_t *feat, const double *y,
+                               int64_t n, float lr, float alpha, float eps, float weight_decay,
+                               int loss, double *loss_out, double *gnorm_out, void *stream);
+
 /* Replace the fp32 master weights from a device buffer (float [param_count])
  * and rebuild the compute copies; for optimizers that run outside the
  * library. Adam state is left as it is. */

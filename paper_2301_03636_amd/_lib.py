@@ -77,6 +77,8 @@ def lib():
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
             "advisor_mfma_peak": ([i32, i64, i32, C.POINTER(C.c_double), P], i32),
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
+            "advisor_train_step_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
+                                            C.c_float, i32, P, P, P], i32),
             "advisor_topn_preds": ([P, P, i64, i64, i32, P, P, P], i32),
             "advisor_rank_topn": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
         }
@@ -405,6 +407,26 @@ def advisor_train_step(h, feat, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, lo
     _check(lib().advisor_train_step(h, _ptr(feat), _ptr(y), feat.shape[0], lr, beta1, beta2, eps,
                                     _ptr(loss_out), _ptr(gnorm_out), _stream()),
            "advisor_train_step")
+    return loss_out, gnorm_out
+
+
+LOSSES = {"mse": 0, "rmse": 1}
+
+
+def advisor_train_step_rmsprop(h, feat, y, lr=1e-2, alpha=0.99, eps=1e-8, weight_decay=1e-4,
+                               loss="rmse", loss_out=None, gnorm_out=None):
+    _dev(feat, torch.int64, "feat")
+    _dev(y, torch.float64, "y")
+    if loss not in LOSSES:
+        raise ValueError("loss must be one of %s" % sorted(LOSSES))
+    if loss_out is None:
+        loss_out = torch.empty(1, dtype=torch.float64, device=feat.device)
+    if gnorm_out is None:
+        gnorm_out = torch.empty(1, dtype=torch.float64, device=feat.device)
+    _check(lib().advisor_train_step_rmsprop(h, _ptr(feat), _ptr(y), feat.shape[0], lr, alpha, eps,
+                                            weight_decay, LOSSES[loss], _ptr(loss_out),
+                                            _ptr(gnorm_out), _stream()),
+           "advisor_train_step_rmsprop")
     return loss_out, gnorm_out
 
 

@@ -550,6 +550,56 @@ __global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float 
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Loss of an RMSprop step from the squared-error partials (the same fixed
+// summation order as finish_kernel): the MSE, or for the RMSE loss of
+// section 5.3 its square root. The RMSE gradient is the MSE gradient times
+// 1 / (2 sqrt(MSE)) (0 when the MSE is 0), so the MSE backward pass serves
+// both; scale[0] receives that factor (1 for the MSE loss).
+__global__ void loss_scale_kernel(const double *__restrict__ part, double inv_n, int rmse,
+                                  double *__restrict__ scale, double *__restrict__ loss_out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < RB; ++i) s += part[i];
+    const double mse = s * inv_n;
+    const double r = sqrt(mse);
+    scale[0] = rmse ? (r > 0.0 ? 0.5 / r : 0.0) : 1.0;
+    if (loss_out) *loss_out = rmse ? r : mse;
+}
+
+// out = sqrt(sum(part[0..RB))) * scale[0]: the norm of the scaled gradient.
+__global__ void scaled_norm_kernel(const double *__restrict__ part,
+                                   const double *__restrict__ scale, double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < RB; ++i) s += part[i];
+    *out = sqrt(s) * scale[0];
+}
+
+// RMSprop (section 5.3's optimizer) on fp32 master weights with weight
+// decay as an L2 term: g' = c g + wd w, v <- alpha v + (1 - alpha) g'^2,
+// w <- w - lr g' / (sqrt(v) + eps), c = scale[0]. With c != 1 the stored
+// gradient is replaced by c g, the gradient of the loss being minimized.
+__global__ void rmsprop_kernel(float *__restrict__ w, float *__restrict__ v,
+                               float *__restrict__ g, int64_t n, float lr, float alpha, float eps,
+                               float wd, const double *__restrict__ scale)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double c = *scale;
+    float gi = g[i];
+    if (c != 1.0) {
+        gi = (float)((double)gi * c);
+        g[i] = gi;
+    }
+    const float wi = w[i];
+    const float gd = gi + wd * wi;
+    const float vi = alpha * v[i] + (1.0f - alpha) * gd * gd;
+    v[i] = vi;
+    w[i] = wi - lr * gd / (sqrtf(vi) + eps);
+}
+
 // ---------------------------------------------------------------------------
 // Model-owned training workspace.
 struct TrainWs {
@@ -561,7 +611,7 @@ struct TrainWs {
     float *pred = nullptr;
     float *dy = nullptr;
     float *grads = nullptr;
-    double *red = nullptr;    // RB partials
+    double *red = nullptr;    // 2 x RB partials, then scalars (red[2 RB] = loss gradient scale)
     void *wt[MAX_LAYERS] = {nullptr};
     size_t partial_floats = 0;
 };
@@ -642,7 +692,7 @@ static int ensure_ws(advisor_model *m, int64_t n, bool with_saved)
         const size_t eb = elem_bytes(m);
         for (int l = 1; l < m->n_hidden; ++l) ADV_HIP(hipMalloc(&w->wt[l], (size_t)tw * tw * eb));
         ADV_HIP(hipMalloc(&w->grads, sizeof(float) * m->n_params));
-        ADV_HIP(hipMalloc(&w->red, sizeof(double) * 2 * RB));
+        ADV_HIP(hipMalloc(&w->red, sizeof(double) * (2 * RB + 8)));  // + scalars
         size_t pf = 0;
         for (int l = 0; l < m->n_hidden; ++l) {
             const int na = tw, nb = l == 0 ? NFEAT : tw;
@@ -962,6 +1012,60 @@ extern "C" int advisor_train_step(advisor_model *m, const int64_t *feat, const d
                        m->master, m->adam_m, m->adam_v, w->grads, m->n_params, lr, beta1, beta2, eps,
                        (const int64_t *)m->d_step);
     ADV_LAUNCHED("adam_kernel");
+    rc = repack(m, s);
+    if (rc) return rc;
+    return repack_transposed(m, s);
+}
+
+extern "C" int advisor_train_step_rmsprop(advisor_model *m, const int64_t *feat, const double *y,
+                                          int64_t n, float lr, float alpha, float eps,
+                                          float weight_decay, int loss, double *loss_out,
+                                          double *gnorm_out, void *stream)
+{
+    clear_error();
+    int rc = check_trainable(m);
+    if (rc) return rc;
+    if (n < 1 || n >= ((int64_t)1 << 32)) return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+    if (!feat || !y) return fail(ADVISOR_EINVAL, "advisor_train_step_rmsprop: null pointer");
+    if (!(lr > 0.0f) || !(alpha >= 0.0f && alpha < 1.0f) || !(eps >= 0.0f) ||
+        !(weight_decay >= 0.0f) || !(weight_decay < 1e30f))
+        return fail(ADVISOR_EINVAL, "bad RMSprop hyper-parameters");
+    if (loss != ADVISOR_LOSS_MSE && loss != ADVISOR_LOSS_RMSE)
+        return fail(ADVISOR_EINVAL, "loss must be ADVISOR_LOSS_MSE or ADVISOR_LOSS_RMSE");
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    rc = ensure_ws(m, n, true);
+    if (rc) return rc;
+    TrainWs *w = train_ws(m);
+    hipStream_t s = as_stream(stream);
+    const int64_t ld = ld_for(n);
+    TileArgs a{};
+    a.feat = feat;
+    a.n_rows = n;
+    a.pred = w->pred;
+    a.save_ld = ld;
+    a.save_x = w->saved;
+    a.save_h = reinterpret_cast<unsigned char *>(w->saved) + (size_t)NFEAT * ld * elem_bytes(m);
+    a.save_mask = saved_masks(m, w->saved, ld);
+    rc = launch_train_forward(m, a, s);
+    if (rc) return rc;
+    double *scale = w->red + 2 * RB;
+    hipLaunchKernelGGL(loss_kernel, dim3(RB), dim3(RT), 0, s, w->pred, y, n, w->dy, w->red);
+    hipLaunchKernelGGL(loss_scale_kernel, dim3(1), dim3(64), 0, s, w->red, 1.0 / (double)n,
+                       loss == ADVISOR_LOSS_RMSE ? 1 : 0, scale, loss_out);
+    ADV_LAUNCHED("loss kernels");
+    rc = backward_core(m, w->dy, w->saved, n, w->grads, s);
+    if (rc) return rc;
+    if (gnorm_out) {
+        hipLaunchKernelGGL(sumsq_kernel, dim3(RB), dim3(RT), 0, s, w->grads, m->n_params,
+                           w->red + RB);
+        hipLaunchKernelGGL(scaled_norm_kernel, dim3(1), dim3(64), 0, s, w->red + RB,
+                           (const double *)scale, gnorm_out);
+        ADV_LAUNCHED("gradient norm kernels");
+    }
+    hipLaunchKernelGGL(rmsprop_kernel, dim3((unsigned)((m->n_params + 255) / 256)), dim3(256), 0, s,
+                       m->master, m->adam_v, w->grads, m->n_params, lr, alpha, eps, weight_decay,
+                       (const double *)scale);
+    ADV_LAUNCHED("rmsprop_kernel");
     rc = repack(m, s);
     if (rc) return rc;
     return repack_transposed(m, s);

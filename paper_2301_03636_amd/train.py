@@ -1,7 +1,7 @@
 """Training drivers: a torch.autograd.Function whose forward and backward
 are the library's hand-written kernels, and a loop around the library's own
 fused training step (forward, float64 loss, backward, float64 gradient norm,
-Adam)."""
+Adam or RMSprop)."""
 from __future__ import annotations
 
 import torch
@@ -45,3 +45,31 @@ class Trainer:
     def step(self, feat, y, loss_out=None, gnorm_out=None):
         return _lib.advisor_train_step(self.model.handle, feat, y, self.lr, self.beta1, self.beta2,
                                        self.eps, loss_out, gnorm_out)
+
+
+def step_lr(epoch, lr0=1e-2, gamma=0.1, every=30):
+    """Section 5.3's learning-rate schedule: lr0, multiplied by gamma after
+    every `every` epochs."""
+    return lr0 * gamma ** (int(epoch) // int(every))
+
+
+class RMSpropTrainer:
+    """Section 5.3's recipe in the library's fused step: RMSprop with weight
+    decay 1e-4 on the RMSE loss, the learning rate 0.01 stepped down by 10x
+    every 30 epochs (call set_epoch at each epoch). alpha and eps, which the
+    paper leaves unstated, default to 0.99 and 1e-8."""
+
+    def __init__(self, model, lr0=1e-2, alpha=0.99, eps=1e-8, weight_decay=1e-4, loss="rmse",
+                 gamma=0.1, every=30):
+        self.model = model
+        self.lr0, self.gamma, self.every = lr0, gamma, every
+        self.alpha, self.eps, self.weight_decay, self.loss = alpha, eps, weight_decay, loss
+        self.lr = lr0
+
+    def set_epoch(self, epoch):
+        self.lr = step_lr(epoch, self.lr0, self.gamma, self.every)
+
+    def step(self, feat, y, loss_out=None, gnorm_out=None):
+        return _lib.advisor_train_step_rmsprop(self.model.handle, feat, y, self.lr, self.alpha,
+                                               self.eps, self.weight_decay, self.loss, loss_out,
+                                               gnorm_out)

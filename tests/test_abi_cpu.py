@@ -128,3 +128,12 @@ def test_topn_argument_checks():
     assert L.advisor_topn_preds(None, None, 0, 0, 10, None, None, None) == OK
     assert L.advisor_rank_topn(None, v, v, v, 1, 4, 10, v, None, None, None) == EINVAL
     assert "null model" in _lib.last_error()
+
+
+def test_rmsprop_argument_checks():
+    L = _lib.lib()
+    v = C.c_void_p(8)
+    f = C.c_float
+    assert L.advisor_train_step_rmsprop(None, v, v, 16, f(1e-2), f(0.99), f(1e-8), f(1e-4), 1,
+                                        None, None, None) == EINVAL
+    assert "null" in _lib.last_error() or "model" in _lib.last_error()
