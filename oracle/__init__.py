@@ -64,6 +64,8 @@ def _load():
         lib.oracle_rmsprop.argtypes = [P, P, P, i64, C.c_double, C.c_double, C.c_double,
                                        C.c_double]
         lib.oracle_rmsprop.restype = None
+        lib.oracle_enumerate.argtypes = [C.c_int, C.c_int, P]
+        lib.oracle_enumerate.restype = i64
         lib.oracle_rank.argtypes = [P, P, P, i64, i64, P, C.c_int, P, P, P, P, P, C.c_int]
         lib.oracle_rank.restype = C.c_int
         lib.oracle_max_threads.argtypes = []
@@ -207,6 +209,25 @@ def step_lr(epoch, lr0=1e-2, gamma=0.1, every=30):
     """The learning-rate schedule of section 5.3: lr0, multiplied by gamma
     after every `every` epochs."""
     return lr0 * gamma ** (int(epoch) // int(every))
+
+
+def enumerate_variants(n_loops, sched_mask=7):
+    """Section 4.1.3's variants of kernels with the given loop counts:
+    (offsets [n_k + 1], rows [n_v, 6] = kernel, x, d, c, schedule, data)."""
+    nl = np.asarray(n_loops, dtype=np.int64).ravel()
+    L = _load()
+    counts = np.array([L.oracle_enumerate(int(n) if -2**31 < n < 2**31 else 0, int(sched_mask),
+                                          None) for n in nl], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    rows = np.zeros((int(off[-1]), 6), dtype=np.int64)
+    for k, n in enumerate(nl):
+        if counts[k] == 0:
+            continue
+        blk = np.zeros((int(counts[k]), 5), dtype=np.int64)
+        L.oracle_enumerate(int(n), int(sched_mask), _p(blk))
+        rows[off[k]:off[k + 1], 0] = k
+        rows[off[k]:off[k + 1], 1:] = blk
+    return off, rows
 
 
 def rank(kdesc, vdesc, offsets, widths, params, mu, sigma, n_threads=0, want_pred=True):

@@ -391,6 +391,41 @@ void oracle_adam(double *w, double *m, double *v, const double *g, int64_t n, in
 }
 
 /*
+ * Variant generation of section 4.1.3 for one kernel with n collapsible
+ * loops (1 <= n <= 4; any other n gives no variant). Loop 0 is always
+ * distributed over the teams. The parallel-for directive sits at loop x:
+ * at x = 0 it merges with teams distribute into one combined directive
+ * whose collapse c runs over 1..n (no separate teams collapse, d = 0); at
+ * 1 <= x < n teams distribute collapses d in 1..x loops and parallel for
+ * collapses c in 1..n-x. Every placement takes each schedule whose bit is
+ * set in sched_mask (bit 0 static, 1 dynamic, 2 guided) and each of the two
+ * data-transfer options. Rows [x, d, c, schedule, data] in that nesting
+ * order are written to out (if not NULL); the count is returned.
+ */
+int64_t oracle_enumerate(int n, int sched_mask, int64_t *out)
+{
+    int64_t count = 0;
+    if (n < 1 || n > 4) return 0;
+    for (int x = 0; x < n; x++) {
+        int d_lo = x == 0 ? 0 : 1, d_hi = x == 0 ? 0 : x;
+        int c_hi = x == 0 ? n : n - x;
+        for (int d = d_lo; d <= d_hi; d++)
+            for (int c = 1; c <= c_hi; c++)
+                for (int sch = 0; sch < 3; sch++) {
+                    if (!((sched_mask >> sch) & 1)) continue;
+                    for (int data = 0; data < 2; data++) {
+                        if (out) {
+                            int64_t *r = out + count * 5;
+                            r[0] = x; r[1] = d; r[2] = c; r[3] = sch; r[4] = data;
+                        }
+                        count++;
+                    }
+                }
+    }
+    return count;
+}
+
+/*
  * RMSprop (the optimizer section 5.3 selects; Hinton's lecture notes), with
  * the weight decay of section 5.3 entering as an L2 term of the gradient:
  * g' = g + wd w; v <- alpha v + (1 - alpha) g'^2; w <- w - lr g' / (sqrt(v) + eps).
