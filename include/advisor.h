@@ -65,7 +65,9 @@ enum advisor_precision {
 #define ADVISOR_VD_COLS 8
 #define ADVISOR_MAX_LAYERS 9   /* hidden layers + output layer */
 #define ADVISOR_MAX_WIDTH 1024
-#define ADVISOR_MAX_TOP_N 32   /* longest top-N list of advisor_topn_preds / advisor_rank_topn */
+#define ADVISOR_MAX_TOP_N 32
+#define ADVISOR_MAX_LOOPS 4      /* collapsible loops per kernel the variant generator handles */
+#define ADVISOR_VARIANT_COLS 6   /* columns of a generated variant row */   /* longest top-N list of advisor_topn_preds / advisor_rank_topn */
 
 typedef struct advisor_model advisor_model;  /* opaque; owned by the library */
 
@@ -260,6 +262,40 @@ int advisor_topn_preds(const float *pred, const int64_t *offsets, int64_t n_kern
 int advisor_rank_topn(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
                       const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int top_n,
                       int64_t *idx_out, float *val_out, float *pred_out, void *stream);
+
+/*
+ * Variant generation (section 4.1.3). For a kernel with n collapsible loops
+ * (1 <= n <= 4; any other value gives the kernel no variants) loop 0 is
+ * distributed over the teams and the parallel-for directive is placed
+ * either at loop 0, merged into one combined directive with collapse c in
+ * 1..n, or at loop x (1 <= x < n) with teams distribute collapsing d in
+ * 1..x loops and parallel for collapsing c in 1..n-x; every placement takes
+ * each allowed schedule and both data-transfer options. With all three
+ * schedules that is n^3 + 5n variants (6, 18, 42, 84 for n = 1..4).
+ *
+ * advisor_count_variants: n_loops (device, int64 [n_kernels]) ->
+ * offsets_out (device, int64 [n_kernels + 1]): offsets_out[0] = 0 and
+ * offsets_out[k+1] - offsets_out[k] = kernel k's variant count.
+ * sched_mask (1..7) selects schedules: bit 0 static, bit 1 dynamic, bit 2
+ * guided (compilers without dynamic or guided scheduling on the GPU take
+ * 1). n_kernels < 2^31. Allocates and frees a small scratch buffer in
+ * stream order.
+ *
+ * advisor_enumerate_variants: with those offsets and n_variants =
+ * offsets[n_kernels], writes variants_out (device, int64 [n_variants, 6],
+ * row-major): [kernel, x, d, c, schedule (0 static, 1 dynamic, 2 guided),
+ * data option (0, 1)], d = 0 for the combined directive at x = 0. Within a
+ * kernel the rows run over placements (x ascending; at x = 0 c ascending,
+ * then d, c ascending), then allowed schedules ascending, then the data
+ * option. Writes stay inside [0, n_variants) rows whatever the offsets;
+ * rows past a kernel's own count (offsets not from advisor_count_variants)
+ * hold -1.
+ */
+int advisor_count_variants(const int64_t *n_loops, int64_t n_kernels, int sched_mask,
+                           int64_t *offsets_out, void *stream);
+int advisor_enumerate_variants(const int64_t *n_loops, const int64_t *offsets, int64_t n_kernels,
+                               int64_t n_variants, int sched_mask, int64_t *variants_out,
+                               void *stream);
 
 /*
  * Training (section 5.3: the network is fit to measured runtimes with a

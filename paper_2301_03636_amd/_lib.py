@@ -79,6 +79,8 @@ def lib():
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
             "advisor_train_step_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
                                             C.c_float, i32, P, P, P], i32),
+            "advisor_count_variants": ([P, i64, i32, P, P], i32),
+            "advisor_enumerate_variants": ([P, P, i64, i64, i32, P, P], i32),
             "advisor_topn_preds": ([P, P, i64, i64, i32, P, P, P], i32),
             "advisor_rank_topn": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
         }
@@ -293,6 +295,39 @@ def advisor_rank_preds(pred, offsets, best_out=None):
     _check(lib().advisor_rank_preds(_ptr(pred), _ptr(offsets), nk, pred.shape[0], _ptr(best_out),
                                     _stream()), "advisor_rank_preds")
     return best_out
+
+
+def advisor_count_variants(n_loops, sched_mask=7, offsets_out=None):
+    _dev(n_loops, torch.int64, "n_loops")
+    nk = n_loops.shape[0]
+    if offsets_out is None:
+        offsets_out = torch.empty(nk + 1, dtype=torch.int64, device=n_loops.device)
+    _dev(offsets_out, torch.int64, "offsets_out")
+    if offsets_out.numel() != nk + 1:
+        raise ValueError("offsets_out must hold n_kernels + 1 elements")
+    _check(lib().advisor_count_variants(_ptr(n_loops), nk, int(sched_mask), _ptr(offsets_out),
+                                        _stream()), "advisor_count_variants")
+    return offsets_out
+
+
+def advisor_enumerate_variants(n_loops, sched_mask=7, offsets=None, variants_out=None):
+    """(offsets [n_k + 1], variants [n_v, 6]) of section 4.1.3's variant
+    generation; counts first (one host synchronization to size the rows)."""
+    _dev(n_loops, torch.int64, "n_loops")
+    if offsets is None:
+        offsets = advisor_count_variants(n_loops, sched_mask)
+    _dev(offsets, torch.int64, "offsets")
+    nk = n_loops.shape[0]
+    nv = int(offsets[-1].item())
+    if variants_out is None:
+        variants_out = torch.empty((nv, 6), dtype=torch.int64, device=n_loops.device)
+    _dev(variants_out, torch.int64, "variants_out")
+    if variants_out.numel() != nv * 6:
+        raise ValueError("variants_out must hold offsets[-1] rows of 6")
+    _check(lib().advisor_enumerate_variants(_ptr(n_loops), _ptr(offsets), nk, nv, int(sched_mask),
+                                            _ptr(variants_out), _stream()),
+           "advisor_enumerate_variants")
+    return offsets, variants_out
 
 
 def _topn_outputs(nk, top_n, idx_out, val_out, device):

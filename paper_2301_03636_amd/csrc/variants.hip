@@ -1,0 +1,231 @@
+// Variant generation (section 4.1.3): for every kernel with n collapsible
+// loops (1 <= n <= 4), the placements of the parallel-for directive (merged
+// with teams distribute at loop 0 with collapse 1..n; or at loop x, 1 <= x <
+// n, with teams distribute collapsing 1..x loops and parallel for 1..n-x),
+// times the allowed schedules, times the two data-transfer options:
+// n^3 + 5n variants per kernel with all three schedules. Integer work only:
+// a count pass with a prefix sum gives the offsets, then each kernel's rows
+// are written by one wave, every lane decoding the rows of the words it
+// stores so the stores are contiguous.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace adv {
+
+namespace {
+
+constexpr int VG_THREADS = 256;
+constexpr int VG_ITEMS = 4;                        // kernels per thread in the scan
+constexpr int VG_BLOCK = VG_THREADS * VG_ITEMS;    // kernels per scan block
+constexpr int VG_WAVES = VG_THREADS / 64;
+
+// placements of the parallel-for directive for n loops: n + sum x (n - x)
+__device__ __forceinline__ int64_t vg_placements(int64_t n)
+{
+    if (n < 1 || n > ADVISOR_MAX_LOOPS) return 0;
+    int64_t p = n;
+    for (int64_t x = 1; x < n; ++x) p += x * (n - x);
+    return p;
+}
+
+__device__ __forceinline__ int64_t vg_count(int64_t n, int n_sched)
+{
+    return vg_placements(n) * n_sched * 2;
+}
+
+// exclusive prefix sum over the block's threads (LDS, Hillis-Steele)
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, int64_t *total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < VG_THREADS; off <<= 1) {
+        const int64_t add = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const int64_t incl = sh[t];
+    *total = sh[VG_THREADS - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// per-block sums of the variant counts
+__global__ __launch_bounds__(VG_THREADS) void vg_block_sums_kernel(
+    const int64_t *__restrict__ n_loops, int64_t n_k, int n_sched, int64_t *__restrict__ sums)
+{
+    __shared__ int64_t sh[VG_THREADS];
+    const int64_t base = (int64_t)blockIdx.x * VG_BLOCK + (int64_t)threadIdx.x * VG_ITEMS;
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < VG_ITEMS; ++j)
+        if (base + j < n_k) s += vg_count(n_loops[base + j], n_sched);
+    int64_t total;
+    (void)block_exclusive_scan(s, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// exclusive scan of the block sums in place, one workgroup, in chunks
+__global__ __launch_bounds__(VG_THREADS) void vg_scan_sums_kernel(int64_t *__restrict__ sums,
+                                                                 int64_t n_blocks)
+{
+    __shared__ int64_t sh[VG_THREADS];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n_blocks; base += VG_THREADS) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < n_blocks ? sums[i] : 0;
+        int64_t total;
+        const int64_t ex = block_exclusive_scan(v, sh, &total);
+        if (i < n_blocks) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+// offsets[k] = start of kernel k's rows; the last block also writes offsets[n_k]
+__global__ __launch_bounds__(VG_THREADS) void vg_offsets_kernel(
+    const int64_t *__restrict__ n_loops, int64_t n_k, int n_sched,
+    const int64_t *__restrict__ sums, int64_t *__restrict__ offsets)
+{
+    __shared__ int64_t sh[VG_THREADS];
+    const int64_t base = (int64_t)blockIdx.x * VG_BLOCK + (int64_t)threadIdx.x * VG_ITEMS;
+    int64_t c[VG_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < VG_ITEMS; ++j) {
+        c[j] = base + j < n_k ? vg_count(n_loops[base + j], n_sched) : 0;
+        s += c[j];
+    }
+    int64_t total;
+    int64_t run = sums[blockIdx.x] + block_exclusive_scan(s, sh, &total);
+#pragma unroll
+    for (int j = 0; j < VG_ITEMS; ++j) {
+        if (base + j < n_k) offsets[base + j] = run;
+        run += c[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == VG_THREADS - 1) offsets[n_k] = run;
+}
+
+__global__ void vg_zero_kernel(int64_t *p) { *p = 0; }
+
+// One wave per kernel: the segment's words [6 off[k], 6 off[k+1]), clamped to
+// the output, written in order; the word's row r (local index) decodes as
+// data = r mod 2, schedule = the (r / 2 mod n_sched)-th allowed schedule,
+// placement = r / (2 n_sched) in the order x = 0 (c = 1..n), then x = 1..n-1
+// with (d, c) row-major over 1..x by 1..n-x. Rows past the kernel's own
+// count (offsets not from the count pass) are written as -1.
+__global__ __launch_bounds__(VG_THREADS) void vg_rows_kernel(
+    const int64_t *__restrict__ n_loops, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, int sched_mask, int n_sched, int64_t *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * VG_WAVES;
+    for (int64_t k = (int64_t)blockIdx.x * VG_WAVES + (threadIdx.x >> 6); k < n_k; k += nwaves) {
+        const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
+        const int64_t hi = max(lo, min(offsets[k + 1], n_v));
+        const int64_t n = n_loops[k];
+        const int64_t cnt = vg_count(n, n_sched);
+        const int64_t seg0 = offsets[k];
+        for (int64_t w = lo * ADVISOR_VARIANT_COLS + lane; w < hi * ADVISOR_VARIANT_COLS; w += 64) {
+            const int64_t row = w / ADVISOR_VARIANT_COLS;
+            const int col = (int)(w - row * ADVISOR_VARIANT_COLS);
+            const int64_t r = row - seg0;
+            int64_t val = -1;
+            if (r >= 0 && r < cnt) {
+                const int64_t data = r & 1;
+                const int64_t q = r >> 1;
+                const int si = (int)(q % n_sched);
+                int64_t p = q / n_sched;
+                int sch = 0;
+                for (int b = 0, seen = 0; b < 3; ++b)
+                    if ((sched_mask >> b) & 1) {
+                        if (seen == si) sch = b;
+                        ++seen;
+                    }
+                int64_t x = 0, d = 0, c = 0;
+                if (p < n) {
+                    c = p + 1;
+                } else {
+                    p -= n;
+                    for (x = 1; x < n; ++x) {
+                        const int64_t m = x * (n - x);
+                        if (p < m) break;
+                        p -= m;
+                    }
+                    d = p / (n - x) + 1;
+                    c = p % (n - x) + 1;
+                }
+                const int64_t vals[ADVISOR_VARIANT_COLS] = {k, x, d, c, sch, data};
+                val = vals[0];
+#pragma unroll
+                for (int j = 1; j < ADVISOR_VARIANT_COLS; ++j)
+                    if (col == j) val = vals[j];
+            }
+            out[w] = val;
+        }
+    }
+}
+
+int check_variant_args(const int64_t *n_loops, int64_t n_k, int sched_mask)
+{
+    if (sched_mask < 1 || sched_mask > 7) return fail(ADVISOR_EINVAL, "sched_mask must be in [1, 7]");
+    if (n_k < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_k >= (int64_t)1 << 31) return fail(ADVISOR_ESHAPE, "n_kernels must be < 2^31");
+    if (n_k > 0 && !n_loops) return fail(ADVISOR_EINVAL, "null n_loops");
+    return ADVISOR_OK;
+}
+
+}  // namespace
+
+}  // namespace adv
+
+using namespace adv;
+
+extern "C" int advisor_count_variants(const int64_t *n_loops, int64_t n_kernels, int sched_mask,
+                                      int64_t *offsets_out, void *stream)
+{
+    clear_error();
+    if (int rc = check_variant_args(n_loops, n_kernels, sched_mask)) return rc;
+    if (!offsets_out) return fail(ADVISOR_EINVAL, "null offsets_out");
+    hipStream_t s = as_stream(stream);
+    if (n_kernels == 0) {
+        hipLaunchKernelGGL(vg_zero_kernel, dim3(1), dim3(1), 0, s, offsets_out);
+        ADV_LAUNCHED("vg_zero_kernel");
+        return ADVISOR_OK;
+    }
+    const int n_sched = __builtin_popcount((unsigned)sched_mask);
+    const int64_t n_blocks = (n_kernels + VG_BLOCK - 1) / VG_BLOCK;
+    int64_t *sums = nullptr;
+    ADV_HIP(hipMallocAsync((void **)&sums, sizeof(int64_t) * n_blocks, s));
+    hipLaunchKernelGGL(vg_block_sums_kernel, dim3((unsigned)n_blocks), dim3(VG_THREADS), 0, s,
+                       n_loops, n_kernels, n_sched, sums);
+    hipLaunchKernelGGL(vg_scan_sums_kernel, dim3(1), dim3(VG_THREADS), 0, s, sums, n_blocks);
+    hipLaunchKernelGGL(vg_offsets_kernel, dim3((unsigned)n_blocks), dim3(VG_THREADS), 0, s,
+                       n_loops, n_kernels, n_sched, (const int64_t *)sums, offsets_out);
+    hipError_t le = hipGetLastError();
+    hipError_t fe = hipFreeAsync(sums, s);
+    if (le != hipSuccess) return hip_fail(le, "variant count kernels");
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+    return ADVISOR_OK;
+}
+
+extern "C" int advisor_enumerate_variants(const int64_t *n_loops, const int64_t *offsets,
+                                          int64_t n_kernels, int64_t n_variants, int sched_mask,
+                                          int64_t *variants_out, void *stream)
+{
+    clear_error();
+    if (int rc = check_variant_args(n_loops, n_kernels, sched_mask)) return rc;
+    if (n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= ((int64_t)1 << 62) / ADVISOR_VARIANT_COLS)
+        return fail(ADVISOR_ESHAPE, "n_variants too large");
+    if (n_kernels == 0 || n_variants == 0) return ADVISOR_OK;
+    if (!offsets || !variants_out) return fail(ADVISOR_EINVAL, "advisor_enumerate_variants: null pointer");
+    hipStream_t s = as_stream(stream);
+    const int n_sched = __builtin_popcount((unsigned)sched_mask);
+    const int64_t blocks = std::min<int64_t>((n_kernels + VG_WAVES - 1) / VG_WAVES, 1 << 20);
+    hipLaunchKernelGGL(vg_rows_kernel, dim3((unsigned)blocks), dim3(VG_THREADS), 0, s, n_loops,
+                       offsets, n_kernels, n_variants, sched_mask, n_sched, variants_out);
+    ADV_LAUNCHED("vg_rows_kernel");
+    return ADVISOR_OK;
+}

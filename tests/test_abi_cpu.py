@@ -137,3 +137,16 @@ def test_rmsprop_argument_checks():
     assert L.advisor_train_step_rmsprop(None, v, v, 16, f(1e-2), f(0.99), f(1e-8), f(1e-4), 1,
                                         None, None, None) == EINVAL
     assert "null" in _lib.last_error() or "model" in _lib.last_error()
+
+
+def test_variant_generation_argument_checks():
+    L = _lib.lib()
+    v = C.c_void_p(8)
+    assert L.advisor_count_variants(v, 4, 0, v, None) == EINVAL
+    assert L.advisor_count_variants(v, 4, 8, v, None) == EINVAL
+    assert L.advisor_count_variants(None, 4, 7, v, None) == EINVAL
+    assert L.advisor_count_variants(v, -1, 7, v, None) == ESHAPE
+    assert L.advisor_count_variants(v, 4, 7, None, None) == EINVAL
+    assert L.advisor_enumerate_variants(v, v, 4, -1, 7, v, None) == ESHAPE
+    assert L.advisor_enumerate_variants(v, None, 4, 10, 7, v, None) == EINVAL
+    assert L.advisor_enumerate_variants(v, v, 0, 0, 7, None, None) == OK
