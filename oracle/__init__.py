@@ -66,6 +66,10 @@ def _load():
         lib.oracle_rmsprop.restype = None
         lib.oracle_enumerate.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_enumerate.restype = i64
+        lib.oracle_map_class.argtypes = [C.c_int]
+        lib.oracle_map_class.restype = C.c_int
+        lib.oracle_classify.argtypes = [P, P, P, i64, P, P, P, P]
+        lib.oracle_classify.restype = None
         lib.oracle_rank.argtypes = [P, P, P, i64, i64, P, C.c_int, P, P, P, P, P, C.c_int]
         lib.oracle_rank.restype = C.c_int
         lib.oracle_max_threads.argtypes = []
@@ -209,6 +213,23 @@ def step_lr(epoch, lr0=1e-2, gamma=0.1, every=30):
     """The learning-rate schedule of section 5.3: lr0, multiplied by gamma
     after every `every` epochs."""
     return lr0 * gamma ** (int(epoch) // int(every))
+
+
+def map_class(bits):
+    """Section 4.1.2's map class of one variable from its access bits."""
+    return _load().oracle_map_class(int(bits))
+
+
+def classify(access, nbytes, var_offsets):
+    """(class [n_vars] uint8, enter, exit, naive bytes [n_k] int64)."""
+    acc = _c(access, np.uint8)
+    b = _c(nbytes, np.int64)
+    off = _c(var_offsets, np.int64)
+    nk = off.size - 1
+    cls = np.zeros(acc.size, dtype=np.uint8)
+    e, x, nv = (np.zeros(nk, dtype=np.int64) for _ in range(3))
+    _load().oracle_classify(_p(acc), _p(b), _p(off), nk, _p(cls), _p(e), _p(x), _p(nv))
+    return cls, e, x, nv
 
 
 def enumerate_variants(n_loops, sched_mask=7):

@@ -391,6 +391,59 @@ void oracle_adam(double *w, double *m, double *v, const double *g, int64_t n, in
 }
 
 /*
+ * Data analysis of section 4.1.2: the map class of each variable a kernel
+ * uses, from what happens to it before, during and after the kernel. The
+ * access bits: 1 assigned before the kernel, 2 read within it, 4 written
+ * (assigned or updated) within it, 8 accessed after it, 16 declared within
+ * it. Classes (codes shared with the descriptors' data classes):
+ *   0 alloc   - first assigned within the kernel, not needed after it;
+ *   1 to      - assigned before and only read within (not modified);
+ *   2 from    - updated within and accessed after, not assigned before;
+ *   3 tofrom  - assigned before, updated within and accessed after;
+ *   4 private - declared within the kernel;
+ *   5 none    - neither read nor written within (not a kernel variable).
+ * Patterns the five definitions leave open take the choice that moves the
+ * data the kernel may need: a variable read within but never modified is
+ * "to" even without an assignment before; one assigned before, updated and
+ * read within but not needed after is "to"; one assigned before and only
+ * written within (its old value never read) and not needed after is alloc.
+ */
+int oracle_map_class(int bits)
+{
+    int before = bits & 1, rd = (bits >> 1) & 1, wr = (bits >> 2) & 1, after = (bits >> 3) & 1;
+    if (bits & 16) return 4;
+    if (!rd && !wr) return 5;
+    if (!wr) return 1;
+    if (after) return before ? 3 : 2;
+    return (before && rd) ? 1 : 0;
+}
+
+/*
+ * Per kernel k (variables [var_off[k], var_off[k+1])): the class of every
+ * variable, and the bytes of the enter-data directive's transfers (to and
+ * tofrom variables), of the exit-data directive's (from and tofrom), and of
+ * mapping every variable the kernel uses (classes 0-3) to and from the GPU,
+ * the untransformed code of section 5.1's first experiment.
+ */
+void oracle_classify(const uint8_t *access, const int64_t *bytes, const int64_t *var_off,
+                     int64_t n_k, uint8_t *cls, int64_t *enter, int64_t *exit_, int64_t *naive)
+{
+    for (int64_t k = 0; k < n_k; k++) {
+        int64_t e = 0, x = 0, nv = 0;
+        for (int64_t i = var_off[k]; i < var_off[k + 1]; i++) {
+            int c = oracle_map_class(access[i]);
+            cls[i] = (uint8_t)c;
+            if (c == 1 || c == 3) e += bytes[i];
+            if (c == 2 || c == 3) x += bytes[i];
+            if (c <= 3) nv += 2 * bytes[i];
+        }
+        enter[k] = e;
+        exit_[k] = x;
+        naive[k] = nv;
+    }
+}
+
+/*
  * Variant generation of section 4.1.3 for one kernel with n collapsible
  * loops (1 <= n <= 4; any other n gives no variant). Loop 0 is always
  * distributed over the teams. The parallel-for directive sits at loop x:
