@@ -264,6 +264,41 @@ int advisor_rank_topn(advisor_model *model, const int64_t *kdesc, const int64_t 
                       int64_t *idx_out, float *val_out, float *pred_out, void *stream);
 
 /*
+ * Data analysis (section 4.1.2). Access bits of a variable a kernel may use
+ * (OR of ADVISOR_ACC_*), and the map classes they give (ADVISOR_MAP_*; the
+ * first four are the data classes of the kernel descriptor's req columns):
+ *   alloc   - first assigned within the kernel and not needed after it;
+ *   to      - assigned before and only read within;
+ *   from    - updated within and accessed after, not assigned before;
+ *   tofrom  - assigned before, updated within and accessed after;
+ *   private - declared within the kernel;
+ *   none    - neither read nor written within.
+ * Patterns those definitions leave open: read within but never modified is
+ * to (assigned before or not); assigned before, read and updated within but
+ * not needed after is to; assigned before, only written within and not
+ * needed after is alloc.
+ *
+ * advisor_classify_maps: access (device, uint8 [n_vars]) and nbytes
+ * (device, int64 [n_vars], each variable's mapped extent in bytes), grouped
+ * per kernel by var_offsets (device, int64 [n_kernels + 1]); writes
+ * class_out (device, uint8 [n_vars]) and per kernel enter_bytes (to and
+ * tofrom bytes, sent by the enter-data directive), exit_bytes (from and
+ * tofrom bytes, returned by the exit-data directive) and naive_bytes (twice
+ * the bytes of every alloc/to/from/tofrom variable: the code that maps
+ * everything to and from the GPU), each device int64 [n_kernels]. Any
+ * output may be NULL. Offsets are clamped to [0, n_vars]. Sums wrap modulo
+ * 2^64.
+ */
+enum { ADVISOR_ACC_BEFORE = 1, ADVISOR_ACC_READ = 2, ADVISOR_ACC_WRITE = 4,
+       ADVISOR_ACC_AFTER = 8, ADVISOR_ACC_LOCAL = 16 };
+enum { ADVISOR_MAP_ALLOC = 0, ADVISOR_MAP_TO = 1, ADVISOR_MAP_FROM = 2, ADVISOR_MAP_TOFROM = 3,
+       ADVISOR_MAP_PRIVATE = 4, ADVISOR_MAP_NONE = 5 };
+int advisor_classify_maps(const uint8_t *access, const int64_t *nbytes, const int64_t *var_offsets,
+                          int64_t n_kernels, int64_t n_vars, uint8_t *class_out,
+                          int64_t *enter_bytes, int64_t *exit_bytes, int64_t *naive_bytes,
+                          void *stream);
+
+/*
  * Variant generation (section 4.1.3). For a kernel with n collapsible loops
  * (1 <= n <= 4; any other value gives the kernel no variants) loop 0 is
  * distributed over the teams and the parallel-for directive is placed

@@ -79,6 +79,7 @@ def lib():
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
             "advisor_train_step_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
                                             C.c_float, i32, P, P, P], i32),
+            "advisor_classify_maps": ([P, P, P, i64, i64, P, P, P, P, P], i32),
             "advisor_count_variants": ([P, i64, i32, P, P], i32),
             "advisor_enumerate_variants": ([P, P, i64, i64, i32, P, P], i32),
             "advisor_topn_preds": ([P, P, i64, i64, i32, P, P, P], i32),
@@ -295,6 +296,25 @@ def advisor_rank_preds(pred, offsets, best_out=None):
     _check(lib().advisor_rank_preds(_ptr(pred), _ptr(offsets), nk, pred.shape[0], _ptr(best_out),
                                     _stream()), "advisor_rank_preds")
     return best_out
+
+
+def advisor_classify_maps(access, nbytes, var_offsets):
+    """(class [n_vars] uint8, enter, exit, naive bytes [n_k] int64) of
+    section 4.1.2's data analysis."""
+    _dev(access, torch.uint8, "access")
+    _dev(nbytes, torch.int64, "nbytes")
+    _dev(var_offsets, torch.int64, "var_offsets")
+    nk = var_offsets.shape[0] - 1
+    nv = access.shape[0]
+    if nbytes.shape[0] != nv:
+        raise ValueError("access and nbytes differ in length")
+    dev = access.device
+    cls = torch.empty(nv, dtype=torch.uint8, device=dev)
+    e, x, n = (torch.empty(nk, dtype=torch.int64, device=dev) for _ in range(3))
+    _check(lib().advisor_classify_maps(_ptr(access), _ptr(nbytes), _ptr(var_offsets), nk, nv,
+                                       _ptr(cls), _ptr(e), _ptr(x), _ptr(n), _stream()),
+           "advisor_classify_maps")
+    return cls, e, x, n
 
 
 def advisor_count_variants(n_loops, sched_mask=7, offsets_out=None):

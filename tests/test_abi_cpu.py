@@ -150,3 +150,12 @@ def test_variant_generation_argument_checks():
     assert L.advisor_enumerate_variants(v, v, 4, -1, 7, v, None) == ESHAPE
     assert L.advisor_enumerate_variants(v, None, 4, 10, 7, v, None) == EINVAL
     assert L.advisor_enumerate_variants(v, v, 0, 0, 7, None, None) == OK
+
+
+def test_classify_maps_argument_checks():
+    L = _lib.lib()
+    v = C.c_void_p(8)
+    assert L.advisor_classify_maps(v, v, None, 2, 5, None, None, None, None, None) == EINVAL
+    assert L.advisor_classify_maps(None, v, v, 2, 5, None, None, None, None, None) == EINVAL
+    assert L.advisor_classify_maps(v, v, v, -1, 5, None, None, None, None, None) == ESHAPE
+    assert L.advisor_classify_maps(None, None, None, 0, 0, None, None, None, None, None) == OK
