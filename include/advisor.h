@@ -201,6 +201,19 @@ int advisor_rank(const advisor_model *model, const int64_t *kdesc, const int64_t
                  int64_t *best_out, float *pred_out, void *stream);
 
 /*
+ * Multi-target prediction (section 3 trains one model per cluster and GPU
+ * architecture): the same variants ranked by n_models models, each a fused
+ * pass as advisor_rank. best_out (device, int64 [n_models, n_kernels],
+ * row-major) receives target t's winners in row t; pred_out (device, float
+ * [n_models, n_variants], may be NULL) its predictions. Models may differ
+ * in widths and precision; all must live on the current device. Each row
+ * equals advisor_rank with that model, bit for bit.
+ */
+int advisor_rank_multi(const advisor_model *const *models, int n_models, const int64_t *kdesc,
+                       const int64_t *vdesc, const int64_t *offsets, int64_t n_kernels,
+                       int64_t n_variants, int64_t *best_out, float *pred_out, void *stream);
+
+/*
  * Precision-refined ranking (the prediction flow of section 3, N = 1, with
  * the argmin decided in two precisions). `model` (any precision) ranks every
  * variant as advisor_rank does; then, per kernel, its top_k variants by

@@ -14,6 +14,7 @@ from ._lib import (AdvisorError, PRECISIONS, advisor_featurize, advisor_model_cr
                    advisor_plan_destroy, advisor_autotune, advisor_model_set_tile_variant,
                    advisor_model_get_tile_variant, advisor_validate_offsets, advisor_topn_preds,
                    advisor_rank_topn, advisor_train_step_rmsprop,
-                   advisor_count_variants, advisor_enumerate_variants, advisor_classify_maps)
+                   advisor_count_variants, advisor_enumerate_variants, advisor_classify_maps,
+                   advisor_rank_multi)
 from .model import Model, Plan  # noqa: F401
 from .train import MLPFunction, RMSpropTrainer, Trainer, mlp, step_lr  # noqa: F401

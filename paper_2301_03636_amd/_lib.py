@@ -79,6 +79,7 @@ def lib():
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
             "advisor_train_step_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
                                             C.c_float, i32, P, P, P], i32),
+            "advisor_rank_multi": ([P, i32, P, P, P, i64, i64, P, P, P], i32),
             "advisor_classify_maps": ([P, P, P, i64, i64, P, P, P, P, P], i32),
             "advisor_count_variants": ([P, i64, i32, P, P], i32),
             "advisor_enumerate_variants": ([P, P, i64, i64, i32, P, P], i32),
@@ -254,6 +255,30 @@ def advisor_rank(h, kdesc, vdesc, offsets, best_out=None, pred_out=None, want_pr
     _dev(pred_out, torch.float32, "pred_out")
     _check(lib().advisor_rank(h, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
                               _ptr(best_out), _ptr(pred_out), _stream()), "advisor_rank")
+    return (best_out, pred_out) if want_pred or pred_out is not None else best_out
+
+
+def advisor_rank_multi(handles, kdesc, vdesc, offsets, best_out=None, pred_out=None,
+                       want_pred=False):
+    """Rank the same variants by several models (one per target): best
+    [n_models, n_k] (and pred [n_models, n_v])."""
+    for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
+        _dev(t, torch.int64, nm)
+    nm_ = len(handles)
+    nk = offsets.shape[0] - 1
+    nv = vdesc.shape[0]
+    if best_out is None:
+        best_out = torch.empty((nm_, nk), dtype=torch.int64, device=vdesc.device)
+    if pred_out is None and want_pred:
+        pred_out = torch.empty((nm_, nv), dtype=torch.float32, device=vdesc.device)
+    _dev(best_out, torch.int64, "best_out")
+    _dev(pred_out, torch.float32, "pred_out")
+    if best_out.numel() != nm_ * nk or (pred_out is not None and pred_out.numel() != nm_ * nv):
+        raise ValueError("output sizes do not match n_models x n_kernels / n_variants")
+    arr = (C.c_void_p * max(nm_, 1))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    _check(lib().advisor_rank_multi(arr, nm_, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
+                                    _ptr(best_out), _ptr(pred_out), _stream()),
+           "advisor_rank_multi")
     return (best_out, pred_out) if want_pred or pred_out is not None else best_out
 
 

@@ -339,6 +339,30 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
     return ADVISOR_OK;
 }
 
+extern "C" int advisor_rank_multi(const advisor_model *const *models, int n_models,
+                                  const int64_t *kdesc, const int64_t *vdesc,
+                                  const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
+                                  int64_t *best_out, float *pred_out, void *stream)
+{
+    clear_error();
+    if (n_models < 1 || !models) return fail(ADVISOR_EINVAL, "need at least one model");
+    for (int t = 0; t < n_models; ++t) {
+        if (int rc = check_model_ready(models[t])) return rc;
+        if (models[t]->device != models[0]->device)
+            return fail(ADVISOR_EINVAL, "the models live on different devices");
+    }
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_kernels == 0) return ADVISOR_OK;
+    if (!best_out) return fail(ADVISOR_EINVAL, "advisor_rank_multi: null best_out");
+    for (int t = 0; t < n_models; ++t) {
+        int rc = advisor_rank(models[t], kdesc, vdesc, offsets, n_kernels, n_variants,
+                              best_out + (int64_t)t * n_kernels,
+                              pred_out ? pred_out + (int64_t)t * n_variants : nullptr, stream);
+        if (rc) return rc;
+    }
+    return ADVISOR_OK;
+}
+
 extern "C" int advisor_profile_enable(int on)
 {
     clear_error();

@@ -159,3 +159,10 @@ def test_classify_maps_argument_checks():
     assert L.advisor_classify_maps(None, v, v, 2, 5, None, None, None, None, None) == EINVAL
     assert L.advisor_classify_maps(v, v, v, -1, 5, None, None, None, None, None) == ESHAPE
     assert L.advisor_classify_maps(None, None, None, 0, 0, None, None, None, None, None) == OK
+
+
+def test_rank_multi_argument_checks():
+    L = _lib.lib()
+    assert L.advisor_rank_multi(None, 0, None, None, None, 1, 1, None, None, None) == EINVAL
+    arr = (C.c_void_p * 1)(None)
+    assert L.advisor_rank_multi(arr, 1, None, None, None, 1, 1, None, None, None) == EINVAL
