@@ -459,6 +459,12 @@ int advisor_rank_plan_create(const advisor_model *model, const int64_t *kdesc,
 int advisor_train_plan_create(advisor_model *model, const int64_t *feat, const double *y,
                               int64_t n, float lr, float beta1, float beta2, float eps,
                               double *loss_out, double *gnorm_out, advisor_plan **out);
+/* advisor_train_step_rmsprop captured the same way; lr is fixed in the plan,
+ * so a stepped schedule takes one plan per learning rate. */
+int advisor_train_plan_create_rmsprop(advisor_model *model, const int64_t *feat, const double *y,
+                                      int64_t n, float lr, float alpha, float eps,
+                                      float weight_decay, int loss, double *loss_out,
+                                      double *gnorm_out, advisor_plan **out);
 int advisor_plan_launch(advisor_plan *plan, void *stream);
 void advisor_plan_destroy(advisor_plan *plan);
 

@@ -79,6 +79,9 @@ def lib():
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
             "advisor_train_step_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
                                             C.c_float, i32, P, P, P], i32),
+            "advisor_train_plan_create_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
+                                                   C.c_float, i32, P, P, C.POINTER(C.c_void_p)],
+                                                  i32),
             "advisor_rank_multi": ([P, i32, P, P, P, i64, i64, P, P, P], i32),
             "advisor_classify_maps": ([P, P, P, i64, i64, P, P, P, P, P], i32),
             "advisor_count_variants": ([P, i64, i32, P, P], i32),
@@ -547,6 +550,21 @@ def advisor_train_plan_create(h, feat, y, loss_out, gnorm_out, lr=1e-3, beta1=0.
     _check(lib().advisor_train_plan_create(h, _ptr(feat), _ptr(y), feat.shape[0], lr, beta1, beta2,
                                            eps, _ptr(loss_out), _ptr(gnorm_out), C.byref(p)),
            "advisor_train_plan_create")
+    return p
+
+
+def advisor_train_plan_create_rmsprop(h, feat, y, loss_out, gnorm_out, lr=1e-2, alpha=0.99,
+                                      eps=1e-8, weight_decay=1e-4, loss="rmse"):
+    _dev(feat, torch.int64, "feat")
+    for t, nm in ((y, "y"), (loss_out, "loss_out"), (gnorm_out, "gnorm_out")):
+        _dev(t, torch.float64, nm)
+    if loss not in LOSSES:
+        raise ValueError("loss must be one of %s" % sorted(LOSSES))
+    p = C.c_void_p()
+    _check(lib().advisor_train_plan_create_rmsprop(h, _ptr(feat), _ptr(y), feat.shape[0], lr, alpha,
+                                                   eps, weight_decay, LOSSES[loss], _ptr(loss_out),
+                                                   _ptr(gnorm_out), C.byref(p)),
+           "advisor_train_plan_create_rmsprop")
     return p
 
 

@@ -107,6 +107,30 @@ extern "C" int advisor_train_plan_create(advisor_model *model, const int64_t *fe
         out);
 }
 
+extern "C" int advisor_train_plan_create_rmsprop(advisor_model *model, const int64_t *feat,
+                                                 const double *y, int64_t n, float lr,
+                                                 float alpha, float eps, float weight_decay,
+                                                 int loss, double *loss_out, double *gnorm_out,
+                                                 advisor_plan **out)
+{
+    clear_error();
+    if (!out) return fail(ADVISOR_EINVAL, "advisor_train_plan_create_rmsprop: out is null");
+    *out = nullptr;
+    if (!model) return fail(ADVISOR_EINVAL, "null model");
+    if (n < 1 || n >= ((int64_t)1 << 32)) return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+    int rc = reserve_train_ws(model, n);
+    if (rc) return rc;
+    rc = repack_transposed_now(model, nullptr);
+    if (rc) return rc;
+    ADV_HIP(hipDeviceSynchronize());
+    return capture(
+        [&](hipStream_t cs) {
+            return advisor_train_step_rmsprop(model, feat, y, n, lr, alpha, eps, weight_decay, loss,
+                                              loss_out, gnorm_out, cs);
+        },
+        out);
+}
+
 extern "C" int advisor_plan_launch(advisor_plan *p, void *stream)
 {
     clear_error();

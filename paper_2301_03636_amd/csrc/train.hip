@@ -514,15 +514,30 @@ __global__ __launch_bounds__(RT) void sumsq_kernel(const float *__restrict__ g, 
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// Sum of the RB partials by one wave in a fixed order: lane l adds
+// part[4l .. 4l+3] in turn, then a butterfly over the lanes (each addition
+// pairs the same two values in every lane, so all lanes hold the same,
+// run-to-run identical sum). Launched as one workgroup of 64 threads.
+static_assert(RB == 4 * 64, "one wave, four partials per lane");
+__device__ __forceinline__ double wave_sum_partials(const double *__restrict__ part)
+{
+    const int l = threadIdx.x & 63;
+    double s = part[4 * l];
+    s += part[4 * l + 1];
+    s += part[4 * l + 2];
+    s += part[4 * l + 3];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
 // out = scale * sum(part[0..RB)), then sqrt if asked.
 __global__ void finish_kernel(const double *__restrict__ part, double scale, int take_sqrt,
                               double *__restrict__ out)
 {
-    if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int i = 0; i < RB; ++i) s += part[i];
+    double s = wave_sum_partials(part);
     s *= scale;
-    *out = take_sqrt ? sqrt(s) : s;
+    if (threadIdx.x == 0) *out = take_sqrt ? sqrt(s) : s;
 }
 
 // Adam step counter lives on the device so a captured step replays correctly.
@@ -558,10 +573,8 @@ __global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float 
 __global__ void loss_scale_kernel(const double *__restrict__ part, double inv_n, int rmse,
                                   double *__restrict__ scale, double *__restrict__ loss_out)
 {
+    const double mse = wave_sum_partials(part) * inv_n;
     if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int i = 0; i < RB; ++i) s += part[i];
-    const double mse = s * inv_n;
     const double r = sqrt(mse);
     scale[0] = rmse ? (r > 0.0 ? 0.5 / r : 0.0) : 1.0;
     if (loss_out) *loss_out = rmse ? r : mse;
@@ -571,10 +584,8 @@ __global__ void loss_scale_kernel(const double *__restrict__ part, double inv_n,
 __global__ void scaled_norm_kernel(const double *__restrict__ part,
                                    const double *__restrict__ scale, double *__restrict__ out)
 {
-    if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int i = 0; i < RB; ++i) s += part[i];
-    *out = sqrt(s) * scale[0];
+    const double s = wave_sum_partials(part);
+    if (threadIdx.x == 0) *out = sqrt(s) * scale[0];
 }
 
 // RMSprop (section 5.3's optimizer) on fp32 master weights with weight

@@ -89,6 +89,13 @@ class Plan:
                                            beta2, eps)
         return cls(h, (model, feat, y, loss_out, gnorm_out))
 
+    @classmethod
+    def train_rmsprop(cls, model, feat, y, loss_out, gnorm_out, lr=1e-2, alpha=0.99, eps=1e-8,
+                      weight_decay=1e-4, loss="rmse"):
+        h = _lib.advisor_train_plan_create_rmsprop(model.handle, feat, y, loss_out, gnorm_out, lr,
+                                                   alpha, eps, weight_decay, loss)
+        return cls(h, (model, feat, y, loss_out, gnorm_out))
+
     def launch(self):
         _lib.advisor_plan_launch(self.handle)
 

@@ -152,3 +152,49 @@ def test_rmsprop_recipe_reaches_nrmse_bar():
         (losses[0], losses[-1], rmse, nrmse))
     assert losses[-1] < losses[0]
     assert nrmse < 0.1
+
+
+@pytest.mark.parametrize("precision,n", [("fp32", 16), ("bf16", 3000)])
+def test_rmsprop_plan_replays_match_eager_steps(precision, n):
+    """A captured RMSprop step (the paper's batch of 16 rows, and a larger
+    one) replays exactly the eager step, with eager work and device
+    synchronizations between replays; the eager and replayed step times at
+    batch 16 are printed."""
+    import time
+    widths = (32, 64, 128, 64, 32, 1)
+    f, y, mu, sd = _batch(max(n, 600), 451)
+    f, y = f[:n], y[:n]
+    p0 = workload.he_init(widths, 452)
+    F, Y = to_dev(f), to_dev(y)
+    a = adv.Model(widths, precision)
+    a.set_params(p0, mu, sd)
+    b = adv.Model(widths, precision)
+    b.set_params(p0, mu, sd)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    gn = torch.empty(1, dtype=torch.float64, device="cuda")
+    plan = adv.Plan.train_rmsprop(b, F, Y, loss, gn, lr=1e-2, weight_decay=1e-4)
+    wb, _, _ = b.get_params()
+    assert np.array_equal(wb, p0)  # creating the plan ran no step
+    for step in range(3):
+        la, ga = adv.advisor_train_step_rmsprop(a.handle, F, Y, lr=1e-2, weight_decay=1e-4)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        wa, _, _ = a.get_params()
+        wb, _, _ = b.get_params()
+        assert np.array_equal(wa.view(np.int32), wb.view(np.int32)), step
+        assert host(la)[0] == host(loss)[0] and host(ga)[0] == host(gn)[0], step
+        assert np.isfinite(host(b.predict(F))).all()
+    if n == 16:
+        reps = 200
+        for name, fn in (("eager", lambda: adv.advisor_train_step_rmsprop(
+                a.handle, F, Y, lr=1e-2, weight_decay=1e-4, loss_out=loss, gnorm_out=gn)),
+                         ("plan", plan.launch)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            say("batch-16 RMSprop step, %s: %.1f us" % (name, (time.perf_counter() - t0) / reps * 1e6))
+    plan.close()
