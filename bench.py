@@ -377,6 +377,16 @@ def train_leg(adv, torch, d, steps, warmup):
         adv.advisor_train_step(m.handle, feat, y, 1e-3, 0.9, 0.999, 1e-8, loss, gn)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    loss_adam = float(loss.item())
+    # the paper's optimizer on the same batch (RMSprop, weight decay, RMSE loss)
+    for _ in range(max(1, warmup)):
+        adv.advisor_train_step_rmsprop(m.handle, feat, y, 1e-3, 0.99, 1e-8, 1e-4, "rmse", loss, gn)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        adv.advisor_train_step_rmsprop(m.handle, feat, y, 1e-3, 0.99, 1e-8, 1e-4, "rmse", loss, gn)
+    torch.cuda.synchronize()
+    ms_rms = (time.perf_counter() - t0) * 1e3 / steps
     m.close()
     fps = train_flops_per_sample(widths)
     tflops = fps * B / (ms / 1e3) / 1e12
@@ -388,7 +398,8 @@ def train_leg(adv, torch, d, steps, warmup):
             "roofline_frac": tflops / PEAK_TFLOPS["bf16"],
             "hbm_bytes_per_step": nbytes, "hbm_gbs": nbytes / (ms / 1e3) / 1e9,
             "hbm_frac": nbytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS,
-            "loss_last": float(loss.item())}
+            "rmsprop_rmse_ms_per_step": ms_rms,
+            "loss_last": loss_adam}
 
 
 def train_bytes_per_step(widths, batch, m_params):
