@@ -541,22 +541,28 @@ __global__ void finish_kernel(const double *__restrict__ part, double scale, int
 }
 
 // Adam step counter lives on the device so a captured step replays correctly.
-__global__ void step_inc_kernel(int64_t *step)
+// The same thread forms the step's bias corrections 1 - b^t in float64 once
+// (corr[0], corr[1]) for every element of the update to read.
+__global__ void step_inc_kernel(int64_t *step, float b1, float b2, double *corr)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t t = *step + 1;
+        *step = t;
+        corr[0] = 1.0 - pow((double)b1, (double)t);
+        corr[1] = 1.0 - pow((double)b2, (double)t);
+    }
 }
 
-// Adam (Kingma and Ba) on fp32 master weights, t = *step (already
-// incremented); the bias corrections 1 - b^t are formed in float64.
+// Adam (Kingma and Ba) on fp32 master weights with the bias corrections of
+// the current step (corr, from step_inc_kernel).
 __global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
                             const float *__restrict__ g, int64_t n, float lr, float b1, float b2,
-                            float eps, const int64_t *__restrict__ step)
+                            float eps, const double *__restrict__ corr)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double t = (double)*step;
-    const float c1 = (float)(1.0 - pow((double)b1, t));
-    const float c2 = (float)(1.0 - pow((double)b2, t));
+    const float c1 = (float)corr[0];
+    const float c2 = (float)corr[1];
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -622,7 +628,8 @@ struct TrainWs {
     float *pred = nullptr;
     float *dy = nullptr;
     float *grads = nullptr;
-    double *red = nullptr;    // 2 x RB partials, then scalars (red[2 RB] = loss gradient scale)
+    double *red = nullptr;    // 2 x RB partials, then scalars: red[2 RB] loss gradient scale,
+                              // red[2 RB + 2 ..] Adam's bias corrections
     void *wt[MAX_LAYERS] = {nullptr};
     size_t partial_floats = 0;
 };
@@ -746,6 +753,111 @@ static int repack_transposed(advisor_model *m, hipStream_t s)
                                m->widths[l + 1], m->widths[l], tw, w->wt[l]);
         ADV_LAUNCHED("pack_transposed_kernel");
     }
+    m->wt_valid = true;
+    return ADVISOR_OK;
+}
+
+// After an optimizer step: every compute copy of a trainable (fp32 or bf16)
+// model rebuilt from the master parameters in one launch. Jobs are the
+// forward packing of each hidden layer, the transposed packing of layers
+// 1 .. L-1 and the biases (the same element mappings as pack_layer_kernel,
+// pack_transposed_kernel and pack_bias_kernel); the flat index picks the job.
+constexpr int PJ_MAX = 2 * ADVISOR_MAX_LAYERS;
+struct PackJobs {
+    const float *src[PJ_MAX];
+    void *dst[PJ_MAX];
+    int out[PJ_MAX], in[PJ_MAX], kp[PJ_MAX], transposed[PJ_MAX];
+    int64_t start[PJ_MAX + 1];
+    int n_jobs;
+    int tile_w;
+    // biases: hidden layers then the head weights and bias
+    const float *master;
+    int64_t layer_off[ADVISOR_MAX_LAYERS + 1];
+    int widths[ADVISOR_MAX_LAYERS + 1];
+    int n_hidden;
+    float *bias;
+    float *head;
+    int64_t total;
+};
+
+template <int P>
+__global__ void pack_train_kernel(PackJobs a)
+{
+    using T = typename CT<P>::T;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.total) return;
+    if (idx < a.start[a.n_jobs]) {
+        int j = 0;
+        while (j + 1 < a.n_jobs && idx >= a.start[j + 1]) ++j;
+        const int64_t local = idx - a.start[j];
+        const int kp = a.kp[j];
+        const int r = (int)(local / kp), c = (int)(local % kp);
+        // forward: row r = output n, column c = input k; transposed: r = k, c = n
+        const int n = a.transposed[j] ? c : r, k = a.transposed[j] ? r : c;
+        const float v = (n < a.out[j] && k < a.in[j]) ? a.src[j][(int64_t)n * a.in[j] + k] : 0.0f;
+        reinterpret_cast<T *>(a.dst[j])[pack_index<P>(r, c, kp)] = (T)v;
+        return;
+    }
+    const int i = (int)(idx - a.start[a.n_jobs]);
+    const int tw = a.tile_w;
+    if (i < a.n_hidden * tw) {
+        const int l = i / tw, n = i % tw;
+        const int in = a.widths[l], out = a.widths[l + 1];
+        a.bias[i] = n < out ? a.master[a.layer_off[l] + (int64_t)out * in + n] : 0.0f;
+    } else {
+        const int j = i - a.n_hidden * tw;
+        const int in = a.widths[a.n_hidden];
+        const float *hw = a.master + a.layer_off[a.n_hidden];
+        a.head[j] = j < tw ? (j < in ? hw[j] : 0.0f) : hw[in];
+    }
+}
+
+static int repack_train(advisor_model *m, hipStream_t s)
+{
+    TrainWs *w = train_ws(m);
+    PackJobs a{};
+    const int tw = m->tile_w;
+    int64_t at = 0;
+    for (int l = 0; l < m->n_hidden; ++l) {  // forward copies
+        const int j = a.n_jobs++;
+        a.src[j] = m->master + m->layer_off[l];
+        a.dst[j] = m->wpack[l];
+        a.out[j] = m->widths[l + 1];
+        a.in[j] = m->widths[l];
+        a.kp[j] = l == 0 ? NFEAT : tw;
+        a.transposed[j] = 0;
+        a.start[j] = at;
+        at += (int64_t)tw * a.kp[j];
+    }
+    for (int l = 1; l < m->n_hidden; ++l) {  // transposed copies for the backward chain
+        const int j = a.n_jobs++;
+        a.src[j] = m->master + m->layer_off[l];
+        a.dst[j] = w->wt[l];
+        a.out[j] = m->widths[l + 1];
+        a.in[j] = m->widths[l];
+        a.kp[j] = tw;
+        a.transposed[j] = 1;
+        a.start[j] = at;
+        at += (int64_t)tw * tw;
+    }
+    a.start[a.n_jobs] = at;
+    a.tile_w = tw;
+    a.master = m->master;
+    for (int l = 0; l <= m->n_hidden; ++l) {
+        a.layer_off[l] = m->layer_off[l];
+        a.widths[l] = m->widths[l];
+    }
+    a.widths[m->n_hidden + 1] = m->widths[m->n_hidden + 1];
+    a.n_hidden = m->n_hidden;
+    a.bias = m->bias;
+    a.head = m->head;
+    a.total = at + (int64_t)(m->n_hidden + 1) * tw + 1;
+    const unsigned blocks = (unsigned)((a.total + 255) / 256);
+    if (m->precision == PREC_FP32)
+        hipLaunchKernelGGL(pack_train_kernel<PREC_FP32>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(pack_train_kernel<PREC_BF16>, dim3(blocks), dim3(256), 0, s, a);
+    ADV_LAUNCHED("pack_train_kernel");
     m->wt_valid = true;
     return ADVISOR_OK;
 }
@@ -1018,14 +1130,13 @@ extern "C" int advisor_train_step(advisor_model *m, const int64_t *feat, const d
         ADV_LAUNCHED("gradient norm kernels");
     }
     // Adam on the fp32 master weights, then new compute copies
-    hipLaunchKernelGGL(step_inc_kernel, dim3(1), dim3(64), 0, s, m->d_step);
+    double *corr = w->red + 2 * RB + 2;  // workspace scalars: the bias corrections
+    hipLaunchKernelGGL(step_inc_kernel, dim3(1), dim3(64), 0, s, m->d_step, beta1, beta2, corr);
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((m->n_params + 255) / 256)), dim3(256), 0, s,
                        m->master, m->adam_m, m->adam_v, w->grads, m->n_params, lr, beta1, beta2, eps,
-                       (const int64_t *)m->d_step);
+                       (const double *)corr);
     ADV_LAUNCHED("adam_kernel");
-    rc = repack(m, s);
-    if (rc) return rc;
-    return repack_transposed(m, s);
+    return repack_train(m, s);
 }
 
 extern "C" int advisor_train_step_rmsprop(advisor_model *m, const int64_t *feat, const double *y,
@@ -1077,9 +1188,7 @@ extern "C" int advisor_train_step_rmsprop(advisor_model *m, const int64_t *feat,
                        m->master, m->adam_v, w->grads, m->n_params, lr, alpha, eps, weight_decay,
                        (const double *)scale);
     ADV_LAUNCHED("rmsprop_kernel");
-    rc = repack(m, s);
-    if (rc) return rc;
-    return repack_transposed(m, s);
+    return repack_train(m, s);
 }
 
 // Replace the fp32 master parameters from a device buffer (for optimizers
