@@ -518,6 +518,21 @@ def main():
             results[p]["with_transfers"] = time_with_transfers(
                 adv, torch, m, kd, vd, off, kdd, vdd, offd, best, max(5, args.steps // 2),
                 args.warmup)
+        # the prediction flow's top-10 list per kernel (fused pass + top-N), eager calls
+        tidx = torch.empty((nk, 10), dtype=torch.int64, device=d)
+        tval = torch.empty((nk, 10), dtype=torch.float32, device=d)
+        nsteps = args.steps if p == prec else max(5, args.steps // 2)
+        for _ in range(args.warmup):
+            m.rank_topn(kdd, vdd, offd, 10, idx_out=tidx, val_out=tval)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            m.rank_topn(kdd, vdd, offd, 10, idx_out=tidx, val_out=tval)
+        torch.cuda.synchronize()
+        tms = (time.perf_counter() - t0) * 1e3 / nsteps
+        results[p]["top10"] = dict(ms_per_step=tms, value=nv / (tms / 1e3),
+                                   head_equals_argmin=bool(torch.equal(tidx[:, 0], best)))
+        del tidx, tval
         rk = refine_k_for(p, args.refine_k)
         if p != "fp32" and rk > 0:
             # the same ranking with each kernel's top-k re-ranked in fp32 (eager calls)
@@ -602,6 +617,7 @@ def main():
             "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
             "tile_shape": r["tile_shape"], "autotune_ms": r["tune_ms"],
             "replay_ms": r["replay_ms"], "mfma_peak_measured": r["mfma_peak_measured"],
+            "top10": r.get("top10"),
             "argmin_agreement_vs_oracle_sample": agree.get(p),
             "argmin_agreement_trained_network": agree_t.get(p),
             "refined_by_fp32": None if "refined" not in r else dict(
