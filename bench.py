@@ -417,9 +417,11 @@ def train_bytes_per_step(widths, batch, m_params):
                + L * W * eb                  # g_l^T out
                + (L - 1) * (W // 32) * 4     # masks in
                + L * W * eb + nf * eb + (L - 1) * W * eb)  # weight gradients: g^T, x^T, h^T in
+    ld = -(-batch // 256) * 256
+
     def splits(na, nb, cus=256):  # the library's split rule on a 256-CU device
         tiles, s = -(-na // 128) * -(-nb // 128), 1
-        while tiles * s < 2 * cus and s < 64:
+        while tiles * s < 2 * cus and s < 64 and 2 * s * 512 <= ld:
             s *= 2
         return s
     partials = 2 * 4 * (splits(W, nf) * W * nf + (L - 1) * splits(W, W) * W * W)  # written, read back

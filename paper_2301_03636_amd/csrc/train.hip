@@ -218,7 +218,9 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
                                                     int64_t ld, int64_t kchunk, int tiles_n,
                                                     int tiles_k, int splits,
                                                     float *__restrict__ partial,
-                                                    float *__restrict__ partial_b)
+                                                    float *__restrict__ partial_b,
+                                                    float *__restrict__ direct, int dout, int din,
+                                                    int64_t n_rows)
 {
     using G = Geo<P>;
     using V = typename G::Vec;
@@ -342,7 +344,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
     // last load the last chunk again, so every step issues the same loads
     // unconditionally and the compiler's wait before each copy leaves the
     // two younger chunks in flight.
-    const int64_t chunks = kchunk / CH;
+    // chunks of this split's batch range that hold rows (at least one; the
+    // rows past n_rows are zero in g^T and add nothing)
+    int64_t chunks = kchunk / CH;
+    {
+        const int64_t live = n_rows - b0;
+        if (live < kchunk) chunks = live <= 0 ? 1 : min(chunks, (live + CH - 1) / CH);
+    }
     auto clampc = [&](int64_t c) { return c < chunks ? c : chunks - 1; };
     v4i_ sa[3][4], sb[3][4];
     fetch(0, sa[0], sb[0]);
@@ -362,6 +370,9 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
         step(c + 1, sa[2], sb[2]);
         step(c + 2, sa[0], sb[0]);
     }
+    // One split (direct != null): the layer's gradient goes straight to its
+    // place in the gradient vector, W [dout, din] then the bias, and no
+    // reduction follows; otherwise this split's partial tile.
     float *out = partial + (int64_t)split * na * nb;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -372,15 +383,25 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
             for (int r = 0; r < 16; ++r) {
                 const int nn = n0 + wn * 64 + 32 * i + 8 * (r / 4) + 4 * half + (r % 4);
                 const int kk = k0 + wk * 64 + 32 * j + col;
-                out[(int64_t)nn * nb + kk] = acc[i][j][r];
+                if (direct) {
+                    if (nn < dout && kk < din) direct[(int64_t)nn * din + kk] = acc[i][j][r];
+                } else {
+                    out[(int64_t)nn * nb + kk] = acc[i][j][r];
+                }
             }
         }
     if (bias_sums) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const float t = rsum[i] + __shfl_xor(rsum[i], 32, 64);
-            if (half == 0 && va[i])
-                partial_b[(int64_t)split * na + n0 + wn * 64 + 32 * i + col] = t;
+            const int nn = n0 + wn * 64 + 32 * i + col;
+            if (half == 0 && va[i]) {
+                if (direct) {
+                    if (nn < dout) direct[(int64_t)dout * din + nn] = t;
+                } else {
+                    partial_b[(int64_t)split * na + nn] = t;
+                }
+            }
         }
     }
 }
@@ -655,7 +676,9 @@ static int splits_for(int na, int nb, int64_t ld)
 {
     const int tiles = ((na + 127) / 128) * ((nb + 127) / 128);
     int s = 1;
-    while (tiles * s < 2 * device_cus() && s < 64) s *= 2;
+    // enough workgroups to fill the device, but at least 512 batch rows per
+    // split (a small batch is one split, written without a reduction)
+    while (tiles * s < 2 * device_cus() && s < 64 && (int64_t)(2 * s) * 512 <= ld) s *= 2;
     while (s > 1 && (ld / 64) % s != 0) s /= 2;
     return s;
 }
@@ -983,20 +1006,22 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         const int tn = (na + 127) / 128, tk = (nb + 127) / 128;
         const dim3 grid((unsigned)(tn * tk * splits));
         float *partial_b = w->partial + w->partial_floats;
+        // weights then biases of the layer (the bias gradient is the sum of
+        // g^T's rows over the batch; rows past n are zero)
+        float *gw = grads + m->layer_off[l];
+        float *direct = splits == 1 ? gw : nullptr;
         if (m->precision == PREC_FP32)
             hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, grid, dim3(256), WGRAD_LDS_BYTES, s,
                                reinterpret_cast<const float *>(Ab), na,
                                reinterpret_cast<const float *>(Bb), nb, ld, kchunk, tn, tk, splits,
-                               w->partial, partial_b);
+                               w->partial, partial_b, direct, out, in, n);
         else
             hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, grid, dim3(256), WGRAD_LDS_BYTES, s,
                                reinterpret_cast<const __bf16 *>(Ab), na,
                                reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, tn, tk, splits,
-                               w->partial, partial_b);
+                               w->partial, partial_b, direct, out, in, n);
         ADV_LAUNCHED("wgrad_kernel");
-        // weights then biases of the layer (the bias gradient is the sum of
-        // g^T's rows over the batch; rows past n are zero)
-        float *gw = grads + m->layer_off[l];
+        if (direct) continue;
         const int64_t ne = (int64_t)out * in + out;
         if (in % 4 == 0 && nb % 4 == 0 && ((uintptr_t)gw & 15) == 0) {
             const int64_t ne4 = (int64_t)out * in / 4 + out;
