@@ -15,6 +15,7 @@ from ._lib import (AdvisorError, PRECISIONS, advisor_featurize, advisor_model_cr
                    advisor_model_get_tile_variant, advisor_validate_offsets, advisor_topn_preds,
                    advisor_rank_topn, advisor_train_step_rmsprop,
                    advisor_count_variants, advisor_enumerate_variants, advisor_classify_maps,
-                   advisor_rank_multi, advisor_train_plan_create_rmsprop)
+                   advisor_rank_multi, advisor_train_plan_create_rmsprop,
+                   advisor_train_plan_create_rmsprop_multi)
 from .model import Model, Plan  # noqa: F401
 from .train import MLPFunction, RMSpropTrainer, Trainer, mlp, step_lr  # noqa: F401

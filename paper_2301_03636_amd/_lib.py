@@ -82,6 +82,9 @@ def lib():
             "advisor_train_plan_create_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
                                                    C.c_float, i32, P, P, C.POINTER(C.c_void_p)],
                                                   i32),
+            "advisor_train_plan_create_rmsprop_multi": ([P, P, P, P, i32, C.c_float, C.c_float,
+                                                         C.c_float, C.c_float, i32, P, P,
+                                                         C.POINTER(C.c_void_p)], i32),
             "advisor_rank_multi": ([P, i32, P, P, P, i64, i64, P, P, P], i32),
             "advisor_classify_maps": ([P, P, P, i64, i64, P, P, P, P, P], i32),
             "advisor_count_variants": ([P, i64, i32, P, P], i32),
@@ -565,6 +568,36 @@ def advisor_train_plan_create_rmsprop(h, feat, y, loss_out, gnorm_out, lr=1e-2, 
                                                    eps, weight_decay, LOSSES[loss], _ptr(loss_out),
                                                    _ptr(gnorm_out), C.byref(p)),
            "advisor_train_plan_create_rmsprop")
+    return p
+
+
+def advisor_train_plan_create_rmsprop_multi(handles, feats, ys, loss_out=None, gnorm_out=None,
+                                            lr=1e-2, alpha=0.99, eps=1e-8, weight_decay=1e-4,
+                                            loss="rmse"):
+    n = len(handles)
+    if not (len(feats) == len(ys) == n):
+        raise ValueError("one batch per model")
+    for f, y in zip(feats, ys):
+        _dev(f, torch.int64, "feat")
+        _dev(y, torch.float64, "y")
+        if y.shape[0] != f.shape[0]:
+            raise ValueError("feat and y differ in rows")
+    for t, nm in ((loss_out, "loss_out"), (gnorm_out, "gnorm_out")):
+        _dev(t, torch.float64, nm)
+        if t is not None and t.numel() < n:
+            raise ValueError("%s needs one entry per model" % nm)
+    if loss not in LOSSES:
+        raise ValueError("loss must be one of %s" % sorted(LOSSES))
+    hs = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    fp = (C.c_void_p * n)(*[f.data_ptr() for f in feats])
+    yp = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
+    ns = (C.c_int64 * n)(*[f.shape[0] for f in feats])
+    p = C.c_void_p()
+    _check(lib().advisor_train_plan_create_rmsprop_multi(hs, fp, yp, ns, n, lr, alpha, eps,
+                                                         weight_decay, LOSSES[loss],
+                                                         _ptr(loss_out), _ptr(gnorm_out),
+                                                         C.byref(p)),
+           "advisor_train_plan_create_rmsprop_multi")
     return p
 
 

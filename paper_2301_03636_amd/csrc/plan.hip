@@ -1,6 +1,8 @@
 // Captured launch plans: one advisor_rank or advisor_train_step call with
 // fixed buffers recorded into a HIP graph and replayed with one launch. The
 // kernels are the same as the direct calls; replays give the same bits.
+#include <vector>
+
 #include "internal.h"
 
 struct advisor_plan {
@@ -129,6 +131,75 @@ extern "C" int advisor_train_plan_create_rmsprop(advisor_model *model, const int
                                               loss_out, gnorm_out, cs);
         },
         out);
+}
+
+extern "C" int advisor_train_plan_create_rmsprop_multi(
+    advisor_model *const *models, const int64_t *const *feats, const double *const *ys,
+    const int64_t *ns, int n_models, float lr, float alpha, float eps, float weight_decay, int loss,
+    double *loss_out, double *gnorm_out, advisor_plan **out)
+{
+    clear_error();
+    if (!out) return fail(ADVISOR_EINVAL, "advisor_train_plan_create_rmsprop_multi: out is null");
+    *out = nullptr;
+    if (n_models < 1 || n_models > 64 || !models || !feats || !ys || !ns)
+        return fail(ADVISOR_EINVAL, "need 1 to 64 models with their batches");
+    for (int t = 0; t < n_models; ++t) {
+        if (!models[t]) return fail(ADVISOR_EINVAL, "null model");
+        for (int u = 0; u < t; ++u)
+            if (models[u] == models[t]) return fail(ADVISOR_EINVAL, "a model appears twice");
+        if (ns[t] < 1 || ns[t] >= ((int64_t)1 << 32))
+            return fail(ADVISOR_ESHAPE, "row count must be in [1, 2^32)");
+        int rc = reserve_train_ws(models[t], ns[t]);
+        if (rc) return rc;
+        rc = repack_transposed_now(models[t], nullptr);
+        if (rc) return rc;
+    }
+    ADV_HIP(hipDeviceSynchronize());
+    // one branch per model: fork from the capture stream through an event,
+    // each model's step on a stream of its own, joined back before the end
+    std::vector<hipStream_t> st(n_models, nullptr);
+    std::vector<hipEvent_t> done(n_models, nullptr);
+    hipEvent_t fork = nullptr;
+    int rc = ADVISOR_OK;
+    auto check = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == ADVISOR_OK) rc = hip_fail(e, what);
+        return rc == ADVISOR_OK;
+    };
+    check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate");
+    for (int t = 0; t < n_models && rc == ADVISOR_OK; ++t) {
+        check(hipStreamCreateWithFlags(&st[t], hipStreamNonBlocking), "hipStreamCreate");
+        check(hipEventCreateWithFlags(&done[t], hipEventDisableTiming), "hipEventCreate");
+    }
+    if (rc == ADVISOR_OK) {
+        rc = capture(
+            [&](hipStream_t cs) {
+                int r = ADVISOR_OK;
+                auto ok = [&](hipError_t e, const char *what) {
+                    if (e != hipSuccess && r == ADVISOR_OK) r = hip_fail(e, what);
+                    return r == ADVISOR_OK;
+                };
+                ok(hipEventRecord(fork, cs), "hipEventRecord");
+                for (int t = 0; t < n_models && r == ADVISOR_OK; ++t) {
+                    if (!ok(hipStreamWaitEvent(st[t], fork, 0), "hipStreamWaitEvent")) break;
+                    r = advisor_train_step_rmsprop(models[t], feats[t], ys[t], ns[t], lr, alpha,
+                                                   eps, weight_decay, loss,
+                                                   loss_out ? loss_out + t : nullptr,
+                                                   gnorm_out ? gnorm_out + t : nullptr, st[t]);
+                    if (r == ADVISOR_OK) ok(hipEventRecord(done[t], st[t]), "hipEventRecord");
+                }
+                // join every forked branch, also after an error, so the capture can end
+                for (int t = 0; t < n_models; ++t)
+                    (void)hipStreamWaitEvent(cs, done[t], 0);
+                return r;
+            },
+            out);
+    }
+    for (int t = 0; t < n_models; ++t) {
+        if (done[t]) (void)hipEventDestroy(done[t]);
+        if (st[t]) (void)hipStreamDestroy(st[t]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    return rc;
 }
 
 extern "C" int advisor_plan_launch(advisor_plan *p, void *stream)

@@ -96,6 +96,15 @@ class Plan:
                                                    alpha, eps, weight_decay, loss)
         return cls(h, (model, feat, y, loss_out, gnorm_out))
 
+    @classmethod
+    def train_rmsprop_multi(cls, models, feats, ys, loss_out=None, gnorm_out=None, lr=1e-2,
+                            alpha=0.99, eps=1e-8, weight_decay=1e-4, loss="rmse"):
+        """One RMSprop step of every model on its own batch, as one plan."""
+        h = _lib.advisor_train_plan_create_rmsprop_multi([m.handle for m in models], feats, ys,
+                                                         loss_out, gnorm_out, lr, alpha, eps,
+                                                         weight_decay, loss)
+        return cls(h, (list(models), list(feats), list(ys), loss_out, gnorm_out))
+
     def launch(self):
         _lib.advisor_plan_launch(self.handle)
 

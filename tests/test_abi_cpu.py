@@ -166,3 +166,12 @@ def test_rank_multi_argument_checks():
     assert L.advisor_rank_multi(None, 0, None, None, None, 1, 1, None, None, None) == EINVAL
     arr = (C.c_void_p * 1)(None)
     assert L.advisor_rank_multi(arr, 1, None, None, None, 1, 1, None, None, None) == EINVAL
+
+
+def test_multi_train_plan_argument_checks():
+    L = _lib.lib()
+    out = C.c_void_p()
+    assert L.advisor_train_plan_create_rmsprop_multi(None, None, None, None, 0, C.c_float(1e-2),
+                                                     C.c_float(0.99), C.c_float(1e-8),
+                                                     C.c_float(1e-4), 1, None, None,
+                                                     C.byref(out)) == EINVAL

@@ -198,3 +198,60 @@ def test_rmsprop_plan_replays_match_eager_steps(precision, n):
             torch.cuda.synchronize()
             say("batch-16 RMSprop step, %s: %.1f us" % (name, (time.perf_counter() - t0) / reps * 1e6))
     plan.close()
+
+
+def test_multi_model_plan_matches_separate_steps():
+    """Seven models of the paper's shape (one per cluster of its experiments),
+    each with its own 16-row batch, stepped together by one plan with a branch
+    per model: every replay leaves each model exactly as its own eager step
+    does. The replay time is printed beside seven single-model plans."""
+    import time
+    widths = (32, 64, 128, 64, 32, 1)
+    T = 7
+    eager, planned, feats, ys = [], [], [], []
+    for t in range(T):
+        f, y, mu, sd = _batch(600, 460 + t)
+        f, y = f[:16], y[:16]
+        p0 = workload.he_init(widths, 470 + t)
+        a = adv.Model(widths, "fp32")
+        a.set_params(p0, mu, sd)
+        b = adv.Model(widths, "fp32")
+        b.set_params(p0, mu, sd)
+        eager.append(a)
+        planned.append(b)
+        feats.append(to_dev(f))
+        ys.append(to_dev(y))
+    loss = torch.zeros(T, dtype=torch.float64, device="cuda")
+    gn = torch.zeros(T, dtype=torch.float64, device="cuda")
+    plan = adv.Plan.train_rmsprop_multi(planned, feats, ys, loss, gn)
+    for step in range(3):
+        ref = []
+        for t in range(T):
+            la, ga = adv.advisor_train_step_rmsprop(eager[t].handle, feats[t], ys[t])
+            ref.append((host(la)[0], host(ga)[0]))
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        lo, gg = host(loss), host(gn)
+        for t in range(T):
+            wa, _, _ = eager[t].get_params()
+            wb, _, _ = planned[t].get_params()
+            assert np.array_equal(wa.view(np.int32), wb.view(np.int32)), (step, t)
+            assert lo[t] == ref[t][0] and gg[t] == ref[t][1], (step, t)
+        assert np.isfinite(host(planned[0].predict(feats[0]))).all()
+    singles = [adv.Plan.train_rmsprop(eager[t], feats[t], ys[t], loss[t:t + 1], gn[t:t + 1])
+               for t in range(T)]
+    reps = 50
+    for name, fn in (("one plan, 7 branches", plan.launch),
+                     ("7 single-model plans", lambda: [s.launch() for s in singles])):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        say("7 models x 16 rows, %s: %.1f us per step of all" %
+            (name, (time.perf_counter() - t0) / reps * 1e6))
+    for s in singles:
+        s.close()
+    plan.close()
