@@ -814,11 +814,13 @@ __global__ void pack_train_kernel(PackJobs a)
         while (j + 1 < a.n_jobs && idx >= a.start[j + 1]) ++j;
         const int64_t local = idx - a.start[j];
         const int kp = a.kp[j];
-        const int r = (int)(local / kp), c = (int)(local % kp);
-        // forward: row r = output n, column c = input k; transposed: r = k, c = n
-        const int n = a.transposed[j] ? c : r, k = a.transposed[j] ? r : c;
+        // consecutive threads take consecutive inputs k of one output n, so
+        // the master weights are read contiguously; the forward copy puts n
+        // in the fragment's rows, the transposed copy puts k there
+        const int n = (int)(local / kp), k = (int)(local % kp);
         const float v = (n < a.out[j] && k < a.in[j]) ? a.src[j][(int64_t)n * a.in[j] + k] : 0.0f;
-        reinterpret_cast<T *>(a.dst[j])[pack_index<P>(r, c, kp)] = (T)v;
+        const int64_t at = a.transposed[j] ? pack_index<P>(k, n, kp) : pack_index<P>(n, k, kp);
+        reinterpret_cast<T *>(a.dst[j])[at] = (T)v;
         return;
     }
     const int i = (int)(idx - a.start[a.n_jobs]);
