@@ -175,3 +175,13 @@ def test_multi_train_plan_argument_checks():
                                                      C.c_float(0.99), C.c_float(1e-8),
                                                      C.c_float(1e-4), 1, None, None,
                                                      C.byref(out)) == EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built library every entry point raises."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libadvisor.so")
+    with pytest.raises(ImportError):
+        _lib.lib()
+    with pytest.raises(ImportError):
+        adv.Model((32, 8, 1), "fp32")
