@@ -479,6 +479,8 @@ int advisor_train_plan_create_rmsprop_multi(advisor_model *const *models,
                                             double *loss_out, double *gnorm_out,
                                             advisor_plan **out);
 int advisor_plan_launch(advisor_plan *plan, void *stream);
+/* Waits for the plan's device to finish all queued work (so no launch of the
+ * plan is still pending), then frees the plan. */
 void advisor_plan_destroy(advisor_plan *plan);
 
 /*

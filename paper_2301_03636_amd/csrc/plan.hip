@@ -64,6 +64,15 @@ using namespace adv;
 extern "C" void advisor_plan_destroy(advisor_plan *p)
 {
     if (!p) return;
+    // the runtime does not defer freeing an executable graph whose launches
+    // are still queued or running: wait for the plan's device to go idle first
+    if (p->exec) {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        if (prev != p->device) (void)hipSetDevice(p->device);
+        (void)hipDeviceSynchronize();
+        if (prev >= 0 && prev != p->device) (void)hipSetDevice(prev);
+    }
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     delete p;

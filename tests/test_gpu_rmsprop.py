@@ -255,3 +255,65 @@ def test_multi_model_plan_matches_separate_steps():
     for s in singles:
         s.close()
     plan.close()
+
+
+def test_paper_recipe_seven_models_batch16():
+    """Section 5.3's recipe as written, for seven models at once (one per
+    cluster of the paper's experiments, each on 2000 synthetic runtimes of
+    200 kernels):
+    32-64-128-64-32-1 (the paper's multiples of the input count), Glorot
+    weights and zero biases, batches of 16, 150 epochs of RMSprop with lr
+    0.01 divided by 10 every 30 epochs and weight decay 1e-4, the RMSE loss,
+    an 80/20 split and Z-score inputs. Each epoch's minibatches are gathered
+    into the plan's fixed buffers and the plan (one graph branch per model)
+    is rebuilt when the learning rate steps. Every model's validation NRMSE
+    ends below the paper's 0.1 bar."""
+    widths = (32, 64, 128, 64, 32, 1)
+    T, N, bs, epochs = 7, 2000, 16, 150
+    n_train = int(0.8 * N)
+    models, data = [], []
+    for t in range(T):
+        # 2000 variants of 200 kernels, shuffled before the 80/20 split
+        kd, vd, off = workload.make_descriptors(200, 8, 40, 480 + 10 * t)
+        f, inv = oracle.featurize(kd, vd)
+        f = f[inv == 0]
+        f = f[np.random.default_rng(482 + 10 * t).permutation(f.shape[0])[:N]]
+        y = cost.target(f, workload.noise(f.shape[0], 483 + 10 * t))
+        mu, sd = oracle.zscore_fit(f[:n_train])
+        m = adv.Model(widths, "fp32")
+        m.set_params(workload.glorot_init(widths, 481 + 10 * t), mu, sd)
+        models.append(m)
+        data.append((to_dev(f[:n_train]), to_dev(y[:n_train]), f[n_train:], y[n_train:]))
+    fb = [torch.empty((bs, 32), dtype=torch.int64, device="cuda") for _ in range(T)]
+    yb = [torch.empty(bs, dtype=torch.float64, device="cuda") for _ in range(T)]
+    loss = torch.zeros(T, dtype=torch.float64, device="cuda")
+    gn = torch.zeros(T, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(489)
+    plan, plan_lr = None, None
+    first = None
+    for epoch in range(epochs):
+        lr = adv.step_lr(epoch)
+        assert lr == oracle.step_lr(epoch)
+        if lr != plan_lr:
+            if plan is not None:
+                torch.cuda.synchronize()
+                plan.close()
+            plan = adv.Plan.train_rmsprop_multi(models, fb, yb, loss, gn, lr=lr)
+            plan_lr = lr
+        perms = [to_dev(rng.permutation(n_train)) for _ in range(T)]
+        for s in range(0, n_train - bs + 1, bs):
+            for t in range(T):
+                idx = perms[t][s:s + bs]
+                torch.index_select(data[t][0], 0, idx, out=fb[t])
+                torch.index_select(data[t][1], 0, idx, out=yb[t])
+            plan.launch()
+        if first is None:
+            first = host(loss).copy()
+    torch.cuda.synchronize()
+    plan.close()
+    last = host(loss)
+    for t in range(T):
+        pred = host(models[t].predict(to_dev(data[t][2]))).astype(np.float64)
+        nr = oracle.nrmse(pred, data[t][3])
+        say("model %d: batch RMSE %.3f -> %.3f, validation NRMSE %.4f" % (t, first[t], last[t], nr))
+        assert nr < 0.1

@@ -445,3 +445,21 @@ def test_permutation_invariance():
     assert np.array_equal(pred3, pred[rows])
     for j, k in enumerate(kp):
         assert best3[j] - off3[j] == best[k] - off[k]
+
+
+def test_glorot_init_statistics():
+    """Section 5.3's Glorot initialization: weights within +-sqrt(6/(in+out))
+    with variance 2/(in+out), biases zero, the [out, in] then bias layout."""
+    widths = (32, 64, 128, 64, 32, 1)
+    p = workload.glorot_init(widths, 5).astype(np.float64)
+    assert p.size == workload.param_count(widths)
+    off = 0
+    for i in range(len(widths) - 1):
+        fi, fo = widths[i], widths[i + 1]
+        w = p[off:off + fi * fo]
+        b = p[off + fi * fo:off + fi * fo + fo]
+        a = np.sqrt(6.0 / (fi + fo))
+        assert np.all(np.abs(w) <= a) and np.all(b == 0.0)
+        if w.size >= 2048:
+            assert abs(w.var() / (2.0 / (fi + fo)) - 1.0) < 0.1
+        off += fi * fo + fo

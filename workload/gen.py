@@ -167,6 +167,21 @@ def he_init(widths, seed: int, bias_scale: float = 0.0) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def glorot_init(widths, seed: int) -> np.ndarray:
+    """Glorot (Xavier) uniform weights U(-a, a), a = sqrt(6 / (fan_in +
+    fan_out)), drawn in float64 and rounded to the float32 master copy, and
+    zero biases: the initialization section 5.3 names. Same layout as
+    he_init."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(widths) - 1):
+        fan_in, fan_out = widths[i], widths[i + 1]
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-a, a, (fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def sample_rows(n_rows: int, n_sample: int, seed: int) -> np.ndarray:
     """Sorted seeded sample of row indices without replacement."""
     rng = np.random.default_rng(seed)
