@@ -200,6 +200,42 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
         out[name] = {"ms": ms, "bytes": nbytes, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
                      "frac": gbs / PEAK_HBM_GBS}
     del feat, inv, pred, best, tidx, tval
+    # the method's integer steps on synthetic inputs of their own: variant
+    # generation for 262,144 kernels of 1-4 loops (8 B of loop count read per
+    # kernel, 8 B of offsets and 48 B per variant row written), and the data
+    # analysis of 4 variables per kernel for 1,048,576 kernels (1 B of access
+    # bits and 8 B of size read and 1 B of class written per variable, 8 B of
+    # offsets read and 24 B of byte totals written per kernel)
+    g = torch.Generator(device="cpu").manual_seed(77)
+    nk_v = 1 << 18
+    nl = torch.randint(1, 5, (nk_v,), generator=g, dtype=torch.int64).to(vdd.device)
+    offv = adv.advisor_count_variants(nl)
+    nv_v = int(offv[-1].item())
+    rows = torch.empty((nv_v, 6), dtype=torch.int64, device=vdd.device)
+    nk_d = 1 << 20
+    acc = torch.randint(0, 32, (4 * nk_d,), generator=g, dtype=torch.uint8).to(vdd.device)
+    nbytes = torch.randint(0, 1 << 30, (4 * nk_d,), generator=g, dtype=torch.int64).to(vdd.device)
+    offd_d = torch.arange(0, 4 * nk_d + 1, 4, dtype=torch.int64, device=vdd.device)
+    for name, fn, nbytes_alg in (
+            ("variant_generation", lambda: adv.advisor_enumerate_variants(
+                nl, 7, offsets=adv.advisor_count_variants(nl, 7, offsets_out=offv),
+                variants_out=rows), nk_v * 16 + nv_v * 48 + 8),
+            ("data_analysis", lambda: adv.advisor_classify_maps(acc, nbytes, offd_d),
+             4 * nk_d * 10 + nk_d * 32 + 8)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        gbs = nbytes_alg / (ms / 1e3) / 1e9
+        out[name] = {"ms": ms, "bytes": nbytes_alg, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
+                     "frac": gbs / PEAK_HBM_GBS,
+                     "units": {"variant_generation": "%d kernels, %d variants" % (nk_v, nv_v),
+                               "data_analysis": "%d kernels x 4 variables" % nk_d}[name]}
+    del nl, offv, rows, acc, nbytes, offd_d
     return out
 
 

@@ -2,8 +2,7 @@
 // class from what happens to it before, during and after the kernel, and each
 // kernel gets the bytes its enter-data and exit-data directives move, beside
 // the bytes of mapping every variable to and from the GPU. Integer work on a
-// few bytes per variable: one wave per kernel, lanes over its variables,
-// 64-bit sums reduced across the wave.
+// few bytes per variable, bound by memory: one thread per kernel.
 #include <algorithm>
 
 #include "internal.h"
@@ -12,7 +11,7 @@ namespace adv {
 
 namespace {
 
-constexpr int DF_WAVES = 4;
+constexpr int DF_THREADS = 256;
 
 // class of one variable from its access bits (the codes of ADVISOR_MAP_*)
 __device__ __forceinline__ int map_class(unsigned bits)
@@ -26,25 +25,21 @@ __device__ __forceinline__ int map_class(unsigned bits)
     return (before && rd) ? ADVISOR_MAP_TO : ADVISOR_MAP_ALLOC;
 }
 
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__global__ __launch_bounds__(DF_WAVES * 64) void classify_kernel(
+// One thread per kernel: a kernel has a handful of variables (the paper's
+// kernels map a few arrays), so each thread walks its own segment; adjacent
+// threads walk adjacent segments, which keeps the loads of a wave within a
+// few cache lines.
+__global__ __launch_bounds__(DF_THREADS) void classify_kernel(
     const uint8_t *__restrict__ access, const int64_t *__restrict__ nbytes,
     const int64_t *__restrict__ var_off, int64_t n_k, int64_t n_vars, uint8_t *__restrict__ cls,
     int64_t *__restrict__ enter, int64_t *__restrict__ exit_, int64_t *__restrict__ naive)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * DF_WAVES;
-    for (int64_t k = (int64_t)blockIdx.x * DF_WAVES + (threadIdx.x >> 6); k < n_k; k += nwaves) {
+    const int64_t stride = (int64_t)gridDim.x * DF_THREADS;
+    for (int64_t k = (int64_t)blockIdx.x * DF_THREADS + threadIdx.x; k < n_k; k += stride) {
         const int64_t lo = max((int64_t)0, min(var_off[k], n_vars));
         const int64_t hi = max(lo, min(var_off[k + 1], n_vars));
         int64_t e = 0, x = 0, nv = 0;
-        for (int64_t i = lo + lane; i < hi; i += 64) {
+        for (int64_t i = lo; i < hi; ++i) {
             const int c = map_class(access[i]);
             if (cls) cls[i] = (uint8_t)c;
             const int64_t b = nbytes[i];
@@ -52,14 +47,9 @@ __global__ __launch_bounds__(DF_WAVES * 64) void classify_kernel(
             if (c == ADVISOR_MAP_FROM || c == ADVISOR_MAP_TOFROM) x += b;
             if (c <= ADVISOR_MAP_TOFROM) nv += 2 * b;
         }
-        e = wave_sum_i64(e);
-        x = wave_sum_i64(x);
-        nv = wave_sum_i64(nv);
-        if (lane == 0) {
-            if (enter) enter[k] = e;
-            if (exit_) exit_[k] = x;
-            if (naive) naive[k] = nv;
-        }
+        if (enter) enter[k] = e;
+        if (exit_) exit_[k] = x;
+        if (naive) naive[k] = nv;
     }
 }
 
@@ -81,8 +71,8 @@ extern "C" int advisor_classify_maps(const uint8_t *access, const int64_t *nbyte
     if (!var_offsets || (n_vars > 0 && (!access || !nbytes)))
         return fail(ADVISOR_EINVAL, "advisor_classify_maps: null pointer");
     hipStream_t s = as_stream(stream);
-    const int64_t blocks = std::min<int64_t>((n_kernels + DF_WAVES - 1) / DF_WAVES, 1 << 20);
-    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(DF_WAVES * 64), 0, s, access,
+    const int64_t blocks = std::min<int64_t>((n_kernels + DF_THREADS - 1) / DF_THREADS, 1 << 20);
+    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)blocks), dim3(DF_THREADS), 0, s, access,
                        nbytes, var_offsets, n_kernels, n_vars, class_out, enter_bytes, exit_bytes,
                        naive_bytes);
     ADV_LAUNCHED("classify_kernel");
