@@ -86,7 +86,7 @@ def stored_traffic(cfg, precision):
 
 
 def make_inputs(cfg, seed_desc=None):
-    c = workload.CONFIGS[cfg]
+    c = workload.WORKLOADS[cfg]
     s = workload.seeds(cfg)
     kd, vd, off = workload.make_descriptors(c["n_kernels"], c["count_lo"], c["count_hi"],
                                             s["desc"] if seed_desc is None else seed_desc)
@@ -391,7 +391,7 @@ def train_leg(adv, torch, d, steps, warmup):
     32-512x4-1, Adam lr 1e-3, float64 loss and gradient norm. The targets are
     seeded draws of the same scale as ln(runtime in us) (the timing does not
     depend on their values; the tests train on the synthetic runtime model)."""
-    c = workload.CONFIGS[4]
+    c = workload.WORKLOADS[4]
     s = workload.seeds(4)
     widths = tuple(c["widths"])
     B = c["batch"]

@@ -49,7 +49,7 @@ _ALLOWED = {
 }
 
 # The five workloads: (kernels, min variants, max variants, layer widths).
-CONFIGS = {
+WORKLOADS = {
     1: dict(n_kernels=1, count_lo=256, count_hi=256, widths=(32, 64, 64, 1)),
     2: dict(n_kernels=4096, count_lo=16, count_hi=1024, widths=(32, 256, 256, 256, 1)),
     3: dict(n_kernels=16384, count_lo=64, count_hi=1024, widths=(32, 512, 512, 512, 512, 1)),
@@ -209,7 +209,7 @@ def noise(n: int, seed: int) -> np.ndarray:
 
 def make_config(cfg: int, **overrides):
     """Descriptors and float32 master weights of one of the five workloads."""
-    c = dict(CONFIGS[cfg])
+    c = dict(WORKLOADS[cfg])
     c.update(overrides)
     s = seeds(cfg)
     kd, vd, off = make_descriptors(c["n_kernels"], c["count_lo"], c["count_hi"], s["desc"])
