@@ -130,31 +130,33 @@ __global__ __launch_bounds__(VG_THREADS) void vg_rows_kernel(
         for (int64_t w = lo * ADVISOR_VARIANT_COLS + lane; w < hi * ADVISOR_VARIANT_COLS; w += 64) {
             const int64_t row = w / ADVISOR_VARIANT_COLS;
             const int col = (int)(w - row * ADVISOR_VARIANT_COLS);
-            const int64_t r = row - seg0;
+            const int64_t r64 = row - seg0;
             int64_t val = -1;
-            if (r >= 0 && r < cnt) {
-                const int64_t data = r & 1;
-                const int64_t q = r >> 1;
-                const int si = (int)(q % n_sched);
-                int64_t p = q / n_sched;
+            if (r64 >= 0 && r64 < cnt) {
+                // a kernel has at most 84 rows and 1 <= n <= 4 here: 32-bit decode
+                const int r = (int)r64, nn = (int)n;
+                const int data = r & 1;
+                const int q = r >> 1;
+                const int si = q % n_sched;
+                int p = q / n_sched;
                 int sch = 0;
                 for (int b = 0, seen = 0; b < 3; ++b)
                     if ((sched_mask >> b) & 1) {
                         if (seen == si) sch = b;
                         ++seen;
                     }
-                int64_t x = 0, d = 0, c = 0;
-                if (p < n) {
+                int x = 0, d = 0, c = 0;
+                if (p < nn) {
                     c = p + 1;
                 } else {
-                    p -= n;
-                    for (x = 1; x < n; ++x) {
-                        const int64_t m = x * (n - x);
+                    p -= nn;
+                    for (x = 1; x < nn; ++x) {
+                        const int m = x * (nn - x);
                         if (p < m) break;
                         p -= m;
                     }
-                    d = p / (n - x) + 1;
-                    c = p % (n - x) + 1;
+                    d = p / (nn - x) + 1;
+                    c = p % (nn - x) + 1;
                 }
                 const int64_t vals[ADVISOR_VARIANT_COLS] = {k, x, d, c, sch, data};
                 val = vals[0];
