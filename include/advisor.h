@@ -65,9 +65,10 @@ enum advisor_precision {
 #define ADVISOR_VD_COLS 8
 #define ADVISOR_MAX_LAYERS 9   /* hidden layers + output layer */
 #define ADVISOR_MAX_WIDTH 1024
-#define ADVISOR_MAX_TOP_N 32
+#define ADVISOR_MAX_TOP_N 32     /* longest top-N list of advisor_topn_preds / advisor_rank_topn */
 #define ADVISOR_MAX_LOOPS 4      /* collapsible loops per kernel the variant generator handles */
-#define ADVISOR_VARIANT_COLS 6   /* columns of a generated variant row */   /* longest top-N list of advisor_topn_preds / advisor_rank_topn */
+#define ADVISOR_VARIANT_COLS 6   /* columns of a generated variant row */
+#define ADVISOR_MAX_STAGES 4     /* models of one advisor_rank_cascade call */
 
 typedef struct advisor_model advisor_model;  /* opaque; owned by the library */
 
@@ -233,6 +234,34 @@ int advisor_rank_multi(const advisor_model *const *models, int n_models, const i
 int advisor_rank_refined(advisor_model *model, const advisor_model *refine,
                          const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
                          int64_t n_kernels, int64_t n_variants, int top_k, int64_t *best_out,
+                         float *pred_out, void *stream);
+
+/*
+ * Multi-stage ranking (the prediction flow of section 3, N = 1, with the
+ * argmin decided by the most precise of several models of one network, for
+ * example fp8, then bf16, then fp32 copies of the same weights). models[0]
+ * ranks every variant as advisor_rank does; for s = 0 .. n_stages - 2, each
+ * kernel's keep[s] best candidates by models[s]'s predictions (lowest
+ * variant index first on ties; NaN and ineligible variants never enter)
+ * are ranked again by models[s + 1], which passes on its own keep[s + 1]
+ * best of them; best_out[k] receives the variant the last model predicts
+ * fastest among its candidates (lowest variant index on ties), or -1 if the
+ * kernel has no eligible variant. Whenever the last model's own argmin of a
+ * kernel survives every earlier cut, the result equals advisor_rank with
+ * the last model. 1 <= n_stages <= ADVISOR_MAX_STAGES; keep (host,
+ * int [n_stages - 1], may be NULL for one stage) values in {1, 2, 4, 8, 16,
+ * 32}, non-increasing; n_kernels * 32 < 2^31. Arguments as for
+ * advisor_rank; pred_out (may be NULL) receives models[0]'s predictions. All
+ * models must live on the current device. models[0] owns a workspace that
+ * grows on demand (synchronous allocation; at most 4 n_variants bytes for
+ * the first-stage predictions when pred_out is NULL, plus about
+ * 80 n_kernels * keep[s] bytes per cut); calls sharing models[0] must not
+ * overlap. advisor_rank_refined(model, refine, ..., top_k, ...) is this call
+ * with models {model, refine} and keep {top_k}.
+ */
+int advisor_rank_cascade(advisor_model *const *models, const int *keep, int n_stages,
+                         const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
+                         int64_t n_kernels, int64_t n_variants, int64_t *best_out,
                          float *pred_out, void *stream);
 
 /*

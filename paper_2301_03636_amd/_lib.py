@@ -56,6 +56,7 @@ def lib():
             "advisor_rank": ([P, P, P, P, i64, i64, P, P, P], i32),
             "advisor_rank_preds": ([P, P, i64, i64, P, P], i32),
             "advisor_rank_refined": ([P, P, P, P, P, i64, i64, i32, P, P, P], i32),
+            "advisor_rank_cascade": ([P, P, i32, P, P, P, i64, i64, P, P, P], i32),
             "advisor_mlp_saved_bytes": ([P, i64], i64),
             "advisor_mlp_forward": ([P, P, i64, P, P, P], i32),
             "advisor_mlp_backward": ([P, P, P, i64, P, P], i32),
@@ -301,6 +302,26 @@ def advisor_rank_refined(h, refine, kdesc, vdesc, offsets, top_k=8, best_out=Non
     _check(lib().advisor_rank_refined(h, refine, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
                                       int(top_k), _ptr(best_out), _ptr(pred_out), _stream()),
            "advisor_rank_refined")
+    return best_out
+
+
+def advisor_rank_cascade(handles, keep, kdesc, vdesc, offsets, best_out=None, pred_out=None):
+    """Multi-stage ranking: handles [n_stages] model handles (first the
+    fastest), keep [n_stages - 1] candidates per kernel handed on by each cut."""
+    for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
+        _dev(t, torch.int64, nm)
+    nk = offsets.shape[0] - 1
+    nv = vdesc.shape[0]
+    if best_out is None:
+        best_out = torch.empty(nk, dtype=torch.int64, device=vdesc.device)
+    _dev(best_out, torch.int64, "best_out")
+    _dev(pred_out, torch.float32, "pred_out")
+    ns = len(handles)
+    arr = (C.c_void_p * max(ns, 1))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    kp = (C.c_int * max(len(keep), 1))(*[int(k) for k in keep])
+    _check(lib().advisor_rank_cascade(arr, kp, ns, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk,
+                                      nv, _ptr(best_out), _ptr(pred_out), _stream()),
+           "advisor_rank_cascade")
     return best_out
 
 

@@ -58,6 +58,42 @@ bool debug_offsets(hipStream_t s);
 int launch_topn_preds(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v, int N,
                       int64_t *idx_out, float *val_out, hipStream_t s);
 
+// advisor_rank without clearing the error text; the opt-in offsets check
+// (which allocates) runs only when may_check_offsets is set (mlp.hip).
+int rank_core(const advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
+              const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int64_t *best_out,
+              float *pred_out, hipStream_t s, bool may_check_offsets);
+
+// Multi-stage ranking (refine.hip): argument checks, workspace layout and
+// the stages on a given workspace.
+constexpr int CS_MAX_STAGES = ADVISOR_MAX_STAGES;
+constexpr int CS_MAX_K = 32;
+// Byte offsets of a cascade's buffers inside its workspace (each part
+// 256-byte aligned). Stage s < n_stages - 1 hands on keep[s] candidates per
+// kernel: their variant indices (ascending, -1 padded), their descriptor
+// rows (kernel id k, or -1 for padding, which makes the row ineligible) and
+// the segment offsets k * keep[s] of that compact workload; a middle stage
+// also writes its predictions of the previous compact workload.
+struct CascadeLayout {
+    size_t pred = 0;                    // float [n_v] first-stage predictions (caller gave none)
+    size_t cand[CS_MAX_STAGES] = {};    // int64 [n_k * keep_s]
+    size_t vd[CS_MAX_STAGES] = {};      // int64 [n_k * keep_s][8]
+    size_t off[CS_MAX_STAGES] = {};     // int64 [n_k + 1]
+    size_t cpred[CS_MAX_STAGES] = {};   // float [n_k * keep_s] (stages with a successor)
+    size_t best = 0;                    // int64 [n_k] winners inside the last compact workload
+    size_t total = 0;
+};
+
+CascadeLayout cascade_layout(int64_t n_v, int64_t n_k, const int *keep, int n_stages,
+                             bool own_pred);
+int cascade_check(const advisor_model *const *models, const int *keep, int n_stages,
+                  const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
+                  int64_t n_kernels, int64_t n_variants, const int64_t *best_out);
+int cascade_run(const advisor_model *const *models, const int *keep, int n_stages,
+                const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets, int64_t n_k,
+                int64_t n_v, int64_t *best_out, float *pred_out, unsigned char *ws, hipStream_t s,
+                bool may_check_offsets);
+
 // Whether tile shape V is built for this precision and width (mlp.hip).
 bool tile_shape_exists(int precision, int W, int V);
 

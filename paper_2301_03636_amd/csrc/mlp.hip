@@ -299,11 +299,12 @@ extern "C" int advisor_predict(const advisor_model *model, const int64_t *feat, 
                                                model->tile_variant, a, as_stream(stream));
 }
 
-extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
-                            const int64_t *vdesc, const int64_t *offsets, int64_t n_kernels,
-                            int64_t n_variants, int64_t *best_out, float *pred_out, void *stream)
+namespace adv {
+
+int rank_core(const advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
+              const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int64_t *best_out,
+              float *pred_out, hipStream_t s, bool may_check_offsets)
 {
-    clear_error();
     int rc = check_model_ready(model);
     if (rc) return rc;
     if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
@@ -312,9 +313,8 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
     if (n_kernels == 0) return ADVISOR_OK;
     if (!kdesc || !offsets || !best_out || (n_variants > 0 && !vdesc))
         return fail(ADVISOR_EINVAL, "advisor_rank: null pointer");
-    hipStream_t s = as_stream(stream);
-    if (debug_offsets(s)) {
-        if (int rc2 = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, stream)) return rc2;
+    if (may_check_offsets && debug_offsets(s)) {
+        if (int rc2 = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, s)) return rc2;
     }
     const unsigned kb = (unsigned)((n_kernels + 255) / 256);
     hipLaunchKernelGGL(keys_init_kernel, dim3(kb), dim3(256), 0, s,
@@ -337,6 +337,17 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
     hipLaunchKernelGGL(keys_final_kernel, dim3(kb), dim3(256), 0, s, best_out, n_kernels);
     ADV_LAUNCHED("keys_final_kernel");
     return ADVISOR_OK;
+}
+
+}  // namespace adv
+
+extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
+                            const int64_t *vdesc, const int64_t *offsets, int64_t n_kernels,
+                            int64_t n_variants, int64_t *best_out, float *pred_out, void *stream)
+{
+    clear_error();
+    return rank_core(model, kdesc, vdesc, offsets, n_kernels, n_variants, best_out, pred_out,
+                     as_stream(stream), true);
 }
 
 extern "C" int advisor_rank_multi(const advisor_model *const *models, int n_models,

@@ -1,9 +1,11 @@
-// Precision-refined ranking: a low-precision model ranks every variant, then
-// each kernel's K best variants by its predictions are ranked again by a
-// second (higher-precision) model, so near-ties that low-precision rounding
-// could order either way are decided as the second model decides them. The
-// argmin of section 3's prediction flow (N = 1) over a candidate set chosen
-// by the same network in another precision.
+// Multi-stage ranking: a fast low-precision model ranks every variant, each
+// kernel's K best variants by its predictions go on to a second, more
+// precise model, whose K' best go on to a third, and so on; the last model's
+// argmin over its candidates is the answer. Near-ties that low-precision
+// rounding could order either way are thereby decided as the last model
+// decides them, at the cost of its predictions for a few candidates per
+// kernel. It is the argmin of section 3's prediction flow (N = 1) over
+// candidate sets chosen by the same network in lower precisions.
 // The file also holds the prediction flow with a top-N list (the fused pass,
 // then the segmented top-N on its predictions), which shares the workspace.
 #include <algorithm>
@@ -12,82 +14,90 @@
 
 namespace adv {
 
-constexpr int RF_MAX_K = 16;
-
-struct RefineWs {
-    int64_t n_v = 0, n_k = 0;
-    int k = 0;
-    float *pred = nullptr;      // [n_v] first-pass predictions
-    int64_t *cand = nullptr;    // [n_k * K] candidate variant indices, ascending, -1 padded
-    int64_t *vdesc_c = nullptr; // [n_k * K][8] candidate descriptors
-    int64_t *off_c = nullptr;   // [n_k + 1] = k * K
-    int64_t *best_c = nullptr;  // [n_k] second-pass winners (index into the candidates)
+// A model's workspace for the multi-stage and top-N calls: one device arena,
+// grown on demand (synchronous allocation).
+struct RankWs {
+    unsigned char *base = nullptr;
+    size_t bytes = 0;
 };
 
 void free_refine_ws(advisor_model *m)
 {
-    RefineWs *w = reinterpret_cast<RefineWs *>(m->refine_ws);
+    RankWs *w = reinterpret_cast<RankWs *>(m->refine_ws);
     if (!w) return;
-    void *ptrs[] = {w->pred, w->cand, w->vdesc_c, w->off_c, w->best_c};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    if (w->base) (void)hipFree(w->base);
     delete w;
     m->refine_ws = nullptr;
 }
 
-static int ensure_refine_ws(advisor_model *m, int64_t n_v, int64_t n_k, int k)
+static int ensure_arena(advisor_model *m, size_t bytes, unsigned char **out)
 {
-    RefineWs *w = reinterpret_cast<RefineWs *>(m->refine_ws);
+    RankWs *w = reinterpret_cast<RankWs *>(m->refine_ws);
     if (!w) {
-        w = new (std::nothrow) RefineWs();
+        w = new (std::nothrow) RankWs();
         if (!w) return fail(ADVISOR_ENOMEM, "host allocation");
         m->refine_ws = w;
     }
-    if (n_v > w->n_v) {
-        if (w->pred) (void)hipFree(w->pred);
-        w->pred = nullptr;
-        w->n_v = 0;
-        ADV_HIP(hipMalloc((void **)&w->pred, sizeof(float) * n_v));
-        w->n_v = n_v;
+    if (bytes > w->bytes) {
+        if (w->base) (void)hipFree(w->base);
+        w->base = nullptr;
+        w->bytes = 0;
+        ADV_HIP(hipMalloc((void **)&w->base, bytes));
+        w->bytes = bytes;
     }
-    if (n_k > w->n_k || k > w->k) {
-        const int64_t nk = std::max(n_k, w->n_k);
-        const int kk = std::max(k, w->k);
-        for (void **p : {(void **)&w->cand, (void **)&w->vdesc_c, (void **)&w->off_c, (void **)&w->best_c})
-            if (*p) { (void)hipFree(*p); *p = nullptr; }
-        w->n_k = 0;
-        w->k = 0;
-        ADV_HIP(hipMalloc((void **)&w->cand, sizeof(int64_t) * nk * kk));
-        ADV_HIP(hipMalloc((void **)&w->vdesc_c, sizeof(int64_t) * nk * kk * VD));
-        ADV_HIP(hipMalloc((void **)&w->off_c, sizeof(int64_t) * (nk + 1)));
-        ADV_HIP(hipMalloc((void **)&w->best_c, sizeof(int64_t) * nk));
-        w->n_k = nk;
-        w->k = kk;
-    }
+    *out = w->base;
     return ADVISOR_OK;
 }
 
-// order-preserving key of (prediction, index): smaller prediction first,
-// then lower index; -0 equals +0
-__device__ __forceinline__ uint64_t rf_key(float p, uint32_t idx)
+CascadeLayout cascade_layout(int64_t n_v, int64_t n_k, const int *keep, int n_stages,
+                                    bool own_pred)
 {
-    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
-    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return ((uint64_t)u << 32) | idx;
+    CascadeLayout L;
+    size_t at = 0;
+    auto take = [&](size_t b) {
+        const size_t o = at;
+        at += (b + 255) & ~(size_t)255;
+        return o;
+    };
+    if (own_pred) L.pred = take(sizeof(float) * (size_t)n_v);
+    for (int s = 0; s + 1 < n_stages; ++s) {
+        const size_t rows = (size_t)n_k * keep[s];
+        L.cand[s] = take(8 * rows);
+        L.vd[s] = take(8 * rows * VD);
+        L.off[s] = take(8 * ((size_t)n_k + 1));
+        if (s + 2 < n_stages) L.cpred[s] = take(4 * rows);
+    }
+    L.best = take(8 * (size_t)n_k);
+    L.total = at;
+    return L;
 }
 
 constexpr int RF_WAVES = 4;
 
-// One wave per kernel segment: the K smallest keys of its non-NaN
-// predictions (each lane keeps a sorted list of its own K best, then K rounds
-// of a wave-wide minimum pop the overall best), written as candidate indices
-// in ascending index order, padded with -1; the candidates' descriptors are
-// gathered with kernel id k (padding rows get kernel id -1: invalid).
+// order-preserving key of (prediction, row): smaller prediction first, then
+// lower row; -0 equals +0
+__device__ __forceinline__ uint64_t rf_key(float p, uint32_t row)
+{
+    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)u << 32) | row;
+}
+
+// One wave per kernel segment of a workload's predictions: the K smallest
+// keys of its non-NaN predictions (each lane keeps a sorted list of its own K
+// best, then K rounds of a wave-wide minimum pop the overall best), written
+// as candidate variant indices in ascending order, padded with -1. A row's
+// variant index is map[row] for a compact workload (map = the previous
+// stage's candidates, ascending within each kernel, so row order is variant
+// order and ties still go to the lowest variant index), else the row itself.
+// The candidates' descriptor rows are gathered from the original vdesc with
+// kernel id k (padding rows get kernel id -1: never eligible).
 template <int K>
 __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
     const float *__restrict__ pred, const int64_t *__restrict__ offsets,
-    const int64_t *__restrict__ vdesc, int64_t n_k, int64_t n_v, int64_t *__restrict__ cand,
-    int64_t *__restrict__ vdesc_c, int64_t *__restrict__ off_c)
+    const int64_t *__restrict__ map, const int64_t *__restrict__ vdesc, int64_t n_k,
+    int64_t n_rows, int64_t *__restrict__ cand, int64_t *__restrict__ vdesc_c,
+    int64_t *__restrict__ off_c)
 {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * RF_WAVES + (threadIdx.x >> 6);
@@ -96,8 +106,8 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
         if (lane == 0) off_c[n_k] = n_k * K;
         return;
     }
-    const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
-    const int64_t hi = max(lo, min(offsets[k + 1], n_v));
+    const int64_t lo = max((int64_t)0, min(offsets[k], n_rows));
+    const int64_t hi = max(lo, min(offsets[k + 1], n_rows));
     uint64_t top[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) top[q] = ~0ull;
@@ -114,8 +124,9 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
             x = less ? t : x;
         }
     }
-    // K rounds: the wave-wide minimum of the lanes' heads, popped from its lane
-    uint64_t chosen[K];
+    // K rounds: the wave-wide minimum of the lanes' heads (the same value in
+    // every lane, kept scalar), popped from the lane that holds it
+    int64_t crow[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) {
         uint64_t v = top[0];
@@ -124,43 +135,39 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
             const uint64_t o = __shfl_xor(v, off, 64);
             v = o < v ? o : v;
         }
-        chosen[r] = v;
-        if (v != ~0ull && top[0] == v) {  // keys are unique (they hold the index)
+        const uint32_t vlo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+        const uint32_t vhi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+        v = ((uint64_t)vhi << 32) | vlo;
+        crow[r] = v == ~0ull ? INT64_MAX : (int64_t)vlo;
+        if (v != ~0ull && top[0] == v) {  // keys are unique (they hold the row)
 #pragma unroll
             for (int q = 0; q + 1 < K; ++q) top[q] = top[q + 1];
             top[K - 1] = ~0ull;
         }
     }
-    // candidate indices in ascending order (padding ~0 sorts last)
-    int64_t idx[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) idx[r] = chosen[r] == ~0ull ? INT64_MAX : (int64_t)(chosen[r] & 0xffffffffull);
-#pragma unroll
-    for (int a = 0; a < K; ++a)
-#pragma unroll
-        for (int b = 0; b + 1 < K - a; ++b) {
-            const int64_t x = idx[b], y = idx[b + 1];
-            idx[b] = x < y ? x : y;
-            idx[b + 1] = x < y ? y : x;
-        }
-    // lane s < K writes slot s; lanes K .. write nothing
-    int64_t mine = INT64_MAX;
-#pragma unroll
-    for (int r = 0; r < K; ++r)
-        if (lane == r) mine = idx[r];
+    // lane r < K takes the r-th popped row and writes it to the slot of its
+    // rank in ascending row order (padding, INT64_MAX, sorts last)
     if (lane < K) {
-        const int64_t slot = k * K + lane;
-        const bool has = mine != INT64_MAX;
-        cand[slot] = has ? mine : -1;
-        const int64_t *src = vdesc + (has ? mine : 0) * VD;
-        int64_t *dst = vdesc_c + slot * VD;
+        int64_t mine = INT64_MAX;
 #pragma unroll
-        for (int c = 0; c < VD; ++c) dst[c] = has ? (c == 0 ? k : src[c]) : (c == 0 ? -1 : 0);
+        for (int r = 0; r < K; ++r)
+            if (lane == r) mine = crow[r];
+        int slot = 0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) slot += (crow[r] < mine || (crow[r] == mine && r < lane)) ? 1 : 0;
+        const int64_t dst_row = k * K + slot;
+        int64_t var = -1;
+        if (mine != INT64_MAX) var = map ? map[mine] : mine;
+        cand[dst_row] = var;
+        const int64_t *src = vdesc + (var >= 0 ? var : 0) * VD;
+        int64_t *dst = vdesc_c + dst_row * VD;
+#pragma unroll
+        for (int c = 0; c < VD; ++c) dst[c] = var >= 0 ? (c == 0 ? k : src[c]) : (c == 0 ? -1 : 0);
     }
     if (lane == 0) off_c[k] = k * K;
 }
 
-// best[k] = the candidate the second pass chose (its variant index), or -1
+// best[k] = the candidate the last stage chose (its variant index), or -1
 __global__ void refine_map_kernel(const int64_t *__restrict__ best_c,
                                   const int64_t *__restrict__ cand, int64_t n_k,
                                   int64_t *__restrict__ best)
@@ -172,18 +179,119 @@ __global__ void refine_map_kernel(const int64_t *__restrict__ best_c,
     }
 }
 
-template <int K>
-static void launch_topk(const float *pred, const int64_t *offsets, const int64_t *vdesc,
-                        int64_t n_k, int64_t n_v, RefineWs *w, hipStream_t s)
+static int launch_topk(int K, const float *pred, const int64_t *offsets, const int64_t *map,
+                       const int64_t *vdesc, int64_t n_k, int64_t n_rows, int64_t *cand,
+                       int64_t *vdesc_c, int64_t *off_c, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((n_k + 1 + RF_WAVES - 1) / RF_WAVES);
-    hipLaunchKernelGGL(topk_gather_kernel<K>, dim3(blocks), dim3(RF_WAVES * 64), 0, s, pred,
-                       offsets, vdesc, n_k, n_v, w->cand, w->vdesc_c, w->off_c);
+#define ADV_TK(KK)                                                                        \
+    case KK:                                                                              \
+        hipLaunchKernelGGL(topk_gather_kernel<KK>, dim3(blocks), dim3(RF_WAVES * 64), 0, s, \
+                           pred, offsets, map, vdesc, n_k, n_rows, cand, vdesc_c, off_c);  \
+        break;
+    switch (K) {
+        ADV_TK(1) ADV_TK(2) ADV_TK(4) ADV_TK(8) ADV_TK(16) ADV_TK(32)
+    default: return fail(ADVISOR_EINVAL, "candidates per kernel must be 1, 2, 4, 8, 16 or 32");
+    }
+#undef ADV_TK
+    ADV_LAUNCHED("topk_gather_kernel");
+    return ADVISOR_OK;
+}
+
+// Argument checks shared by the multi-stage entry points.
+int cascade_check(const advisor_model *const *models, const int *keep, int n_stages,
+                         const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
+                         int64_t n_kernels, int64_t n_variants, const int64_t *best_out)
+{
+    if (n_stages < 1 || n_stages > CS_MAX_STAGES) return fail(ADVISOR_EINVAL, "1 to 4 stages");
+    if (n_stages > 1 && !keep) return fail(ADVISOR_EINVAL, "null keep");
+    for (int s = 0; s + 1 < n_stages; ++s) {
+        const int K = keep[s];
+        if (K != 1 && K != 2 && K != 4 && K != 8 && K != 16 && K != 32)
+            return fail(ADVISOR_EINVAL, "candidates per kernel must be 1, 2, 4, 8, 16 or 32");
+        if (s > 0 && K > keep[s - 1])
+            return fail(ADVISOR_EINVAL, "a stage keeps no more candidates than the one before");
+    }
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels >= ((int64_t)1 << 31) / CS_MAX_K)
+        return fail(ADVISOR_ESHAPE, "n_kernels * 32 must be < 2^31");
+    if (!models) return fail(ADVISOR_EINVAL, "null models");
+    for (int s = 0; s < n_stages; ++s) {
+        if (!models[s]) return fail(ADVISOR_EINVAL, "null model");
+        if (models[s]->device != models[0]->device)
+            return fail(ADVISOR_EINVAL, "the models live on different devices");
+    }
+    if (n_kernels > 0 && (!kdesc || !offsets || !best_out || (n_variants > 0 && !vdesc)))
+        return fail(ADVISOR_EINVAL, "null pointer");
+    return ADVISOR_OK;
+}
+
+// The stages, on a workspace of at least cascade_layout(...).total bytes.
+int cascade_run(const advisor_model *const *models, const int *keep, int n_stages,
+                       const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
+                       int64_t n_k, int64_t n_v, int64_t *best_out, float *pred_out,
+                       unsigned char *ws, hipStream_t s, bool may_check_offsets)
+{
+    const CascadeLayout L = cascade_layout(n_v, n_k, keep, n_stages, pred_out == nullptr);
+    float *pred = pred_out ? pred_out : reinterpret_cast<float *>(ws + L.pred);
+    // first stage: every variant (its argmin is the answer only with one stage)
+    int rc = rank_core(models[0], kdesc, vdesc, offsets, n_k, n_v, best_out,
+                       n_stages > 1 ? pred : pred_out, s, may_check_offsets);
+    if (rc || n_stages == 1 || n_v == 0) return rc;  // no variant: every kernel is -1 already
+    const float *P = pred;
+    const int64_t *offP = offsets;
+    const int64_t *mapP = nullptr;
+    int64_t rowsP = n_v;
+    int64_t *best_c = reinterpret_cast<int64_t *>(ws + L.best);
+    for (int st = 0; st + 1 < n_stages; ++st) {
+        const int K = keep[st];
+        int64_t *cand = reinterpret_cast<int64_t *>(ws + L.cand[st]);
+        int64_t *vd_c = reinterpret_cast<int64_t *>(ws + L.vd[st]);
+        int64_t *off_c = reinterpret_cast<int64_t *>(ws + L.off[st]);
+        rc = launch_topk(K, P, offP, mapP, vdesc, n_k, rowsP, cand, vd_c, off_c, s);
+        if (rc) return rc;
+        const bool last = st + 2 == n_stages;
+        float *cp = last ? nullptr : reinterpret_cast<float *>(ws + L.cpred[st]);
+        rc = rank_core(models[st + 1], kdesc, vd_c, off_c, n_k, n_k * K, best_c, cp, s, false);
+        if (rc) return rc;
+        if (last) {
+            hipLaunchKernelGGL(refine_map_kernel, dim3((unsigned)((n_k + 255) / 256)), dim3(256),
+                               0, s, best_c, cand, n_k, best_out);
+            ADV_LAUNCHED("refine_map_kernel");
+        }
+        P = cp;
+        offP = off_c;
+        mapP = cand;
+        rowsP = n_k * K;
+    }
+    return ADVISOR_OK;
 }
 
 }  // namespace adv
 
 using namespace adv;
+
+extern "C" int advisor_rank_cascade(advisor_model *const *models, const int *keep, int n_stages,
+                                    const int64_t *kdesc, const int64_t *vdesc,
+                                    const int64_t *offsets, int64_t n_kernels,
+                                    int64_t n_variants, int64_t *best_out, float *pred_out,
+                                    void *stream)
+{
+    clear_error();
+    int rc = cascade_check(models, keep, n_stages, kdesc, vdesc, offsets, n_kernels, n_variants,
+                           best_out);
+    if (rc || n_kernels == 0) return rc;
+    unsigned char *ws = nullptr;
+    if (n_stages > 1) {
+        const CascadeLayout L = cascade_layout(n_variants, n_kernels, keep, n_stages,
+                                               pred_out == nullptr);
+        rc = ensure_arena(models[0], L.total, &ws);
+        if (rc) return rc;
+    }
+    return cascade_run(models, keep, n_stages, kdesc, vdesc, offsets, n_kernels, n_variants,
+                       best_out, pred_out, ws, as_stream(stream), true);
+}
 
 extern "C" int advisor_rank_refined(advisor_model *model, const advisor_model *refine,
                                     const int64_t *kdesc, const int64_t *vdesc,
@@ -193,42 +301,12 @@ extern "C" int advisor_rank_refined(advisor_model *model, const advisor_model *r
 {
     clear_error();
     if (!model || !refine) return fail(ADVISOR_EINVAL, "advisor_rank_refined: null model");
-    if (model->device != refine->device)
-        return fail(ADVISOR_EINVAL, "the two models live on different devices");
     if (top_k != 1 && top_k != 2 && top_k != 4 && top_k != 8 && top_k != 16)
         return fail(ADVISOR_EINVAL, "top_k must be 1, 2, 4, 8 or 16");
-    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
-    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
-    if (n_kernels >= ((int64_t)1 << 31) / RF_MAX_K)
-        return fail(ADVISOR_ESHAPE, "n_kernels * top_k must be < 2^31");
-    if (n_kernels == 0) return ADVISOR_OK;
-    if (!kdesc || !offsets || !best_out || (n_variants > 0 && !vdesc))
-        return fail(ADVISOR_EINVAL, "advisor_rank_refined: null pointer");
-    hipStream_t s = as_stream(stream);
-    int rc = ensure_refine_ws(model, n_variants, n_kernels, top_k);
-    if (rc) return rc;
-    RefineWs *w = reinterpret_cast<RefineWs *>(model->refine_ws);
-    float *pred = pred_out ? pred_out : w->pred;
-    // first pass: every variant, low precision (its argmin is not used)
-    rc = advisor_rank(model, kdesc, vdesc, offsets, n_kernels, n_variants, best_out, pred, s);
-    if (rc) return rc;
-    if (n_variants == 0) return ADVISOR_OK;  // every kernel is -1 already
-    switch (top_k) {
-    case 1: launch_topk<1>(pred, offsets, vdesc, n_kernels, n_variants, w, s); break;
-    case 2: launch_topk<2>(pred, offsets, vdesc, n_kernels, n_variants, w, s); break;
-    case 4: launch_topk<4>(pred, offsets, vdesc, n_kernels, n_variants, w, s); break;
-    case 8: launch_topk<8>(pred, offsets, vdesc, n_kernels, n_variants, w, s); break;
-    default: launch_topk<16>(pred, offsets, vdesc, n_kernels, n_variants, w, s); break;
-    }
-    ADV_LAUNCHED("topk_gather_kernel");
-    // second pass: the candidates, ranked by the refining model
-    rc = advisor_rank(refine, kdesc, w->vdesc_c, w->off_c, n_kernels, n_kernels * top_k,
-                      w->best_c, nullptr, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(refine_map_kernel, dim3((unsigned)((n_kernels + 255) / 256)), dim3(256), 0,
-                       s, w->best_c, w->cand, n_kernels, best_out);
-    ADV_LAUNCHED("refine_map_kernel");
-    return ADVISOR_OK;
+    advisor_model *const models[2] = {model, const_cast<advisor_model *>(refine)};
+    const int keep[1] = {top_k};
+    return advisor_rank_cascade(models, keep, 2, kdesc, vdesc, offsets, n_kernels, n_variants,
+                                best_out, pred_out, stream);
 }
 
 extern "C" int advisor_rank_topn(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
@@ -247,12 +325,15 @@ extern "C" int advisor_rank_topn(advisor_model *model, const int64_t *kdesc, con
     if (!kdesc || !offsets || !idx_out || (n_variants > 0 && !vdesc))
         return fail(ADVISOR_EINVAL, "advisor_rank_topn: null pointer");
     hipStream_t s = as_stream(stream);
-    int rc = ensure_refine_ws(model, pred_out ? 0 : n_variants, n_kernels, 1);
+    // workspace: the predictions (unless the caller keeps them), then the
+    // fused pass's argmin, which is not used
+    const size_t pbytes = pred_out ? 0 : ((sizeof(float) * (size_t)n_variants + 255) & ~(size_t)255);
+    unsigned char *ws = nullptr;
+    int rc = ensure_arena(model, pbytes + 8 * (size_t)n_kernels, &ws);
     if (rc) return rc;
-    RefineWs *w = reinterpret_cast<RefineWs *>(model->refine_ws);
-    float *pred = pred_out ? pred_out : w->pred;
-    // the fused pass; its argmin lands in the workspace and is not used
-    rc = advisor_rank(model, kdesc, vdesc, offsets, n_kernels, n_variants, w->best_c, pred, s);
+    float *pred = pred_out ? pred_out : reinterpret_cast<float *>(ws);
+    rc = advisor_rank(model, kdesc, vdesc, offsets, n_kernels, n_variants,
+                      reinterpret_cast<int64_t *>(ws + pbytes), pred, s);
     if (rc) return rc;
     return launch_topn_preds(pred, offsets, n_kernels, n_variants, top_n, idx_out, val_out, s);
 }

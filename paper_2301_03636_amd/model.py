@@ -51,6 +51,13 @@ class Model:
         return _lib.advisor_rank_refined(self.handle, refine.handle, kdesc, vdesc, offsets, top_k,
                                          best_out, pred_out)
 
+    def rank_cascade(self, later, keep, kdesc, vdesc, offsets, best_out=None, pred_out=None):
+        """Rank with this model, hand each kernel's keep[0] best candidates
+        to later[0], its keep[1] best to later[1], ...; the last model's
+        argmin over its candidates is the pick (advisor_rank_cascade)."""
+        return _lib.advisor_rank_cascade([self.handle] + [m.handle for m in later], keep, kdesc,
+                                         vdesc, offsets, best_out, pred_out)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.advisor_model_destroy(self.handle)
@@ -107,6 +114,13 @@ class Plan:
 
     def launch(self):
         _lib.advisor_plan_launch(self.handle)
+
+    def rank_cascade(self, later, keep, kdesc, vdesc, offsets, best_out=None, pred_out=None):
+        """Rank with this model, hand each kernel's keep[0] best candidates
+        to later[0], its keep[1] best to later[1], ...; the last model's
+        argmin over its candidates is the pick (advisor_rank_cascade)."""
+        return _lib.advisor_rank_cascade([self.handle] + [m.handle for m in later], keep, kdesc,
+                                         vdesc, offsets, best_out, pred_out)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -84,6 +84,27 @@ def test_entry_points_reject_null_model():
     L.advisor_model_destroy(None)
 
 
+def test_cascade_argument_checks():
+    L = _lib.lib()
+    null2 = (C.c_void_p * 3)(None, None, None)
+
+    def call(n_stages, keep, nk=1, nv=4, models=null2):
+        kp = None if keep is None else (C.c_int * len(keep))(*keep)
+        return L.advisor_rank_cascade(models, kp, n_stages, None, None, None, nk, nv, None, None,
+                                      None)
+    assert call(0, [8]) == EINVAL
+    assert call(5, [8, 4, 2, 1]) == EINVAL
+    assert call(2, None) == EINVAL
+    assert call(2, [3]) == EINVAL            # not a power of two
+    assert call(2, [64]) == EINVAL           # more than 32
+    assert call(3, [4, 8]) == EINVAL         # a later cut keeps more
+    assert call(2, [8], nk=-1) == ESHAPE
+    assert call(2, [8], nv=1 << 32) == ESHAPE
+    assert call(2, [8], nk=1 << 26) == ESHAPE
+    assert call(2, [8]) == EINVAL            # null models
+    assert call(1, None, models=None) == EINVAL
+
+
 def test_zscore_argument_checks():
     L = _lib.lib()
     assert L.advisor_zscore_fit(None, 0, None, None, None) == ESHAPE

@@ -1,0 +1,188 @@
+"""Multi-stage ranking (advisor_rank_cascade): fp8, bf16 and fp32 copies of
+one network, each cut handing a kernel's best candidates to the next model.
+
+Checked exactly against its definition (numpy over each model's own
+predictions of every variant: the first model's k0 best, then the second's
+k1 best of those, ..., the last model's argmin, lowest index on ties), and
+for argmin agreement with the float64 oracle on the two large workloads,
+against the oracle's picks stored by tests/golden/make_oracle_picks.py."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2301_03636_amd as adv
+import workload
+from gpu_util import host, say, segment_argmin, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+sys.path.insert(0, GOLDEN)
+import make_oracle_picks  # noqa: E402
+
+# the bar the path headlined by the benchmark must clear on every stored kernel
+AGREEMENT_BAR = 0.995
+
+
+def _expected(preds, keep, off):
+    """Iterated selection on full-workload predictions: per kernel, the
+    keep[0] smallest (preds[0], index) among non-NaN rows, then the keep[1]
+    smallest (preds[1], index) of those, ..., then the smallest (preds[-1],
+    index); -1 if none is left."""
+    out = np.full(off.size - 1, -1, dtype=np.int64)
+    for s in range(off.size - 1):
+        cand = np.arange(off[s], off[s + 1])
+        for st, p in enumerate(preds):
+            cand = cand[~np.isnan(p[cand])]
+            if cand.size == 0:
+                break
+            order = np.lexsort((cand, p[cand].astype(np.float64)))
+            n = keep[st] if st < len(keep) else 1
+            cand = np.sort(cand[order[:n]])
+        if cand.size:
+            out[s] = cand[0]
+    return out
+
+
+def _ragged_workload(seed):
+    kd, vd, off = workload.make_descriptors(300, 1, 900, seed=seed, invalid_frac=0.05)
+    counts = np.diff(off)
+    keep = np.ones(vd.shape[0], dtype=bool)
+    for k in (7, 150):                      # two empty kernels
+        keep[off[k]:off[k + 1]] = False
+        counts[k] = 0
+    vd = vd[keep]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    vd[3, 0] = (vd[3, 0] + 1) % 300         # a variant filed under the wrong kernel
+    return kd, vd, off
+
+
+def _models(widths, precs, p, f_cal, mu, sd):
+    ms = []
+    for pr in precs:
+        m = adv.Model(widths, pr)
+        m.set_params(p, mu, sd)
+        if pr == "fp8":
+            m.calibrate_fp8(to_dev(f_cal))
+        ms.append(m)
+    return ms
+
+
+@pytest.mark.parametrize("precs, keeps", [
+    (("fp8", "bf16", "fp32"), [(16, 4), (32, 2), (8, 8), (4, 1), (32, 32)]),
+    (("fp8", "fp32"), [(1,), (16,), (32,)]),
+    (("bf16", "fp8", "bf16", "fp32"), [(16, 8, 2), (32, 4, 4)]),
+    (("fp32",), [()]),
+])
+def test_cascade_definition(precs, keeps):
+    widths = (32, 256, 256, 256, 1)
+    kd, vd, off = _ragged_workload(711)
+    f, inv = oracle.featurize(kd, vd)
+    mu, sd = oracle.zscore_fit(f[inv == 0])
+    p = workload.he_init(widths, 712, bias_scale=0.2)
+    ms = _models(widths, precs, p, f[inv == 0][:4096], mu, sd)
+    K, V, O = to_dev(kd), to_dev(vd), to_dev(off)
+    # every model's own prediction of every variant (NaN where ineligible)
+    preds = [host(m.rank(K, V, O, want_pred=True)[1]) for m in ms]
+    pred0 = torch.empty(vd.shape[0], dtype=torch.float32, device="cuda")
+    for keep in keeps:
+        pred0.fill_(0.0)
+        best = host(ms[0].rank_cascade(ms[1:], keep, K, V, O, pred_out=pred0))
+        exp = _expected(preds, keep, off)
+        say("cascade %s keep %s: %d kernels, %d differ from the definition" %
+            ("/".join(precs), keep, off.size - 1, int(np.sum(best != exp))))
+        assert np.array_equal(best, exp)
+        assert best[7] == -1 and best[150] == -1
+        # the first model's predictions come back bit for bit
+        assert np.array_equal(host(pred0).view(np.uint32), preds[0].view(np.uint32))
+    if len(precs) == 1:
+        assert np.array_equal(best, segment_argmin(preds[0], off))
+    for m in ms:
+        m.close()
+
+
+def test_cascade_keep_one_equals_first_model_argmin():
+    """A cut keeping one candidate hands on the first model's argmin, so the
+    later models cannot change it; the refined call is the two-stage case."""
+    widths = (32, 64, 64, 1)
+    kd, vd, off = _ragged_workload(721)
+    f, inv = oracle.featurize(kd, vd)
+    mu, sd = oracle.zscore_fit(f[inv == 0])
+    p = workload.he_init(widths, 722, bias_scale=0.2)
+    lo, mid, hi = _models(widths, ("bf16", "bf16", "fp32"), p, None, mu, sd)
+    K, V, O = to_dev(kd), to_dev(vd), to_dev(off)
+    b_lo = host(lo.rank(K, V, O))
+    assert np.array_equal(host(lo.rank_cascade([mid, hi], (1, 1), K, V, O)), b_lo)
+    for k in (2, 8, 16):
+        assert np.array_equal(host(lo.rank_cascade([hi], (k,), K, V, O)),
+                              host(lo.rank_refined(hi, K, V, O, top_k=k)))
+    # workspace reuse: a smaller call (the first 20 kernels) after a larger one
+    off_s = off[:21]
+    V_s = to_dev(vd[:off_s[-1]])
+    O_s = to_dev(off_s)
+    preds_s = [host(m.rank(K, V_s, O_s, want_pred=True)[1]) for m in (lo, mid, hi)]
+    assert np.array_equal(host(lo.rank_cascade([mid, hi], (8, 2), K, V_s, O_s)),
+                          _expected(preds_s, (8, 2), off_s))
+    for m in (lo, mid, hi):
+        m.close()
+
+
+def _stored_agreement(cfg, paths):
+    """Argmin agreement of each path's picks with the oracle's stored picks
+    on the full workload `cfg` (He-initialized weights, Z-score statistics
+    fitted by the library on the calibration sample). paths: name ->
+    (precisions, keep). Returns name -> (agreement, n kernels, picks)."""
+    gold = make_oracle_picks.load(cfg)
+    c = workload.make_config(cfg)
+    kd, vd, off, params, widths = c["kdesc"], c["vdesc"], c["offsets"], c["params"], c["widths"]
+    assert workload.inputs_digest(kd, vd, off, params) == gold["digest"], \
+        "stored oracle picks were computed on other inputs: rerun make_oracle_picks.py"
+    K, V, O = to_dev(kd), to_dev(vd), to_dev(off)
+    del vd
+    cal = to_dev(workload.calibration_rows(cfg, V.shape[0]))
+    fcal, icl = adv.advisor_featurize(K, V[cal])
+    fcal = fcal[icl == 0].contiguous()
+    mu, sd = adv.advisor_zscore_fit(fcal)
+    mu, sd = host(mu), host(sd)
+    models = {}
+    for pr in {p for precs, _ in paths.values() for p in precs}:
+        m = adv.Model(widths, pr)
+        m.set_params(params, mu, sd)
+        if pr == "fp8":
+            m.calibrate_fp8(fcal)
+        models[pr] = m
+    ks = gold["kernels"]
+    out = {}
+    for name, (precs, keep) in paths.items():
+        ms = [models[p] for p in precs]
+        best = host(ms[0].rank_cascade(ms[1:], keep, K, V, O))
+        out[name] = (float(np.mean(best[ks] == gold["best"])), int(ks.size), best[ks])
+        say("cfg %d %s: argmin agreement with the oracle %.5f on %d kernels" %
+            (cfg, name, out[name][0], ks.size))
+    for m in models.values():
+        m.close()
+    return out, gold
+
+
+def test_agreement_with_oracle_1024_wide():
+    """The 32768-kernel, 18.9M-variant workload on 32-1024x4-1: the
+    cascade the benchmark headlines reaches the agreement bar on every
+    stored kernel; fp8 alone does not (its 3-bit mantissas scatter the
+    near-ties), which is why the cut exists."""
+    paths = {"fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
+             "fp8": (("fp8",), ())}
+    res, gold = _stored_agreement(5, paths)
+    assert res["fp8>bf16:16>fp32:2"][0] >= AGREEMENT_BAR
+    assert res["fp8"][0] < res["fp8>bf16:16>fp32:2"][0]
+
+
+def test_agreement_with_oracle_512_wide():
+    """The 16384-kernel, 8.9M-variant workload on 32-512x4-1 in bf16 with
+    an fp32 cut, against the oracle's picks on 8192 stored kernels."""
+    paths = {"bf16>fp32:4": (("bf16", "fp32"), (4,)), "bf16": (("bf16",), ())}
+    res, gold = _stored_agreement(3, paths)
+    assert res["bf16>fp32:4"][0] >= AGREEMENT_BAR

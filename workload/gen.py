@@ -216,3 +216,28 @@ def make_config(cfg: int, **overrides):
     params = he_init(c["widths"], s["w"])
     return dict(kdesc=kd, vdesc=vd, offsets=off, params=params, widths=tuple(c["widths"]),
                 seeds=s)
+
+
+def calibration_rows(cfg: int, n_rows: int, n_sample: int = 65536) -> np.ndarray:
+    """Rows of a workload's seeded calibration sample (the variants the
+    Z-score statistics and the fp8 activation scales are fitted on)."""
+    return sample_rows(n_rows, n_sample, seeds(cfg)["desc"] + 7)
+
+
+def agreement_kernels(cfg: int, offsets: np.ndarray, n_sample: int):
+    """The seeded sample of whole kernels on which argmin agreement with the
+    oracle is measured (same return values as sample_kernels)."""
+    return sample_kernels(offsets, n_sample, 7000 + cfg)
+
+
+def inputs_digest(*arrays) -> str:
+    """SHA-256 of the bytes of the given arrays (dtype and shape included):
+    identifies the exact inputs a stored expected value was computed on."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        a = np.ascontiguousarray(a)
+        h.update(str(a.dtype).encode())
+        h.update(str(a.shape).encode())
+        h.update(memoryview(a).cast("B"))
+    return h.hexdigest()
