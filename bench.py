@@ -1,21 +1,26 @@
 """Throughput of the cost-model hot path on one MI355X.
 
-One step = one advisor_rank call over the whole synthetic workload: feature
+One step = one ranking call over the whole synthetic workload (by default
+32768 kernels, 18.9M variants, the 32-1024x4-1 network): feature
 extraction of every variant, Z-score, the MLP on the matrix cores and the
-per-kernel argmin (the paper's prediction flow, many kernels at once),
-replayed from a HIP graph with the tile shape the library's autotuner chose.
-The descriptors and weights are resident in HBM before the timed region; the
-timed region is exactly --steps replays bracketed by device synchronization.
+per-kernel argmin (the paper's prediction flow, many kernels at once). Each
+ranking path is timed on the same resident inputs: the network alone in
+fp32, bf16 and fp8, and cascades in which a low-precision pass over every
+variant hands each kernel's best few candidates on to more precise copies
+of the same network (advisor_rank_cascade). Every path's picks are compared
+with the float64 oracle's picks stored for a seeded sample of whole kernels
+(tests/golden/make_oracle_picks.py), and `value` is the variants ranked per
+second of the fastest path whose argmin agreement with the oracle reaches
+0.995 there. The timed region is exactly --steps calls bracketed by device
+synchronization, inputs resident in HBM.
 
-Prints one JSON line. `value` is variants ranked per second; `roofline`
-prices the fused tile kernel (the dominant kernel) against the matrix-core
+Prints one JSON line. `roofline` prices the dominant kernel of the headline
+path (the fused tile kernel of its first stage) against the matrix-core
 peak of its precision, with its duration taken from HIP events recorded
-around each of its launches; `cpu_baseline` is the float64 CPU oracle timed
-on a seeded sample of whole kernels of the same workload on this host.
-`precisions` repeats the measurement for the other compute precisions on the
-same inputs, each with its argmin agreement against the oracle on the sample
-(He-initialized weights) and for a network first trained by the library on
-the synthetic runtime model.
+around each of its launches on the launch stream; `cpu_baseline` is the
+float64 CPU oracle timed on a seeded sample of whole kernels of the same
+workload on this host; `also` repeats the measurement on the 16384-kernel,
+8.9M-variant 32-512x4-1 workload.
 """
 from __future__ import annotations
 
@@ -36,8 +41,30 @@ import workload  # noqa: E402
 # MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
 PEAK_HBM_GBS = 8000.0
-DEFAULT_PRECISION = {1: "fp32", 2: "fp32", 3: "bf16", 5: "fp8"}
-DEFAULT_ALSO = {1: "", 2: "bf16", 3: "fp32", 5: "bf16,fp32"}
+# Ranking paths timed per workload: name -> (precision of each stage,
+# candidates per kernel handed on by each cut). A single precision is the
+# network alone; "a>b:k>c:j" ranks every variant in a, hands each kernel's k
+# best to b and b's j best to c, whose argmin is the pick.
+PATHS = {
+    2: {"fp32": (("fp32",), ()), "bf16": (("bf16",), ()),
+        "bf16>fp32:2": (("bf16", "fp32"), (2,)), "bf16>fp32:4": (("bf16", "fp32"), (4,)),
+        "bf16>fp32:8": (("bf16", "fp32"), (8,))},
+    3: {"fp32": (("fp32",), ()), "bf16": (("bf16",), ()), "fp8": (("fp8",), ()),
+        "bf16>fp32:2": (("bf16", "fp32"), (2,)), "bf16>fp32:4": (("bf16", "fp32"), (4,)),
+        "bf16>fp32:8": (("bf16", "fp32"), (8,)),
+        "fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
+        "fp8>bf16:16>fp32:4": (("fp8", "bf16", "fp32"), (16, 4))},
+    5: {"fp32": (("fp32",), ()), "bf16": (("bf16",), ()), "fp8": (("fp8",), ()),
+        "bf16>fp32:2": (("bf16", "fp32"), (2,)), "bf16>fp32:4": (("bf16", "fp32"), (4,)),
+        "fp8>fp32:16": (("fp8", "fp32"), (16,)),
+        "fp8>bf16:16>fp32:1": (("fp8", "bf16", "fp32"), (16, 1)),
+        "fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
+        "fp8>bf16:16>fp32:4": (("fp8", "bf16", "fp32"), (16, 4)),
+        "fp8>bf16:32>fp32:2": (("fp8", "bf16", "fp32"), (32, 2)),
+        "fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4))},
+}
+AGREEMENT_BAR = 0.995
+DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}
 WORKLOAD_NAME = {
     1: "single kernel x 256 variants, 32-64-64-1",
     2: "4096 kernels x U[16,1024] variants (2.1M), 32-256x3-1",
@@ -94,58 +121,24 @@ def make_inputs(cfg, seed_desc=None):
     return kd, vd, off, params, tuple(c["widths"])
 
 
-def time_rank(adv, torch, model, kdd, vdd, offd, best, steps, warmup):
-    """Two timed regions of `steps` calls each. First the fused kernel's own
-    duration: eager advisor_rank calls with HIP events recorded around each
-    tile-kernel launch on its stream. Then the step time: replays of the
-    call captured into a HIP graph, bracketed by device synchronization."""
-    for _ in range(warmup):
-        model.rank(kdd, vdd, offd, best_out=best)
-    torch.cuda.synchronize()
-    adv.advisor_profile_enable(True)
-    for _ in range(steps):
-        model.rank(kdd, vdd, offd, best_out=best)
-    torch.cuda.synchronize()
-    launches, kern_ms = adv.advisor_profile_read()
-    adv.advisor_profile_enable(False)
-    plan = adv.Plan.rank(model, kdd, vdd, offd, best)
-    for _ in range(warmup):
-        plan.launch()
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    t0 = time.perf_counter()
-    ev[0].record()
-    for i in range(steps):
-        plan.launch()
-        ev[i + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.close()
-    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
-    pct = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
-           "p90": float(np.percentile(per, 90))}
-    return (t1 - t0) * 1e3 / steps, kern_ms / max(launches, 1), launches, pct
-
-
-def time_with_transfers(adv, torch, model, kd, vd, off, kdd, vdd, offd, best, steps, warmup):
-    """The same ranking with the descriptors handed over in pinned host
+def time_with_transfers(torch, step, kd, vd, off, kdd, vdd, offd, best, steps, warmup):
+    """The headline path with the descriptors handed over in pinned host
     memory: each step copies kdesc, vdesc and offsets to the device, ranks
-    (graph replay) and copies `best` back, all on one stream."""
+    and copies `best` back, all on one stream."""
     pin = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (kd, vd, off)]
     best_h = torch.empty(best.shape, dtype=best.dtype).pin_memory()
-    plan = adv.Plan.rank(model, kdd, vdd, offd, best)
 
-    def step():
+    def full():
         for dev, host in zip((kdd, vdd, offd), pin):
             dev.copy_(host, non_blocking=True)
-        plan.launch()
+        step()
         best_h.copy_(best, non_blocking=True)
     for _ in range(warmup):
-        step()
+        full()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        full()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -156,7 +149,6 @@ def time_with_transfers(adv, torch, model, kd, vd, off, kdd, vdd, offd, best, st
     best_h.copy_(best, non_blocking=True)
     e[2].record()
     torch.cuda.synchronize()
-    plan.close()
     h2d_bytes = sum(int(a.nbytes) for a in (kd, vd, off))
     h2d_ms, d2h_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
     return {"ms_per_step": ms, "value": vd.shape[0] / (ms / 1e3), "h2d_bytes": h2d_bytes,
@@ -237,146 +229,6 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
                                "data_analysis": "%d kernels x 4 variables" % nk_d}[name]}
     del nl, offv, rows, acc, nbytes, offd_d
     return out
-
-
-def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds, gpu_best_by_prec):
-    """The float64 oracle (as written, parallel over kernels) on a seeded
-    sample of whole kernels sized to about `seconds` of CPU time."""
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    p64 = params.astype(np.float64)
-
-    def run(n_kernels, seed):
-        ks, rows, sub_off = workload.sample_kernels(off, n_kernels, seed)
-        vsub = vd[rows].copy()
-        vsub[:, 0] = np.repeat(np.arange(ks.size), sub_off[1:] - sub_off[:-1])
-        t0 = time.perf_counter()
-        best, _ = oracle.rank(kd[ks], vsub, sub_off, widths, p64, mu, sd, n_threads=threads,
-                              want_pred=False)
-        dt = time.perf_counter() - t0
-        glob = np.where(best >= 0, rows[np.maximum(best, 0)], -1)
-        return ks, rows.size, dt, glob
-
-    nk = off.size - 1
-    probe = min(nk, max(1, 2 * threads))
-    _, nv_probe, dt_probe, _ = run(probe, 4242)
-    per_variant = dt_probe / max(nv_probe, 1)
-    avg = (off[-1] / nk)
-    n_sample = int(min(nk, max(probe, seconds / max(per_variant * avg, 1e-9))))
-    ks, nv_s, dt, best_cpu = run(n_sample, 4243)
-    agree = {}
-    for prec, gb in gpu_best_by_prec.items():
-        agree[prec] = float(np.mean(gb[ks] == best_cpu))
-    return {
-        "value": nv_s / dt,
-        "unit": "variants/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": "%d of %d kernels (seeded), %d variants, %.1f s wall" % (ks.size, nk, nv_s, dt),
-    }, agree, per_variant
-
-
-def trained_agreement(adv, torch, to_dev, kd, vd, off, widths, precs, per_variant, seconds,
-                      refine_k):
-    """Argmin agreement with the oracle for a network trained by the
-    library's own training step on the synthetic runtime model (the targets
-    of the gain test), which is what a user of the method ranks with. A
-    trained network predicts near-equal runtimes for variants whose true
-    runtimes are near-equal (e.g. launch shapes of a memory-bound kernel), so
-    lower-precision picks can differ from the float64 pick among near-ties;
-    the gap between the two picks under the oracle's own prediction says
-    what such a disagreement costs."""
-    import oracle
-    from oracle import cost
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    rows = workload.sample_rows(vd.shape[0], 131072, 4300)
-    f, inv = oracle.featurize(kd, vd[rows])
-    f = f[inv == 0]
-    mu, sd = oracle.zscore_fit(f)
-    y = cost.target(f, workload.noise(f.shape[0], 4301))
-    m = adv.Model(widths, "bf16")
-    m.set_params(workload.he_init(widths, 4302), mu, sd)
-    F, Y = to_dev(f), to_dev(y)
-    rng = np.random.default_rng(4303)
-    loss = None
-    for _ in range(400):
-        idx = torch.from_numpy(rng.integers(0, f.shape[0], 8192)).to(F.device)
-        loss, _ = adv.advisor_train_step(m.handle, F[idx].contiguous(), Y[idx].contiguous(),
-                                         lr=2e-3)
-    w, _, _ = m.get_params()
-    final_loss = float(loss.item())
-    m.close()
-    nk = off.size - 1
-    n_sample = int(min(nk, max(8, seconds / max(per_variant * (off[-1] / nk), 1e-9))))
-    ks, rws, sub_off = workload.sample_kernels(off, n_sample, 4304)
-    vsub = vd[rws].copy()
-    vsub[:, 0] = np.repeat(np.arange(ks.size), sub_off[1:] - sub_off[:-1])
-    best_cpu, pred_cpu = oracle.rank(kd[ks], vsub, sub_off, widths, w.astype(np.float64), mu,
-                                     sd, n_threads=threads, want_pred=True)
-    K, V, O = to_dev(kd[ks]), to_dev(vsub), to_dev(sub_off)
-    agree, regret = {}, {}
-    has = best_cpu >= 0
-    hi = adv.Model(widths, "fp32")
-    hi.set_params(w, mu, sd)
-    for p in precs:
-        g = adv.Model(widths, p)
-        g.set_params(w, mu, sd)
-        if p == "fp8":
-            g.calibrate_fp8(F)
-        picks = {p: g.rank(K, V, O).cpu().numpy()}
-        rk = refine_k_for(p, refine_k)
-        if p != "fp32" and rk > 0:
-            picks[p + "_refined"] = g.rank_refined(hi, K, V, O, top_k=rk).cpu().numpy()
-            if p == "fp8":
-                mid = adv.Model(widths, "bf16")
-                mid.set_params(w, mu, sd)
-                picks["fp8_refined_bf16"] = g.rank_refined(mid, K, V, O, top_k=rk).cpu().numpy()
-                mid.close()
-        g.close()
-        for name, best_gpu in picks.items():
-            agree[name] = float(np.mean(best_gpu == best_cpu))
-            # how much worse the GPU's pick is by the oracle's own prediction
-            # (ln us): a disagreement between near-tied variants costs ~0
-            gap = pred_cpu[best_gpu[has]] - pred_cpu[best_cpu[has]]
-            regret[name] = {"mean": float(gap.mean()), "max": float(gap.max()),
-                            "frac_below_0.01": float(np.mean(gap < 0.01))}
-    hi.close()
-    return agree, {"train_steps": 400, "batch": 8192, "final_loss": final_loss,
-                   "sample_kernels": int(ks.size), "sample_variants": int(rws.size),
-                   "pick_gap_ln_us_by_oracle_prediction": regret,
-                   "top2_gap_ln_us_histogram": top2_gap_histogram(pred_cpu, best_cpu, sub_off)}
-
-
-def top2_gap_histogram(pred, best, off):
-    """Per kernel, the oracle's margin between its best and second-best
-    variant (ln us): how many kernels a low-precision ranking can only get
-    right by resolving a near-tie. Counts per bin [lo, hi)."""
-    edges = [0.0, 1e-6, 1e-4, 1e-3, 1e-2, 1e-1, np.inf]
-    gaps = []
-    for k in range(off.size - 1):
-        if best[k] < 0 or off[k + 1] - off[k] < 2:
-            continue
-        seg = pred[off[k]:off[k + 1]]
-        seg = seg[np.isfinite(seg)]
-        if seg.size < 2:
-            continue
-        two = np.partition(seg, 1)[:2]
-        gaps.append(float(two[1] - two[0]))
-    counts, _ = np.histogram(np.asarray(gaps), bins=edges)
-    names = ["0", "<1e-6", "<1e-4", "<1e-3", "<1e-2", "<1e-1", ">=1e-1"]
-    exact0 = int(np.sum(np.asarray(gaps) == 0.0))
-    out = {"exact_tie": exact0}
-    out.update({n: int(c) for n, c in zip(names[1:], counts)})
-    out["<1e-6"] -= exact0  # the first bin [0, 1e-6) includes the exact ties
-    return out
-
-
-def refine_k_for(precision, requested):
-    """Candidates per kernel for the fp32 re-ranking: 8 after bf16, 16 after
-    fp8 (fp8's 3-bit mantissas scatter near-tied predictions further)."""
-    if requested is not None:
-        return requested
-    return {"bf16": 8, "fp8": 16}.get(precision, 0)
 
 
 def train_flops_per_sample(widths):
@@ -465,30 +317,189 @@ def train_bytes_per_step(widths, batch, m_params):
     return int(per_row * batch + partials + optimizer)
 
 
+def stored_picks(cfg, kd, vd, off, params):
+    """The oracle's picks stored for this workload (None if absent or if
+    they were computed on other inputs)."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_picks_cfg%d.npz" % cfg)
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        gold = {k: z[k] for k in z.files}
+    if bytes(gold["digest"]).decode() != workload.inputs_digest(kd, vd, off, params):
+        return None
+    return gold
+
+
+def time_calls(torch, fn, steps, warmup):
+    """Mean milliseconds per call over exactly `steps` calls bracketed by
+    device synchronization, and p10/p50/p90 of per-call durations from
+    events recorded between the calls (torch's current stream, which the
+    library enqueues on)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return (t1 - t0) * 1e3 / steps, {q: float(np.percentile(per, int(q[1:])))
+                                     for q in ("p10", "p50", "p90")}
+
+
+def tile_kernel_ms(adv, torch, model, kdd, vdd, offd, best, pred, steps):
+    """Average duration of the fused tile kernel as a cascade's first stage
+    launches it (advisor_rank writing every prediction): HIP events recorded
+    around each launch on its stream by the library's profiling aid."""
+    model.rank(kdd, vdd, offd, best_out=best, pred_out=pred)
+    torch.cuda.synchronize()
+    adv.advisor_profile_enable(True)
+    for _ in range(steps):
+        model.rank(kdd, vdd, offd, best_out=best, pred_out=pred)
+    torch.cuda.synchronize()
+    launches, total = adv.advisor_profile_read()
+    adv.advisor_profile_enable(False)
+    return total / max(launches, 1), launches
+
+
+def run_workload(adv, torch, d, cfg, steps, warmup, paths=None):
+    """Every ranking path of PATHS[cfg] on one workload: time, agreement
+    with the stored oracle picks, and the tile kernels' own durations."""
+    kd, vd, off, params, widths = make_inputs(cfg)
+    nv, nk = vd.shape[0], off.size - 1
+    gold = stored_picks(cfg, kd, vd, off, params)
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(d)
+    kdd, vdd, offd = T(kd), T(vd), T(off)
+    # Z-score statistics (and fp8 activation scales) from the workload's
+    # seeded calibration sample, fitted by the library
+    cal = T(workload.calibration_rows(cfg, nv))
+    feat_cal, inv_cal = adv.advisor_featurize(kdd, vdd[cal])
+    feat_cal = feat_cal[inv_cal == 0].contiguous()
+    mu_d, sd_d = adv.advisor_zscore_fit(feat_cal)
+    mu, sd = mu_d.cpu().numpy(), sd_d.cpu().numpy()
+    paths = paths or PATHS[cfg]
+    models, tiles = {}, {}
+    best = torch.empty(nk, dtype=torch.int64, device=d)
+    pred = torch.empty(nv, dtype=torch.float32, device=d)
+    fl = sum(layer_flops(widths))
+    for p in sorted({p for precs, _ in paths.values() for p in precs}):
+        m = adv.Model(widths, p)
+        m.set_params(params, mu, sd)
+        if p == "fp8":
+            m.calibrate_fp8(feat_cal)
+        # one fp32 call on the 1024-wide network takes about a second: its
+        # tile shape is not tuned there
+        if not (p == "fp32" and widths[1] >= 1024):
+            shape, shape_ms = adv.advisor_autotune(m.handle, kdd, vdd, offd, reps=3)
+        else:
+            shape, shape_ms = adv.advisor_model_get_tile_variant(m.handle), []
+        kms, launches = tile_kernel_ms(adv, torch, m, kdd, vdd, offd, best, pred,
+                                       2 if p == "fp32" and widths[1] >= 1024 else 10)
+        tiles[p] = {"kernel_ms": kms, "launches": launches, "tile_shape": shape,
+                    "autotune_ms": [round(t, 4) for t in shape_ms[:4]],
+                    "tflops": fl * nv / (kms / 1e3) / 1e12,
+                    "roofline_frac": fl * nv / (kms / 1e3) / 1e12 / roofline_peak(widths, p),
+                    "mfma_peak_measured": adv.advisor_mfma_peak(p, iters=100000)}
+        models[p] = m
+    del feat_cal, inv_cal, pred
+    results = {}
+    for name, (precs, keep) in paths.items():
+        ms_ = [models[p] for p in precs]
+        slow = "fp32" == precs[0] and widths[1] >= 512
+        n = 3 if slow else steps
+        ms, pct = time_calls(torch, lambda: ms_[0].rank_cascade(ms_[1:], keep, kdd, vdd, offd,
+                                                                best_out=best),
+                             n, 1 if slow else warmup)
+        picks = best.cpu().numpy()
+        r = {"stages": list(precs), "keep": list(keep), "ms_per_step": ms, "steps": n,
+             "value": nv / (ms / 1e3), "step_ms": pct}
+        if gold is not None:
+            ks = gold["kernels"]
+            r["argmin_agreement"] = float(np.mean(picks[ks] == gold["best"]))
+            miss = picks[ks] != gold["best"]
+            r["misses_oracle_margin_below_1e-2"] = int(np.sum(miss & (gold["margin"] < 1e-2)))
+        results[name] = r
+        say("cfg %d %-22s %9.3f ms  %.3e variants/s  agreement %s"
+            % (cfg, name, ms, nv / (ms / 1e3), r.get("argmin_agreement")))
+    ok = [n for n, r in results.items() if r.get("argmin_agreement", 0.0) >= AGREEMENT_BAR]
+    head = min(ok, key=lambda n: results[n]["ms_per_step"]) if ok else "fp32"
+    return dict(kd=kd, vd=vd, off=off, kdd=kdd, vdd=vdd, offd=offd, params=params, mu=mu, sd=sd,
+                widths=widths, models=models, results=results, tiles=tiles, head=head, best=best,
+                gold=gold)
+
+
+def workload_summary(cfg, w):
+    """The per-workload part of the JSON line."""
+    gold = w["gold"]
+    return {"workload": WORKLOAD_NAME[cfg], "n_kernels": int(w["off"].size - 1),
+            "n_variants": int(w["vd"].shape[0]), "widths": list(w["widths"]),
+            "headline_path": w["head"],
+            "agreement_sample": None if gold is None else
+            "oracle picks on %d seeded whole kernels (tests/golden/oracle_picks_cfg%d.npz)"
+            % (gold["kernels"].size, cfg),
+            "paths": w["results"], "tile_kernels": w["tiles"]}
+
+
+def cpu_baseline_leg(kd, vd, off, widths, params, mu, sd, seconds):
+    """The float64 oracle (as written, parallel over kernels) on a seeded
+    sample of whole kernels sized to about `seconds` of CPU time."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    p64 = params.astype(np.float64)
+
+    def run(n_kernels, seed):
+        ks, rows, sub_off = workload.sample_kernels(off, n_kernels, seed)
+        vsub = vd[rows].copy()
+        vsub[:, 0] = np.repeat(np.arange(ks.size), sub_off[1:] - sub_off[:-1])
+        t0 = time.perf_counter()
+        oracle.rank(kd[ks], vsub, sub_off, widths, p64, mu, sd, n_threads=threads,
+                    want_pred=False)
+        return ks, rows.size, time.perf_counter() - t0
+
+    nk = off.size - 1
+    probe = min(nk, max(1, 2 * threads))
+    _, nv_probe, dt_probe = run(probe, 4242)
+    per_variant = dt_probe / max(nv_probe, 1)
+    n_sample = int(min(nk, max(probe, seconds / max(per_variant * off[-1] / nk, 1e-9))))
+    ks, nv_s, dt = run(n_sample, 4243)
+    return {"value": nv_s / dt, "unit": "variants/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d kernels (seeded), %d variants, %.1f s wall"
+                      % (ks.size, nk, nv_s, dt)}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
-    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=5, choices=[2, 3, 5],
+                    help="workload: 2 = 4096 kernels, 2.1M variants, 32-256x3-1; 3 = 16384 "
+                         "kernels, 8.9M variants, 32-512x4-1; 5 = 32768 kernels, 18.9M "
+                         "variants, 32-1024x4-1 (default)")
     ap.add_argument("--also", default=None,
-                    help="comma-separated extra precisions timed on the same inputs ('' for none; "
-                         "default: the other two of fp32, bf16 and fp8 that the workload's "
-                         "network has, i.e. bf16 for the 256-wide network, fp32 for the "
-                         "512-wide one, bf16 and fp32 for the 1024-wide one)")
+                    help="comma-separated further workloads measured the same way (default: 3 "
+                         "beside 5, none otherwise; '' for none)")
+    ap.add_argument("--paths", default=None,
+                    help="comma-separated subset of the ranking paths of the main workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--train-steps", type=int, default=20,
                     help="timed training steps (batch 65536, bf16 32-512x4-1); 0 to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--refine-k", type=int, default=None,
-                    help="also time bf16/fp8 ranking refined by an fp32 model on each kernel's "
-                         "top-k candidates (advisor_rank_refined; default 8 for bf16, 16 for "
-                         "fp8); 0 to skip")
     ap.add_argument("--no-transfers", dest="transfers", action="store_false",
                     help="skip the leg that hands the descriptors over in pinned host memory")
     ap.add_argument("--no-stages", dest="stages", action="store_false",
-                    help="skip timing advisor_featurize and advisor_rank_preds alone")
+                    help="skip timing advisor_featurize, advisor_rank_preds and the method's "
+                         "integer steps alone")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the "
                          "HBM byte counters of a profiler run) and exit")
@@ -516,155 +527,76 @@ def main():
                           "launches": 3}), flush=True)
         return
     cfg = args.config
-    prec = args.precision or DEFAULT_PRECISION[cfg]
-    kd, vd, off, params, widths = make_inputs(cfg)
-    nv, nk = vd.shape[0], off.size - 1
-
-    def T(a):
-        return torch.from_numpy(np.ascontiguousarray(a)).to(d)
-    kdd, vdd, offd = T(kd), T(vd), T(off)
-    # Z-score statistics from a seeded calibration sample, fitted on the GPU
-    cal = T(workload.sample_rows(nv, 65536, workload.seeds(cfg)["desc"] + 7))
-    feat_cal, inv_cal = adv.advisor_featurize(kdd, vdd[cal])
-    feat_cal = feat_cal[inv_cal == 0].contiguous()
-    mu_d, sd_d = adv.advisor_zscore_fit(feat_cal)
-    mu, sd = mu_d.cpu().numpy(), sd_d.cpu().numpy()
-
-    results = {}
-    best_by_prec = {}
-    also = args.also if args.also is not None else DEFAULT_ALSO[cfg]
-    precs = [prec] + [p for p in also.split(",") if p and p != prec]
-    for p in precs:
-        m = adv.Model(widths, p)
-        m.set_params(params, mu, sd)
-        if p == "fp8":
-            m.calibrate_fp8(feat_cal)
-        # tile shape chosen by the library's autotuner on this workload
-        shape, shape_ms = adv.advisor_autotune(m.handle, kdd, vdd, offd, reps=3)
-        best = torch.empty(nk, dtype=torch.int64, device=d)
-        ms, kern_ms, launches, pct = time_rank(adv, torch, m, kdd, vdd, offd, best,
-                                               args.steps if p == prec else max(5, args.steps // 2),
-                                               args.warmup)
-        best_by_prec[p] = best.cpu().numpy()
-        fl = sum(layer_flops(widths))
-        results[p] = dict(ms_per_step=ms, kernel_ms=kern_ms, launches=launches,
-                          value=nv / (ms / 1e3), replay_ms=pct,
-                          tflops=fl * nv / (kern_ms / 1e3) / 1e12,
-                          tile_shape=shape, tune_ms=[round(t, 4) for t in shape_ms[:4]],
-                          mfma_peak_measured=adv.advisor_mfma_peak(p, iters=100000))
-        if p == prec and args.transfers:
-            results[p]["with_transfers"] = time_with_transfers(
-                adv, torch, m, kd, vd, off, kdd, vdd, offd, best, max(5, args.steps // 2),
-                args.warmup)
-        # the prediction flow's top-10 list per kernel (fused pass + top-N), eager calls
-        tidx = torch.empty((nk, 10), dtype=torch.int64, device=d)
-        tval = torch.empty((nk, 10), dtype=torch.float32, device=d)
-        nsteps = args.steps if p == prec else max(5, args.steps // 2)
-        for _ in range(args.warmup):
-            m.rank_topn(kdd, vdd, offd, 10, idx_out=tidx, val_out=tval)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(nsteps):
-            m.rank_topn(kdd, vdd, offd, 10, idx_out=tidx, val_out=tval)
-        torch.cuda.synchronize()
-        tms = (time.perf_counter() - t0) * 1e3 / nsteps
-        results[p]["top10"] = dict(ms_per_step=tms, value=nv / (tms / 1e3),
-                                   head_equals_argmin=bool(torch.equal(tidx[:, 0], best)))
-        del tidx, tval
-        rk = refine_k_for(p, args.refine_k)
-        if p != "fp32" and rk > 0:
-            # the same ranking with each kernel's top-k re-ranked in fp32 (eager calls)
-            hi = adv.Model(widths, "fp32")
-            hi.set_params(params, mu, sd)
-            bref = torch.empty(nk, dtype=torch.int64, device=d)
-            nsteps = args.steps if p == prec else max(5, args.steps // 2)
-            for _ in range(args.warmup):
-                m.rank_refined(hi, kdd, vdd, offd, top_k=rk, best_out=bref)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(nsteps):
-                m.rank_refined(hi, kdd, vdd, offd, top_k=rk, best_out=bref)
-            torch.cuda.synchronize()
-            rms = (time.perf_counter() - t0) * 1e3 / nsteps
-            best_by_prec[p + "_refined"] = bref.cpu().numpy()
-            results[p]["refined"] = dict(top_k=rk, ms_per_step=rms, value=nv / (rms / 1e3))
-            hi.close()
-            if p == "fp8":
-                # the cheaper second stage: the fp8 model's top-k re-ranked in bf16
-                mid = adv.Model(widths, "bf16")
-                mid.set_params(params, mu, sd)
-                for _ in range(args.warmup):
-                    m.rank_refined(mid, kdd, vdd, offd, top_k=rk, best_out=bref)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(nsteps):
-                    m.rank_refined(mid, kdd, vdd, offd, top_k=rk, best_out=bref)
-                torch.cuda.synchronize()
-                rms = (time.perf_counter() - t0) * 1e3 / nsteps
-                best_by_prec["fp8_refined_bf16"] = bref.cpu().numpy()
-                results[p]["refined_bf16"] = dict(top_k=rk, ms_per_step=rms, value=nv / (rms / 1e3))
-                mid.close()
-        m.close()
-    del feat_cal, inv_cal
-
-    main_r = results[prec]
-    peak = roofline_peak(widths, prec)
-    traffic = stored_traffic(cfg, prec)
+    paths = None
+    if args.paths:
+        paths = {n: PATHS[cfg][n] for n in args.paths.split(",")}
+    w = run_workload(adv, torch, d, cfg, args.steps, args.warmup, paths)
+    head = w["head"]
+    hr = w["results"][head]
+    first = hr["stages"][0]
+    widths = w["widths"]
+    nv = int(w["vd"].shape[0])
+    tk = w["tiles"][first]
+    fl = sum(layer_flops(widths))
+    peak = roofline_peak(widths, first)
+    traffic = stored_traffic(cfg, first)
     out = {
         "metric": "variants ranked/sec (featurize+MLP+argmin), BF16/FP8 vs FP32 at argmin agreement",
-        "value": main_r["value"],
+        "value": hr["value"],
         "unit": "variants/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": hr["steps"],
         "warmup": args.warmup,
-        "ms_per_step": main_r["ms_per_step"],
+        "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[prec],
+        "dtype": "+".join(DTYPE[p] for p in hr["stages"]),
         "data": "synthetic (seeded descriptors and He-init weights)",
-        "config": {"workload": WORKLOAD_NAME[cfg], "n_kernels": nk, "n_variants": nv,
-                   "widths": list(widths), "precision": prec},
-        "roofline": {"bound": "mfma", "achieved": main_r["tflops"], "peak": round(peak, 1),
-                     "unit": "TFLOP/s", "frac": main_r["tflops"] / peak,
+        "config": dict(workload_summary(cfg, w), path=head, stages=hr["stages"], keep=hr["keep"],
+                       argmin_agreement=hr.get("argmin_agreement"),
+                       agreement_bar=AGREEMENT_BAR),
+        "roofline": {"bound": "mfma", "achieved": fl * nv / (tk["kernel_ms"] / 1e3) / 1e12,
+                     "peak": round(peak, 1), "unit": "TFLOP/s",
+                     "frac": fl * nv / (tk["kernel_ms"] / 1e3) / 1e12 / peak,
                      "traffic": traffic,
-                     "kernel": "mlp_tiles_kernel (fused featurize+MLP+argmin)",
-                     "kernel_ms": main_r["kernel_ms"],
-                     "flops_per_variant": sum(layer_flops(widths)),
-                     "replay_ms": main_r["replay_ms"],
-                     "mfma_peak_measured": main_r["mfma_peak_measured"]},
+                     "kernel": "mlp_tiles_kernel %s (fused featurize+MLP+argmin, first stage of "
+                               "the headline path)" % first,
+                     "kernel_ms": tk["kernel_ms"], "flops_per_variant": fl,
+                     "variants_per_launch": nv,
+                     "mfma_peak_measured": tk["mfma_peak_measured"]},
+        "value_p10_p50_p90": [nv / (hr["step_ms"][q] / 1e3) for q in ("p90", "p50", "p10")],
     }
-    # variants/s per replay: p10 of the rate is the p90 of the duration
-    out["value_p10_p50_p90"] = [nv / (main_r["replay_ms"][q] / 1e3) for q in ("p90", "p50", "p10")]
-    if "with_transfers" in main_r:
-        out["with_transfers"] = main_r["with_transfers"]
+    # the plain fp32 GPU path on the same inputs, and the gain over it
+    if "fp32" in w["results"]:
+        out["fp32_path"] = {"value": w["results"]["fp32"]["value"],
+                            "speedup_of_headline": hr["value"] / w["results"]["fp32"]["value"]}
+    if args.transfers:
+        ms_ = [w["models"][p] for p in hr["stages"]]
+        out["with_transfers"] = time_with_transfers(
+            torch, lambda: ms_[0].rank_cascade(ms_[1:], hr["keep"], w["kdd"], w["vdd"], w["offd"],
+                                               best_out=w["best"]),
+            w["kd"], w["vd"], w["off"], w["kdd"], w["vdd"], w["offd"], w["best"],
+            max(3, args.steps // 4), 1)
     if args.stages:
-        out["stages"] = stage_kernels(adv, torch, kdd, vdd, offd, max(5, args.steps // 2))
-    agree_t = {}
+        out["stages"] = stage_kernels(adv, torch, w["kdd"], w["vdd"], w["offd"],
+                                      max(5, args.steps // 2))
     if not args.no_cpu_baseline:
-        cb, agree, per_variant = cpu_baseline_leg(kd, vd, off, widths, params, mu, sd,
-                                                  args.cpu_seconds, best_by_prec)
-        agree_t, tinfo = trained_agreement(adv, torch, T, kd, vd, off, widths, list(results),
-                                           per_variant, args.cpu_seconds / 2, args.refine_k)
-        cb["argmin_agreement_trained_network"] = dict(agree_t, **tinfo)
-        out["cpu_baseline"] = cb
-    else:
-        agree = {}
-    out["precisions"] = {
-        p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
-            "tflops": r["tflops"], "roofline_frac": r["tflops"] / roofline_peak(widths, p),
-            "tile_shape": r["tile_shape"], "autotune_ms": r["tune_ms"],
-            "replay_ms": r["replay_ms"], "mfma_peak_measured": r["mfma_peak_measured"],
-            "top10": r.get("top10"),
-            "argmin_agreement_vs_oracle_sample": agree.get(p),
-            "argmin_agreement_trained_network": agree_t.get(p),
-            "refined_by_fp32": None if "refined" not in r else dict(
-                r["refined"], argmin_agreement_vs_oracle_sample=agree.get(p + "_refined"),
-                argmin_agreement_trained_network=agree_t.get(p + "_refined")),
-            "refined_by_bf16": None if "refined_bf16" not in r else dict(
-                r["refined_bf16"], argmin_agreement_vs_oracle_sample=agree.get(p + "_refined_bf16"),
-                argmin_agreement_trained_network=agree_t.get(p + "_refined_bf16"))}
-        for p, r in results.items()}
+        out["cpu_baseline"] = cpu_baseline_leg(w["kd"], w["vd"], w["off"], widths, w["params"],
+                                               w["mu"], w["sd"], args.cpu_seconds)
+    for m in w["models"].values():
+        m.close()
+    del w
+    torch.cuda.empty_cache()
+    also = args.also if args.also is not None else ("3" if cfg == 5 else "")
+    out["also"] = {}
+    for c in [int(x) for x in also.split(",") if x]:
+        wa = run_workload(adv, torch, d, c, args.steps, args.warmup)
+        out["also"][str(c)] = workload_summary(c, wa)
+        for m in wa["models"].values():
+            m.close()
+        del wa
+        torch.cuda.empty_cache()
     if args.train_steps > 0:
         out["train"] = train_leg(adv, torch, d, args.train_steps, args.warmup)
     print(json.dumps(out), flush=True)
