@@ -54,3 +54,23 @@ def segment_argmin(pred, offsets):
     first[1:] = s[1:] != s[:-1]
     best[s[first]] = idx[first]
     return best
+
+
+def elementwise_grad_err(g, g_ref, widths):
+    """Worst element-by-element error of a gradient, per weight matrix and
+    bias vector: max |g - r| / max(|r|, s), where s is the RMS of the
+    reference entries of that matrix or vector (the floor keeps entries that
+    cancel to nearly 0 from demanding a relative accuracy no summation order
+    gives them). Returns the worst ratio over all parts."""
+    g = np.asarray(g, np.float64)
+    worst, off = 0.0, 0
+    for i in range(len(widths) - 1):
+        for k in (widths[i + 1] * widths[i], widths[i + 1]):
+            r = g_ref[off:off + k]
+            s = float(np.sqrt(np.mean(r * r)))
+            if s > 0.0:
+                worst = max(worst, float(np.max(np.abs(g[off:off + k] - r) / np.maximum(np.abs(r), s))))
+            else:
+                assert np.all(g[off:off + k] == 0.0)
+            off += k
+    return worst

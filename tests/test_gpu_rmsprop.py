@@ -11,7 +11,7 @@ import torch
 import oracle
 import paper_2301_03636_amd as adv
 import workload
-from gpu_util import host, say, to_dev
+from gpu_util import elementwise_grad_err, host, say, to_dev
 from oracle import cost
 
 pytestmark = pytest.mark.gpu
@@ -60,6 +60,7 @@ def test_rmsprop_step_fp32_matches_oracle(loss):
     say("rmsprop %s: loss %.6f ref %.6f, rel grad err %.2e" % (loss, lo, l_ref, _rel(g, g_ref)))
     assert abs(lo - l_ref) / l_ref <= 1e-5
     assert _rel(g, g_ref) <= 1e-4
+    assert elementwise_grad_err(g, g_ref, widths) <= 2e-3
     assert abs(gn - np.linalg.norm(g.astype(np.float64))) <= 1e-6 * gn
     assert t == 0  # Adam's step count is not RMSprop's business
     # the update, in float64 on the gradient the GPU used
