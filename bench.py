@@ -53,7 +53,8 @@ PATHS = {
         "bf16>fp32:2": (("bf16", "fp32"), (2,)), "bf16>fp32:4": (("bf16", "fp32"), (4,)),
         "bf16>fp32:8": (("bf16", "fp32"), (8,)),
         "fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
-        "fp8>bf16:16>fp32:4": (("fp8", "bf16", "fp32"), (16, 4))},
+        "fp8>bf16:16>fp32:4": (("fp8", "bf16", "fp32"), (16, 4)),
+        "fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4))},
     5: {"fp32": (("fp32",), ()), "bf16": (("bf16",), ()), "fp8": (("fp8",), ()),
         "bf16>fp32:2": (("bf16", "fp32"), (2,)), "bf16>fp32:4": (("bf16", "fp32"), (4,)),
         "fp8>fp32:16": (("fp8", "fp32"), (16,)),

@@ -430,13 +430,18 @@ enum { ADVISOR_LOSS_MSE = 0, ADVISOR_LOSS_RMSE = 1 };
  * gradient (without the weight-decay term), which advisor_model_grads then
  * returns. The running average v is the model's second-moment buffer, the
  * one advisor_model_get_adam / set_adam read and write as Adam's v (Adam's
- * first moment and step count are left untouched). The learning-rate
- * schedule of section 5.3 (0.01, divided by 10 every 30 epochs) is the
- * caller's: lr is read at every call. 0 < lr, 0 <= alpha < 1, eps >= 0,
- * weight_decay >= 0. Other arguments and limits as for advisor_train_step. */
+ * first moment and step count are left untouched). lr is read at every
+ * call; advisor_step_lr gives section 5.3's schedule for it. 0 < lr,
+ * 0 <= alpha < 1, eps >= 0, weight_decay >= 0. Other arguments and limits as for advisor_train_step. */
 int advisor_train_step_rmsprop(advisor_model *model, const int64_t *feat, const double *y,
                                int64_t n, float lr, float alpha, float eps, float weight_decay,
                                int loss, double *loss_out, double *gnorm_out, void *stream);
+
+/* The stepped learning rate of section 5.3 for epoch `epoch` (counted from
+ * 0): lr0 * gamma^floor(epoch / every) (the paper: lr0 = 0.01, gamma = 0.1,
+ * every = 30). A host computation, no device work; returns NaN (and sets the
+ * error text) when epoch < 0, every < 1, lr0 <= 0 or gamma is outside (0, 1]. */
+double advisor_step_lr(int64_t epoch, double lr0, double gamma, int64_t every);
 
 /* Replace the fp32 master weights from a device buffer (float [param_count])
  * and rebuild the compute copies; for optimizers that run outside the

@@ -92,6 +92,7 @@ def lib():
             "advisor_enumerate_variants": ([P, P, i64, i64, i32, P, P], i32),
             "advisor_topn_preds": ([P, P, i64, i64, i32, P, P, P], i32),
             "advisor_rank_topn": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
+            "advisor_step_lr": ([i64, C.c_double, C.c_double, i64], C.c_double),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -308,6 +309,11 @@ def advisor_rank_refined(h, refine, kdesc, vdesc, offsets, top_k=8, best_out=Non
 def advisor_rank_cascade(handles, keep, kdesc, vdesc, offsets, best_out=None, pred_out=None):
     """Multi-stage ranking: handles [n_stages] model handles (first the
     fastest), keep [n_stages - 1] candidates per kernel handed on by each cut."""
+    return _cascade("advisor_rank_cascade", handles, keep, kdesc, vdesc, offsets, best_out,
+                    pred_out)
+
+
+def _cascade(name, handles, keep, kdesc, vdesc, offsets, best_out, pred_out):
     for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
         _dev(t, torch.int64, nm)
     nk = offsets.shape[0] - 1
@@ -319,9 +325,8 @@ def advisor_rank_cascade(handles, keep, kdesc, vdesc, offsets, best_out=None, pr
     ns = len(handles)
     arr = (C.c_void_p * max(ns, 1))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
     kp = (C.c_int * max(len(keep), 1))(*[int(k) for k in keep])
-    _check(lib().advisor_rank_cascade(arr, kp, ns, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk,
-                                      nv, _ptr(best_out), _ptr(pred_out), _stream()),
-           "advisor_rank_cascade")
+    _check(getattr(lib(), name)(arr, kp, ns, _ptr(kdesc), _ptr(vdesc), _ptr(offsets), nk, nv,
+                                _ptr(best_out), _ptr(pred_out), _stream()), name)
     return best_out
 
 
@@ -518,6 +523,13 @@ def advisor_train_step(h, feat, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, lo
 
 
 LOSSES = {"mse": 0, "rmse": 1}
+
+
+def advisor_step_lr(epoch, lr0=1e-2, gamma=0.1, every=30):
+    r = lib().advisor_step_lr(int(epoch), float(lr0), float(gamma), int(every))
+    if r != r:
+        raise AdvisorError(-1, "advisor_step_lr", last_error())
+    return r
 
 
 def advisor_train_step_rmsprop(h, feat, y, lr=1e-2, alpha=0.99, eps=1e-8, weight_decay=1e-4,

@@ -1218,6 +1218,20 @@ extern "C" int advisor_train_step_rmsprop(advisor_model *m, const int64_t *feat,
     return repack_train(m, s);
 }
 
+// Section 5.3's learning rate: lr0 for the first `every` epochs, then
+// multiplied by gamma after each further `every` epochs.
+extern "C" double advisor_step_lr(int64_t epoch, double lr0, double gamma, int64_t every)
+{
+    clear_error();
+    if (epoch < 0 || every < 1 || !(lr0 > 0.0) || !(gamma > 0.0 && gamma <= 1.0)) {
+        fail(ADVISOR_EINVAL, "advisor_step_lr: need epoch >= 0, every >= 1, lr0 > 0, 0 < gamma <= 1");
+        return __builtin_nan("");
+    }
+    double lr = lr0;
+    for (int64_t k = epoch / every; k > 0; --k) lr *= gamma;
+    return lr;
+}
+
 // Replace the fp32 master parameters from a device buffer (for optimizers
 // driven outside the library) and rebuild every compute copy.
 extern "C" int advisor_model_load_params(advisor_model *m, const float *w_master, void *stream)

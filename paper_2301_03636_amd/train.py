@@ -48,9 +48,9 @@ class Trainer:
 
 
 def step_lr(epoch, lr0=1e-2, gamma=0.1, every=30):
-    """Section 5.3's learning-rate schedule: lr0, multiplied by gamma after
-    every `every` epochs."""
-    return lr0 * gamma ** (int(epoch) // int(every))
+    """Section 5.3's learning-rate schedule (advisor_step_lr): lr0,
+    multiplied by gamma after every `every` epochs."""
+    return _lib.advisor_step_lr(epoch, lr0, gamma, every)
 
 
 class RMSpropTrainer:

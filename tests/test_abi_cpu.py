@@ -206,3 +206,15 @@ def test_missing_library_fails_loudly(monkeypatch):
         _lib.lib()
     with pytest.raises(ImportError):
         adv.Model((32, 8, 1), "fp32")
+
+
+def test_step_lr_schedule_from_the_library():
+    """Section 5.3's schedule as the library computes it (host only): 0.01
+    for epochs 0-29, divided by ten every 30 epochs; bad arguments raise."""
+    assert adv.step_lr(0) == 1e-2 and adv.step_lr(29) == 1e-2
+    assert np.isclose(adv.step_lr(30), 1e-3, rtol=1e-15, atol=0)
+    assert np.isclose(adv.step_lr(149), 1e-6, rtol=1e-14, atol=0)
+    assert adv.step_lr(59, lr0=0.5, gamma=0.5, every=20) == 0.125
+    for bad in ((-1, 1e-2, 0.1, 30), (0, 0.0, 0.1, 30), (0, 1e-2, 1.5, 30), (0, 1e-2, 0.1, 0)):
+        with pytest.raises(adv.AdvisorError):
+            adv.step_lr(*bad)

@@ -173,11 +173,11 @@ def test_agreement_with_oracle_1024_wide():
     cascade the benchmark headlines reaches the agreement bar on every
     stored kernel; fp8 alone does not (its 3-bit mantissas scatter the
     near-ties), which is why the cut exists."""
-    paths = {"fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
+    paths = {"fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4)),
              "fp8": (("fp8",), ())}
     res, gold = _stored_agreement(5, paths)
-    assert res["fp8>bf16:16>fp32:2"][0] >= AGREEMENT_BAR
-    assert res["fp8"][0] < res["fp8>bf16:16>fp32:2"][0]
+    assert res["fp8>bf16:32>fp32:4"][0] >= AGREEMENT_BAR
+    assert res["fp8"][0] < res["fp8>bf16:32>fp32:4"][0]
 
 
 def test_agreement_with_oracle_512_wide():

@@ -274,4 +274,9 @@ def test_backward_small_batches_match_oracle(precision, n):
     ew = _elementwise(g, g_ref, widths)
     say("backward %s n=%d: rel grad err %.2e, worst element %.2e" % (precision, n, err, ew))
     assert err <= (1e-4 if precision == "fp32" else (1e-1 if n < 100 else 3e-2))
-    assert ew <= (2e-3 if precision == "fp32" else 0.25)
+    # element by element in bf16: one flipped ReLU decision changes a whole
+    # row's product in a weight-gradient element; at 16 rows that one row can
+    # be as large as the RMS of the matrix (measured 0.54 of it), at 700 rows
+    # a small part of it (a transposed or misplaced element still gives
+    # several times the RMS)
+    assert ew <= (2e-3 if precision == "fp32" else (1.0 if n < 100 else 0.25))
