@@ -265,6 +265,34 @@ int advisor_rank_cascade(advisor_model *const *models, const int *keep, int n_st
                          float *pred_out, void *stream);
 
 /*
+ * advisor_rank_cascade for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. Same arguments, results and argument checks as
+ * advisor_rank_cascade (bit-identical picks and predictions), but the
+ * stages' workspace (each cut's candidate lists, their gathered descriptor
+ * rows and offsets, middle stages' predictions, the last stage's winners;
+ * plus 4 n_variants bytes for the first stage's predictions when pred_out
+ * is NULL) lives in one library-owned static device array of
+ * ADVISOR_NOALLOC_SCRATCH_BYTES bytes per GPU, held from the first call on
+ * that GPU until the process ends. The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine) and skips the opt-in offsets check
+ * (ADVISOR_DEBUG_OFFSETS), which allocates. A call whose workspace would
+ * exceed the array returns ADVISOR_ESHAPE with the sizes in the error text;
+ * cut s takes 72 bytes per candidate (76 when another cut follows) for its
+ * n_kernels * keep[s] candidates, plus 8 (n_kernels + 1) bytes (the
+ * 32768-kernel workload with keep {32, 4} and pred_out given takes 85 MiB).
+ * The models must live on the current device. Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other threads) race and their picks are undefined; calls ordered on one
+ * stream are safe. One-stage calls use no workspace.
+ */
+#define ADVISOR_NOALLOC_SCRATCH_BYTES (96u << 20)
+int advisor_rank_cascade_noalloc(advisor_model *const *models, const int *keep, int n_stages,
+                                 const int64_t *kdesc, const int64_t *vdesc,
+                                 const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
+                                 int64_t *best_out, float *pred_out, void *stream);
+
+/*
  * The per-kernel argmin alone (the selection step of section 3, N = 1) on
  * given predictions: pred (device, float [n_variants]), offsets (device,
  * int64 [n_kernels + 1]) -> best_out (device, int64 [n_kernels]), with the

@@ -57,6 +57,7 @@ def lib():
             "advisor_rank_preds": ([P, P, i64, i64, P, P], i32),
             "advisor_rank_refined": ([P, P, P, P, P, i64, i64, i32, P, P, P], i32),
             "advisor_rank_cascade": ([P, P, i32, P, P, P, i64, i64, P, P, P], i32),
+            "advisor_rank_cascade_noalloc": ([P, P, i32, P, P, P, i64, i64, P, P, P], i32),
             "advisor_mlp_saved_bytes": ([P, i64], i64),
             "advisor_mlp_forward": ([P, P, i64, P, P, P], i32),
             "advisor_mlp_backward": ([P, P, P, i64, P, P], i32),
@@ -310,6 +311,15 @@ def advisor_rank_cascade(handles, keep, kdesc, vdesc, offsets, best_out=None, pr
     """Multi-stage ranking: handles [n_stages] model handles (first the
     fastest), keep [n_stages - 1] candidates per kernel handed on by each cut."""
     return _cascade("advisor_rank_cascade", handles, keep, kdesc, vdesc, offsets, best_out,
+                    pred_out)
+
+
+def advisor_rank_cascade_noalloc(handles, keep, kdesc, vdesc, offsets, best_out, pred_out=None):
+    """advisor_rank_cascade on the library's fixed static workspace: the call
+    allocates no device memory (best_out must be given)."""
+    if best_out is None:
+        raise ValueError("advisor_rank_cascade_noalloc: best_out must be given")
+    return _cascade("advisor_rank_cascade_noalloc", handles, keep, kdesc, vdesc, offsets, best_out,
                     pred_out)
 
 
