@@ -232,6 +232,53 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
     return out
 
 
+def multi_target_leg(adv, torch, d, steps, warmup):
+    """Section 3 keeps one model per (cluster, GPU architecture); seven
+    targets (the clusters of table tab:advisor:cluster) rank the same
+    variants: the 4096-kernel, 2.1M-variant workload through seven
+    paper-sized networks (32-64-128-64-32-1, He-initialized, one seed each)
+    that share the workload's Z-score statistics, once as one
+    advisor_rank_multi call (grouped passes: each tile's input built once
+    for all seven) and once as seven advisor_rank calls. value = variants x
+    targets ranked per second."""
+    kd, vd, off, _, _ = make_inputs(2)
+    nv, nk = vd.shape[0], off.size - 1
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(d)
+    kdd, vdd, offd = T(kd), T(vd), T(off)
+    cal = T(workload.calibration_rows(2, nv))
+    fc, ic = adv.advisor_featurize(kdd, vdd[cal])
+    mu, sd = adv.advisor_zscore_fit(fc[ic == 0].contiguous())
+    mu, sd = mu.cpu().numpy(), sd.cpu().numpy()
+    widths = (32, 64, 128, 64, 32, 1)
+    out = {"workload": "4096 kernels x U[16,1024] variants (2.1M), 7 targets x 32-64-128-64-32-1",
+           "n_targets": 7, "n_variants": int(nv)}
+    for prec in ("fp32", "bf16"):
+        ms_ = []
+        for t in range(7):
+            m = adv.Model(widths, prec)
+            m.set_params(workload.he_init(widths, 2100 + t), mu, sd)
+            ms_.append(m)
+        best = torch.empty((7, nk), dtype=torch.int64, device=d)
+        hs = [m.handle for m in ms_]
+        g_ms, _ = time_calls(torch, lambda: adv.advisor_rank_multi(hs, kdd, vdd, offd,
+                                                                   best_out=best),
+                             steps, warmup)
+        g_best = best.cpu().numpy().copy()
+        s_ms, _ = time_calls(torch, lambda: [ms_[t].rank(kdd, vdd, offd, best_out=best[t])
+                                             for t in range(7)], steps, warmup)
+        out[prec] = {"grouped_ms": g_ms, "separate_ms": s_ms,
+                     "value": 7 * nv / (g_ms / 1e3), "unit": "variant-targets/s",
+                     "speedup_of_grouping": s_ms / g_ms,
+                     "rows_equal_separate_calls": bool(np.array_equal(g_best, best.cpu().numpy()))}
+        say("multi-target %s: grouped %.3f ms, separate %.3f ms (x%.2f)"
+            % (prec, g_ms, s_ms, s_ms / g_ms))
+        for m in ms_:
+            m.close()
+    return out
+
+
 def train_flops_per_sample(widths):
     """Forward, input gradients of every layer but the first, and weight
     gradients of every layer: 2 flops per multiply-add."""
@@ -496,6 +543,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=20,
                     help="timed training steps (batch 65536, bf16 32-512x4-1); 0 to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-multi", dest="multi", action="store_false",
+                    help="skip the seven-target leg (grouped advisor_rank_multi vs separate calls)")
     ap.add_argument("--no-transfers", dest="transfers", action="store_false",
                     help="skip the leg that hands the descriptors over in pinned host memory")
     ap.add_argument("--no-stages", dest="stages", action="store_false",
@@ -598,6 +647,8 @@ def main():
             m.close()
         del wa
         torch.cuda.empty_cache()
+    if args.multi:
+        out["multi_target"] = multi_target_leg(adv, torch, d, max(5, args.steps // 2), args.warmup)
     if args.train_steps > 0:
         out["train"] = train_leg(adv, torch, d, args.train_steps, args.warmup)
     print(json.dumps(out), flush=True)

@@ -208,7 +208,13 @@ int advisor_rank(const advisor_model *model, const int64_t *kdesc, const int64_t
  * row-major) receives target t's winners in row t; pred_out (device, float
  * [n_models, n_variants], may be NULL) its predictions. Models may differ
  * in widths and precision; all must live on the current device. Each row
- * equals advisor_rank with that model, bit for bit.
+ * equals advisor_rank with that model, bit for bit. Models that share the
+ * precision, the padded hidden width, the tile shape and the Z-score
+ * statistics (set from identical host values by advisor_model_set_params;
+ * the statistics describe the variants' features, which do not depend on
+ * the target) are evaluated in grouped passes of up to 8 models: each tile's
+ * descriptors are read, featurized and standardized once and every model's
+ * network runs on that input. Other models get a pass of their own.
  */
 int advisor_rank_multi(const advisor_model *const *models, int n_models, const int64_t *kdesc,
                        const int64_t *vdesc, const int64_t *offsets, int64_t n_kernels,

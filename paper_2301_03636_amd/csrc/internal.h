@@ -144,5 +144,11 @@ struct advisor_model {
     void *train_ws = nullptr;  // training workspace (train.hip), grown on demand
     void *refine_ws = nullptr; // refined-ranking workspace (refine.hip), grown on demand
     int tile_variant = 0;      // tile shape used by rank/predict (autotuned)
+    // host copies of the Z-score statistics when they were last set from
+    // host values (advisor_model_set_params, or the defaults 0 and 1);
+    // h_stats is false after advisor_model_set_zscore (device values)
+    double h_mu[ADVISOR_NFEAT] = {0};
+    double h_sigma[ADVISOR_NFEAT] = {0};
+    bool h_stats = false;
     bool wt_valid = false;     // transposed packs (backward) match the master weights
 };

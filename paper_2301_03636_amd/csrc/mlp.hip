@@ -1,6 +1,7 @@
 // Launch side of the fused tile pipeline: tile shapes per (precision,
 // width), kernel instances, the argmin-key set-up and read-out kernels, and
 // the advisor_predict / advisor_rank entry points.
+#include <cstring>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -79,7 +80,10 @@ template <int P, int W> struct TileShape<P, W, 3> {
 };
 constexpr int N_TILE_SHAPES = 4;
 
-template <class S, int P, int W, int SRC, int SINK, bool PP = S::PP> struct TileKernel {
+// (a grouped pass runs shape 3's rows and waves on mlp_tiles_kernel: the
+// same bits as the ping-pong kernel)
+template <class S, int P, int W, int SRC, int SINK, bool PP = S::PP && SINK != SINK_GROUP>
+struct TileKernel {
     static constexpr auto kern = mlp_tiles_kernel<P, W, S::M, S::NW, S::NS, SRC, SINK>;
 };
 template <class S, int P, int W, int SRC, int SINK> struct TileKernel<S, P, W, SRC, SINK, true> {
@@ -108,7 +112,8 @@ struct TileLaunch {
     static constexpr int M = S::M;
     static constexpr int NW = S::NW;
     static constexpr int NS = S::NS;
-    using C = TileCfg<P, W, M, NW, NS, SRC == SRC_DESC && tile_vdesc_prefetch<P, W, M, NW>()>;
+    using C = TileCfg<P, W, M, NW, NS,
+                      SRC == SRC_DESC && SINK != SINK_GROUP && tile_vdesc_prefetch<P, W, M, NW>()>;
     static constexpr auto kern = TileKernel<S, P, W, SRC, SINK>::kern;
     static inline std::once_flag once;
     static inline int blocks_per_cu = 1;
@@ -132,12 +137,13 @@ struct TileLaunch {
 };
 
 template <int P, int W, int V, int SRC, int SINK>
-int launch_tiles(const TileArgs &args, hipStream_t s)
+int launch_tiles(const typename KernelArgs<SINK>::type &kargs, hipStream_t s)
 {
     using TL = TileLaunch<P, W, V, SRC, SINK>;
     using C = typename TL::C;
     int rc = TL::setup();
     if (rc) return rc;
+    const TileArgs &args = base_args(kargs);
     const int64_t ntiles = SINK == SINK_TRAIN ? args.save_ld / TL::M
                                               : (args.n_rows + TL::M - 1) / TL::M;
     const int64_t grid = std::min<int64_t>(ntiles, (int64_t)device_cus() * TL::blocks_per_cu);
@@ -151,7 +157,7 @@ int launch_tiles(const TileArgs &args, hipStream_t s)
             ADV_HIP(hipEventRecord(e0, s));
         }
     }
-    hipLaunchKernelGGL(TL::kern, dim3((unsigned)grid), dim3(C::THREADS), C::LDS, s, args);
+    hipLaunchKernelGGL(TL::kern, dim3((unsigned)grid), dim3(C::THREADS), C::LDS, s, kargs);
     ADV_LAUNCHED("mlp_tiles_kernel");
     if (e0) {
         std::lock_guard<std::mutex> lock(g_prof_mu);
@@ -210,7 +216,8 @@ int prepare_model_kernels(int precision, int tile_w)
 }
 
 template <int SRC, int SINK>
-int dispatch_tiles(int precision, int W, int variant, const TileArgs &a, hipStream_t s)
+int dispatch_tiles(int precision, int W, int variant, const typename KernelArgs<SINK>::type &a,
+                   hipStream_t s)
 {
 #define ADV_CASE(P, WW)                                                          \
     if (precision == P && W == WW) {                                             \
@@ -218,7 +225,7 @@ int dispatch_tiles(int precision, int W, int variant, const TileArgs &a, hipStre
             if (variant == 1) return launch_tiles<P, WW, 1, SRC, SINK>(a, s);    \
         if constexpr (TileShape<P, WW, 2>::exists)                               \
             if (variant == 2) return launch_tiles<P, WW, 2, SRC, SINK>(a, s);    \
-        if constexpr (TileShape<P, WW, 3>::exists)                               \
+        if constexpr (TileShape<P, WW, 3>::exists && SINK != SINK_GROUP)         \
             if (variant == 3) return launch_tiles<P, WW, 3, SRC, SINK>(a, s);    \
         return launch_tiles<P, WW, 0, SRC, SINK>(a, s);                          \
     }
@@ -350,6 +357,68 @@ extern "C" int advisor_rank(const advisor_model *model, const int64_t *kdesc,
                      as_stream(stream), true);
 }
 
+namespace adv {
+
+// The tile shape a grouped pass runs a model on: its own, except that the
+// ping-pong shape runs as the shape it schedules (the same bits).
+static int group_variant(const advisor_model *m)
+{
+    if (m->tile_variant != 3) return m->tile_variant;
+    return (m->precision == PREC_FP8 && m->tile_w == 1024) ? 1 : 0;
+}
+
+// Whether two models can share a grouped pass: one kernel instance (precision,
+// tile width, tile shape) and one input tile (identical Z-score statistics).
+static bool groupable(const advisor_model *a, const advisor_model *b)
+{
+    if (a->precision != b->precision || a->tile_w != b->tile_w) return false;
+    if (group_variant(a) != group_variant(b)) return false;
+    if (!a->h_stats || !b->h_stats) return false;
+    return std::memcmp(a->h_mu, b->h_mu, sizeof(a->h_mu)) == 0 &&
+           std::memcmp(a->h_sigma, b->h_sigma, sizeof(a->h_sigma)) == 0;
+}
+
+// One grouped pass: the input tile of each tile is built once (with the
+// shared statistics) and every model's network runs on it; model i's keys
+// go to best_out row idx[i].
+static int rank_group(const advisor_model *const *models, const int *idx, int n_group,
+                      const int64_t *kdesc, const int64_t *vdesc, const int64_t *offsets,
+                      int64_t n_kernels, int64_t n_variants, int64_t *best_out, float *pred_out,
+                      hipStream_t s)
+{
+    const advisor_model *m0 = models[idx[0]];
+    const unsigned kb = (unsigned)((n_kernels + 255) / 256);
+    GroupArgs g{};
+    g.base.kdesc = kdesc;
+    g.base.vdesc = vdesc;
+    g.base.offsets = offsets;
+    g.base.n_k = n_kernels;
+    g.base.n_rows = n_variants;
+    g.base.net = net_view(m0);
+    g.n_models = n_group;
+    for (int i = 0; i < n_group; ++i) {
+        int64_t *row = best_out + (int64_t)idx[i] * n_kernels;
+        hipLaunchKernelGGL(keys_init_kernel, dim3(kb), dim3(256), 0, s,
+                           reinterpret_cast<uint64_t *>(row), n_kernels);
+        g.nets[i] = net_view(models[idx[i]]);
+        g.keys[i] = reinterpret_cast<uint64_t *>(row);
+        g.pred[i] = pred_out ? pred_out + (int64_t)idx[i] * n_variants : nullptr;
+    }
+    ADV_LAUNCHED("keys_init_kernel");
+    if (n_variants > 0) {
+        int rc = dispatch_tiles<SRC_DESC, SINK_GROUP>(m0->precision, m0->tile_w, group_variant(m0),
+                                                      g, s);
+        if (rc) return rc;
+    }
+    for (int i = 0; i < n_group; ++i)
+        hipLaunchKernelGGL(keys_final_kernel, dim3(kb), dim3(256), 0, s,
+                           best_out + (int64_t)idx[i] * n_kernels, n_kernels);
+    ADV_LAUNCHED("keys_final_kernel");
+    return ADVISOR_OK;
+}
+
+}  // namespace adv
+
 extern "C" int advisor_rank_multi(const advisor_model *const *models, int n_models,
                                   const int64_t *kdesc, const int64_t *vdesc,
                                   const int64_t *offsets, int64_t n_kernels, int64_t n_variants,
@@ -363,12 +432,37 @@ extern "C" int advisor_rank_multi(const advisor_model *const *models, int n_mode
             return fail(ADVISOR_EINVAL, "the models live on different devices");
     }
     if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (n_kernels >= (int64_t)1 << 31) return fail(ADVISOR_ESHAPE, "n_kernels must be < 2^31");
     if (n_kernels == 0) return ADVISOR_OK;
     if (!best_out) return fail(ADVISOR_EINVAL, "advisor_rank_multi: null best_out");
-    for (int t = 0; t < n_models; ++t) {
-        int rc = advisor_rank(models[t], kdesc, vdesc, offsets, n_kernels, n_variants,
-                              best_out + (int64_t)t * n_kernels,
-                              pred_out ? pred_out + (int64_t)t * n_variants : nullptr, stream);
+    if (!kdesc || !offsets || (n_variants > 0 && !vdesc))
+        return fail(ADVISOR_EINVAL, "advisor_rank_multi: null pointer");
+    hipStream_t s = as_stream(stream);
+    if (debug_offsets(s)) {
+        if (int rc = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, stream))
+            return rc;
+    }
+    // models that share a kernel instance and their statistics run in one
+    // grouped pass (at most GROUP_MAX each); the others alone
+    std::vector<char> done((size_t)n_models, 0);
+    std::vector<int> idx;
+    for (int t0 = 0; t0 < n_models; ++t0) {
+        if (done[t0]) continue;
+        idx.assign(1, t0);
+        done[t0] = 1;
+        for (int t1 = t0 + 1; t1 < n_models && (int)idx.size() < GROUP_MAX; ++t1)
+            if (!done[t1] && groupable(models[t0], models[t1])) {
+                idx.push_back(t1);
+                done[t1] = 1;
+            }
+        int rc = idx.size() > 1
+                     ? rank_group(models, idx.data(), (int)idx.size(), kdesc, vdesc, offsets,
+                                  n_kernels, n_variants, best_out, pred_out, s)
+                     : rank_core(models[t0], kdesc, vdesc, offsets, n_kernels, n_variants,
+                                 best_out + (int64_t)t0 * n_kernels,
+                                 pred_out ? pred_out + (int64_t)t0 * n_variants : nullptr, s,
+                                 false);
         if (rc) return rc;
     }
     return ADVISOR_OK;

@@ -32,7 +32,10 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 
 enum { PREC_FP32 = ADVISOR_FP32, PREC_BF16 = ADVISOR_BF16, PREC_FP8 = ADVISOR_FP8_E4M3 };
 enum { SRC_DESC = 0, SRC_FEAT = 1 };
-enum { SINK_PRED = 0, SINK_RANK = 1, SINK_TRAIN = 2 };
+// SINK_GROUP: several models that share the input tile (same precision,
+// tile width and Z-score statistics) ranked in one pass, each exactly as
+// SINK_RANK would rank it.
+enum { SINK_PRED = 0, SINK_RANK = 1, SINK_TRAIN = 2, SINK_GROUP = 3 };
 
 // Per-precision fragment geometry. A lane loads KV consecutive k values in
 // one vector (16 or 32 bytes); each matrix-core op consumes KL of them per
@@ -132,6 +135,30 @@ struct TileArgs {
     // 32 b + t of layer l is positive (as stored) for that row
     uint32_t *save_mask;
 };
+
+// A grouped pass: the descriptors, segments and statistics of `base` (its
+// `net` is the first model), then per model its network and its outputs.
+constexpr int GROUP_MAX = 8;
+struct GroupArgs {
+    TileArgs base;
+    int n_models;
+    NetView nets[GROUP_MAX];
+    uint64_t *keys[GROUP_MAX];   // [n_k] argmin keys of each model
+    float *pred[GROUP_MAX];      // [n_rows] predictions of each model, or null
+};
+
+template <int SINK> struct KernelArgs { using type = TileArgs; };
+template <> struct KernelArgs<SINK_GROUP> { using type = GroupArgs; };
+__host__ __device__ __forceinline__ const TileArgs &base_args(const TileArgs &a) { return a; }
+__host__ __device__ __forceinline__ const TileArgs &base_args(const GroupArgs &a) { return a.base; }
+__device__ __forceinline__ int group_size(const TileArgs &) { return 1; }
+__device__ __forceinline__ int group_size(const GroupArgs &a) { return a.n_models; }
+__device__ __forceinline__ const NetView &group_net(const TileArgs &a, int) { return a.net; }
+__device__ __forceinline__ const NetView &group_net(const GroupArgs &a, int t) { return a.nets[t]; }
+__device__ __forceinline__ uint64_t *group_keys(const TileArgs &a, int) { return a.keys; }
+__device__ __forceinline__ uint64_t *group_keys(const GroupArgs &a, int t) { return a.keys[t]; }
+__device__ __forceinline__ float *group_pred(const TileArgs &a, int) { return a.pred; }
+__device__ __forceinline__ float *group_pred(const GroupArgs &a, int t) { return a.pred[t]; }
 
 // Store one value of a saved activation (transposed layout) in precision P.
 template <int P>
@@ -688,23 +715,23 @@ __device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, i
 template <class C, int M, int SINK>
 __device__ __forceinline__ void tile_output(const TileArgs &args, int64_t row0, int tid, int lane,
                                             int wave, const float *hpart, const int *meta_ok,
-                                            const int *meta_kid)
+                                            const int *meta_kid, const float *head_b, float *pred,
+                                            uint64_t *keys)
 {
-    const NetView &net = args.net;
     const int64_t n = args.n_rows;
     if (wave < (M + 63) / 64) {
         const bool inrow = tid < M;
         const int64_t row = row0 + tid;
-        float p = net.head_b[0];
+        float p = head_b[0];
         if (inrow) {
 #pragma unroll
             for (int q = 0; q < C::WN; ++q) p += hpart[q * M + tid];
         }
         const bool ok = inrow && meta_ok[tid] != 0;
         if constexpr (SINK == SINK_PRED || SINK == SINK_TRAIN) {
-            if (inrow && row < n) args.pred[row] = p;
+            if (inrow && row < n) pred[row] = p;
         } else {
-            if (inrow && row < n && args.pred) args.pred[row] = ok ? p : __builtin_nanf("");
+            if (inrow && row < n && pred) pred[row] = ok ? p : __builtin_nanf("");
             const bool take = ok && !__builtin_isnan(p);
             uint64_t key = ~0ull;
             if (take) {
@@ -730,7 +757,7 @@ __device__ __forceinline__ void tile_output(const TileArgs &args, int64_t row0, 
             const int next = __shfl_down(kid, 1, 64);
             const bool last = (lane == 63) || (next != kid);
             if (last && kid >= 0 && kid < args.n_k && key != ~0ull)
-                atomicMin(reinterpret_cast<unsigned long long *>(args.keys + kid),
+                atomicMin(reinterpret_cast<unsigned long long *>(keys + kid),
                           (unsigned long long)key);
         }
     }
@@ -739,9 +766,16 @@ __device__ __forceinline__ void tile_output(const TileArgs &args, int64_t row0, 
 template <int P, int W, int M, int NWAVES, int NSPLIT, int SRC, int SINK>
 __global__ __launch_bounds__(NWAVES * 64)
 __attribute__((amdgpu_waves_per_eu(tile_waves_per_simd<P, W, M, NWAVES>()))) void
-mlp_tiles_kernel(TileArgs args)
+mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
 {
-    constexpr bool VPF = SRC == SRC_DESC && tile_vdesc_prefetch<P, W, M, NWAVES>();
+    static_assert(SINK != SINK_GROUP || SRC == SRC_DESC, "grouped passes rank descriptors");
+    const TileArgs &args = base_args(kargs);
+    // a grouped pass ranks each of its models as SINK_RANK does; it reads the
+    // descriptors from global memory (the staged output weights would have
+    // to be reloaded per model)
+    constexpr int SK = SINK == SINK_GROUP ? SINK_RANK : SINK;
+    constexpr bool VPF = SRC == SRC_DESC && SINK != SINK_GROUP &&
+                         tile_vdesc_prefetch<P, W, M, NWAVES>();
     using C = TileCfg<P, W, M, NWAVES, NSPLIT, VPF>;
     using G = typename C::G;
     constexpr int P0 = FirstP<P>::value;
@@ -759,7 +793,6 @@ mlp_tiles_kernel(TileArgs args)
     const int wave = __builtin_amdgcn_readfirstlane(tid0 >> 6);
     const int wn = wave % C::WN, wm = wave / C::WN;
     const int nb0 = wn * C::NBW, mb0 = wm * C::MBW;
-    const NetView &net = args.net;
     const int64_t n = args.n_rows;
     // the training forward covers every row of the saved buffers (zeros past n)
     const int64_t ntiles = SINK == SINK_TRAIN ? args.save_ld / M : (n + M - 1) / M;
@@ -786,7 +819,6 @@ mlp_tiles_kernel(TileArgs args)
     using RH = typename G::Vec;
     R0 ring0[ring_depth<P0, 32>()][C::NBP];
     RH ringh[ring_depth<P, W>()][C::NBP];
-    const R0 *w0 = reinterpret_cast<const R0 *>(net.w[0]);
 
     // Descriptor prefetch: the variant rows of a tile are one contiguous run
     // of M * 64 bytes, copied straight into LDS by direct-to-LDS loads (lane
@@ -806,7 +838,7 @@ mlp_tiles_kernel(TileArgs args)
         }
     };
     if constexpr (VPF) {
-        for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = net.head_w[i];
+        for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = args.net.head_w[i];
         if ((int64_t)blockIdx.x < ntiles) issue_vdesc(blockIdx.x);
     }
 
@@ -816,177 +848,193 @@ mlp_tiles_kernel(TileArgs args)
         __syncthreads();  // previous tile's readers of xin / meta / hpart are done
         tid = opaque_tid();
         lane = tid & 63, half = lane >> 5, col = lane & 31;
-        tile_input<C, P, M, SRC, SINK>(args, row0, tid, xin, meta_ok, meta_kid, vst);
+        tile_input<C, P, M, SRC, SK>(args, row0, tid, xin, meta_ok, meta_kid, vst);
         // the first layer's weights, requested before the barrier (not across
         // the input stage, whose registers are at their peak)
-        if constexpr (XPF) ring_load<P0, 32, C::NBP>(w0, nb0, lane, ring0);
+        if constexpr (XPF)
+            ring_load<P0, 32, C::NBP>(reinterpret_cast<const R0 *>(args.net.w[0]), nb0, lane, ring0);
         __syncthreads();
 
-        // ---- layer 0 (32 inputs), then hidden layers 1..n_hidden-1. Each wave
-        // covers its n-blocks in NSPLIT passes (smaller accumulators): the
-        // outputs of all passes but the last wait packed in registers; the
-        // last pass's accumulators cross the barrier after which every wave
-        // has read the layer's input, and all outputs then go to LDS in its
-        // place.
-        for (int l = 0; l < net.n_hidden; ++l) {
-            tid = opaque_tid();
-            lane = tid & 63, half = lane >> 5, col = lane & 31;
-            const bool last = l + 1 == net.n_hidden;
-            const float *bias = net.b[l];
-            // fp8 layers scale the products before the bias; every other layer
-            // starts its accumulators at the bias
-            const bool scaled = P == PREC_FP8 && l > 0;
-            const float qs = scaled ? net.qscale[l] : 1.0f;
-            const float qinv = net.qinv[l];
-            typename Held<P>::T held[C::NSPLIT > 1 ? C::NSPLIT - 1 : 1][C::NBP][4][C::MBW];
-            float srow[C::MBW];
-#pragma unroll
-            for (int j = 0; j < C::MBW; ++j) srow[j] = 0.0f;
-#pragma unroll
-            for (int ps = 0; ps < C::NSPLIT; ++ps) {
-                const int nbp0 = nb0 + ps * C::NBP;
-                const bool final_pass = ps + 1 == C::NSPLIT;
-                v16f acc[C::NBP][C::MBW];
-                const RH *wl = reinterpret_cast<const RH *>(net.w[l]);
-                if constexpr (!XPF) {
-                    if (l == 0)
-                        ring_load<P0, 32, C::NBP>(w0, nbp0, lane, ring0);
-                    else
-                        ring_load<P, W, C::NBP>(wl, nbp0, lane, ringh);
-                }
-                if (l == 0)
-                    layer_mma<P0, 32, C::NBP, C::MBW>(w0, xin, C::XS, nbp0, mb0, lane, acc, bias,
-                                                      ring0);
-                else
-                    layer_mma<P, W, C::NBP, C::MBW>(wl, act, C::AS, nbp0, mb0, lane, acc,
-                                                    scaled ? nullptr : bias, ringh);
-                // request the next call's first weight groups before the epilogue
-                if (!XPF) {
-                } else if (!final_pass) {
-                    if (l == 0)
-                        ring_load<P0, 32, C::NBP>(w0, nbp0 + C::NBP, lane, ring0);
-                    else
-                        ring_load<P, W, C::NBP>(wl, nbp0 + C::NBP, lane, ringh);
-                } else if (!last) {
-                    ring_load<P, W, C::NBP>(reinterpret_cast<const RH *>(net.w[l + 1]), nb0, lane,
-                                            ringh);
-                }
-                if constexpr (VPF) {
-                    if (final_pass && last && tile + gridDim.x < ntiles) issue_vdesc(tile + gridDim.x);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                // training keeps the last hidden layer's outputs too (copied out below)
-                constexpr bool keep_last = SINK == SINK_TRAIN;
-                if (final_pass && (!last || keep_last)) {
-                    if (l > 0) __syncthreads();  // every wave finished reading this layer's input
-#pragma unroll
-                    for (int hp = 0; hp + 1 < C::NSPLIT; ++hp)
-#pragma unroll
-                        for (int i = 0; i < C::NBP; ++i)
-#pragma unroll
-                            for (int j = 0; j < C::MBW; ++j)
-#pragma unroll
-                                for (int g = 0; g < 4; ++g) {
-                                    const int nn = (nb0 + hp * C::NBP + i) * 32 + 8 * g + 4 * half;
-                                    const int m = (mb0 + j) * 32 + col;
-                                    store_held<P>(act + (size_t)m * C::AS, nn, held[hp][i][g][j]);
-                                }
-                }
-                // one 32-neuron block at a time: its bias (and output-layer
-                // weight) vectors are loaded together, and the fence keeps the
-                // next block's loads from being hoisted
-#pragma unroll
-                for (int i = 0; i < C::NBP; ++i) {
-                    v4f bias_r[4], hw_r[4];
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
-                        if (scaled) bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
-                        if (last)
-                            hw_r[g] = VPF ? *reinterpret_cast<const v4f *>(hw_lds + nn)
-                                          : *reinterpret_cast<const v4f *>(net.head_w + nn);
+        // one pass of the network per model of a group (one for other sinks),
+        // all on the input tile built above
+        const int n_models = group_size(kargs);
+        for (int t = 0; t < n_models; ++t) {
+            const NetView &net = group_net(kargs, t);
+            const R0 *w0 = reinterpret_cast<const R0 *>(net.w[0]);
+            const bool last_model = t + 1 == n_models;
+            if (t > 0) {
+                __syncthreads();  // the previous model's readers of act and hpart are done
+                if constexpr (XPF) ring_load<P0, 32, C::NBP>(w0, nb0, lane, ring0);
+            }
+
+            // ---- layer 0 (32 inputs), then hidden layers 1..n_hidden-1. Each wave
+            // covers its n-blocks in NSPLIT passes (smaller accumulators): the
+            // outputs of all passes but the last wait packed in registers; the
+            // last pass's accumulators cross the barrier after which every wave
+            // has read the layer's input, and all outputs then go to LDS in its
+            // place.
+            for (int l = 0; l < net.n_hidden; ++l) {
+                tid = opaque_tid();
+                lane = tid & 63, half = lane >> 5, col = lane & 31;
+                const bool last = l + 1 == net.n_hidden;
+                const float *bias = net.b[l];
+                // fp8 layers scale the products before the bias; every other layer
+                // starts its accumulators at the bias
+                const bool scaled = P == PREC_FP8 && l > 0;
+                const float qs = scaled ? net.qscale[l] : 1.0f;
+                const float qinv = net.qinv[l];
+                typename Held<P>::T held[C::NSPLIT > 1 ? C::NSPLIT - 1 : 1][C::NBP][4][C::MBW];
+                float srow[C::MBW];
+    #pragma unroll
+                for (int j = 0; j < C::MBW; ++j) srow[j] = 0.0f;
+    #pragma unroll
+                for (int ps = 0; ps < C::NSPLIT; ++ps) {
+                    const int nbp0 = nb0 + ps * C::NBP;
+                    const bool final_pass = ps + 1 == C::NSPLIT;
+                    v16f acc[C::NBP][C::MBW];
+                    const RH *wl = reinterpret_cast<const RH *>(net.w[l]);
+                    if constexpr (!XPF) {
+                        if (l == 0)
+                            ring_load<P0, 32, C::NBP>(w0, nbp0, lane, ring0);
+                        else
+                            ring_load<P, W, C::NBP>(wl, nbp0, lane, ringh);
                     }
-#pragma unroll
-                    for (int j = 0; j < C::MBW; ++j) {
-                        const int m = (mb0 + j) * 32 + col;
-                        uint32_t mbits = 0;  // training: ReLU mask of this lane's 16 neurons
-#pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
-                            v4f v;
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
-                                                       : acc[i][j][4 * g + e];
-                                v[e] = z > 0.0f ? z : 0.0f;
-                            }
-                            if constexpr (SINK == SINK_TRAIN) {
-                                // from the value as stored (non-negative: any
-                                // non-zero bit pattern is positive)
-                                // the stored values are >= 0 (never -0): positive
-                                // exactly when their bit pattern is non-zero, and
-                                // min(bits, 1) is that bit
-                                const typename Held<P>::T hv = pack4<P>(v, qinv);
-                                uint32_t nib;
-                                if constexpr (P == PREC_FP32) {
-                                    nib = 0;
-#pragma unroll
-                                    for (int e = 0; e < 4; ++e)
-                                        nib |= min(__float_as_uint(hv[e]), 1u) << e;
-                                } else {
-                                    // the four bf16 values as two words, low half first
-                                    typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
-                                    const v2u_ u = __builtin_bit_cast(v2u_, hv);
-                                    nib = min(u[0] & 0xffffu, 1u) | (min(u[0] >> 16, 1u) << 1) |
-                                          (min(u[1] & 0xffffu, 1u) << 2) | (min(u[1] >> 16, 1u) << 3);
-                                }
-                                mbits |= nib << (8 * g + 4 * half);
-                            }
-                            if (last) {
-                                // output layer: fixed order over blocks, groups, elements
-#pragma unroll
-                                for (int e = 0; e < 4; ++e) srow[j] += v[e] * hw_r[g][e];
-                            }
-                            if (!last || keep_last) {
-                                if (final_pass)
-                                    store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
-                                else
-                                    held[final_pass ? 0 : ps][i][g][j] = pack4<P>(v, qinv);
-                            }
-                        }
-                        if constexpr (SINK == SINK_TRAIN) {
-                            // the two lane halves hold the block's other 16 neurons
-                            const uint32_t word = mbits | (uint32_t)__shfl_xor((int)mbits, 32, 64);
-                            if (!last && args.save_mask != nullptr && half == 0)
-                                args.save_mask[((int64_t)l * (W / 32) + nbp0 + i) * args.save_ld +
-                                               row0 + m] = word;
-                        }
+                    if (l == 0)
+                        layer_mma<P0, 32, C::NBP, C::MBW>(w0, xin, C::XS, nbp0, mb0, lane, acc, bias,
+                                                          ring0);
+                    else
+                        layer_mma<P, W, C::NBP, C::MBW>(wl, act, C::AS, nbp0, mb0, lane, acc,
+                                                        scaled ? nullptr : bias, ringh);
+                    // request the next call's first weight groups before the epilogue
+                    if (!XPF) {
+                    } else if (!final_pass) {
+                        if (l == 0)
+                            ring_load<P0, 32, C::NBP>(w0, nbp0 + C::NBP, lane, ring0);
+                        else
+                            ring_load<P, W, C::NBP>(wl, nbp0 + C::NBP, lane, ringh);
+                    } else if (!last) {
+                        ring_load<P, W, C::NBP>(reinterpret_cast<const RH *>(net.w[l + 1]), nb0, lane,
+                                                ringh);
+                    }
+                    if constexpr (VPF) {
+                        if (final_pass && last && last_model && tile + gridDim.x < ntiles)
+                            issue_vdesc(tile + gridDim.x);
                     }
                     __builtin_amdgcn_sched_barrier(0);
+                    // training keeps the last hidden layer's outputs too (copied out below)
+                    constexpr bool keep_last = SINK == SINK_TRAIN;
+                    if (final_pass && (!last || keep_last)) {
+                        if (l > 0) __syncthreads();  // every wave finished reading this layer's input
+    #pragma unroll
+                        for (int hp = 0; hp + 1 < C::NSPLIT; ++hp)
+    #pragma unroll
+                            for (int i = 0; i < C::NBP; ++i)
+    #pragma unroll
+                                for (int j = 0; j < C::MBW; ++j)
+    #pragma unroll
+                                    for (int g = 0; g < 4; ++g) {
+                                        const int nn = (nb0 + hp * C::NBP + i) * 32 + 8 * g + 4 * half;
+                                        const int m = (mb0 + j) * 32 + col;
+                                        store_held<P>(act + (size_t)m * C::AS, nn, held[hp][i][g][j]);
+                                    }
+                    }
+                    // one 32-neuron block at a time: its bias (and output-layer
+                    // weight) vectors are loaded together, and the fence keeps the
+                    // next block's loads from being hoisted
+    #pragma unroll
+                    for (int i = 0; i < C::NBP; ++i) {
+                        v4f bias_r[4], hw_r[4];
+    #pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
+                            if (scaled) bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
+                            if (last)
+                                hw_r[g] = VPF ? *reinterpret_cast<const v4f *>(hw_lds + nn)
+                                              : *reinterpret_cast<const v4f *>(net.head_w + nn);
+                        }
+    #pragma unroll
+                        for (int j = 0; j < C::MBW; ++j) {
+                            const int m = (mb0 + j) * 32 + col;
+                            uint32_t mbits = 0;  // training: ReLU mask of this lane's 16 neurons
+    #pragma unroll
+                            for (int g = 0; g < 4; ++g) {
+                                const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
+                                v4f v;
+    #pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
+                                                           : acc[i][j][4 * g + e];
+                                    v[e] = z > 0.0f ? z : 0.0f;
+                                }
+                                if constexpr (SINK == SINK_TRAIN) {
+                                    // from the value as stored (non-negative: any
+                                    // non-zero bit pattern is positive)
+                                    // the stored values are >= 0 (never -0): positive
+                                    // exactly when their bit pattern is non-zero, and
+                                    // min(bits, 1) is that bit
+                                    const typename Held<P>::T hv = pack4<P>(v, qinv);
+                                    uint32_t nib;
+                                    if constexpr (P == PREC_FP32) {
+                                        nib = 0;
+    #pragma unroll
+                                        for (int e = 0; e < 4; ++e)
+                                            nib |= min(__float_as_uint(hv[e]), 1u) << e;
+                                    } else {
+                                        // the four bf16 values as two words, low half first
+                                        typedef unsigned v2u_ __attribute__((ext_vector_type(2)));
+                                        const v2u_ u = __builtin_bit_cast(v2u_, hv);
+                                        nib = min(u[0] & 0xffffu, 1u) | (min(u[0] >> 16, 1u) << 1) |
+                                              (min(u[1] & 0xffffu, 1u) << 2) | (min(u[1] >> 16, 1u) << 3);
+                                    }
+                                    mbits |= nib << (8 * g + 4 * half);
+                                }
+                                if (last) {
+                                    // output layer: fixed order over blocks, groups, elements
+    #pragma unroll
+                                    for (int e = 0; e < 4; ++e) srow[j] += v[e] * hw_r[g][e];
+                                }
+                                if (!last || keep_last) {
+                                    if (final_pass)
+                                        store4<P>(act + (size_t)m * C::AS, nn, v, qinv);
+                                    else
+                                        held[final_pass ? 0 : ps][i][g][j] = pack4<P>(v, qinv);
+                                }
+                            }
+                            if constexpr (SINK == SINK_TRAIN) {
+                                // the two lane halves hold the block's other 16 neurons
+                                const uint32_t word = mbits | (uint32_t)__shfl_xor((int)mbits, 32, 64);
+                                if (!last && args.save_mask != nullptr && half == 0)
+                                    args.save_mask[((int64_t)l * (W / 32) + nbp0 + i) * args.save_ld +
+                                                   row0 + m] = word;
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                if (!last || SINK == SINK_TRAIN) {
+                    __syncthreads();  // next layer (or the copy below) reads the complete activations
+                    if constexpr (SINK == SINK_TRAIN)
+                        copy_act_transposed<P, W, M, C::THREADS, C::AS>(
+                            act,
+                            reinterpret_cast<unsigned char *>(args.save_h) +
+                                (size_t)l * W * args.save_ld * Geo<P>::EB,
+                            args.save_ld, row0, n, tid);
+                }
+                if (last) {
+    #pragma unroll
+                    for (int j = 0; j < C::MBW; ++j) {
+                        float sj = srow[j];
+                        sj += __shfl_xor(sj, 32, 64);  // the two lane halves hold different neurons
+                        if (half == 0) hpart[wn * M + (mb0 + j) * 32 + col] = sj;
+                    }
                 }
             }
-            if (!last || SINK == SINK_TRAIN) {
-                __syncthreads();  // next layer (or the copy below) reads the complete activations
-                if constexpr (SINK == SINK_TRAIN)
-                    copy_act_transposed<P, W, M, C::THREADS, C::AS>(
-                        act,
-                        reinterpret_cast<unsigned char *>(args.save_h) +
-                            (size_t)l * W * args.save_ld * Geo<P>::EB,
-                        args.save_ld, row0, n, tid);
-            }
-            if (last) {
-#pragma unroll
-                for (int j = 0; j < C::MBW; ++j) {
-                    float sj = srow[j];
-                    sj += __shfl_xor(sj, 32, 64);  // the two lane halves hold different neurons
-                    if (half == 0) hpart[wn * M + (mb0 + j) * 32 + col] = sj;
-                }
-            }
+            __syncthreads();
+            tid = opaque_tid();
+            lane = tid & 63;
+            tile_output<C, M, SK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid, net.head_b,
+                                  group_pred(kargs, t), group_keys(kargs, t));
         }
-        __syncthreads();
-        tid = opaque_tid();
-        lane = tid & 63;
-        tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid);
     }
 }
 
@@ -1178,7 +1226,8 @@ mlp_pp_kernel(TileArgs args)
         __syncthreads();
         tid = opaque_tid();
         lane = tid & 63;
-        tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid);
+        tile_output<C, M, SINK>(args, row0, tid, lane, wave, hpart, meta_ok, meta_kid, net.head_b,
+                                args.pred, args.keys);
     }
 }
 

@@ -234,6 +234,11 @@ extern "C" int advisor_model_create(const int32_t *widths, int n_widths, int pre
                           hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy");
     }
+    for (int j = 0; j < NFEAT; ++j) {
+        m->h_mu[j] = 0.0;
+        m->h_sigma[j] = 1.0;
+    }
+    m->h_stats = true;
     for (int l = 0; l < ADVISOR_MAX_LAYERS; ++l) {
         m->qscale[l] = 1.0f;
         m->qinv[l] = 1.0f;
@@ -280,6 +285,11 @@ extern "C" int advisor_model_set_params(advisor_model *m, const float *w_master,
         (void)hipSetDevice(prev);
         return hip_fail(e, "set_params copy");
     }
+    for (int j = 0; j < NFEAT; ++j) {
+        m->h_mu[j] = mu[j];
+        m->h_sigma[j] = sigma[j];
+    }
+    m->h_stats = true;
     m->fp8_calibrated = false;
     m->wt_valid = false;
     int rc = repack(m, nullptr);
@@ -309,6 +319,7 @@ extern "C" int advisor_model_set_zscore(advisor_model *m, const double *mu, cons
     clear_error();
     if (!m || !mu || !sigma) return fail(ADVISOR_EINVAL, "set_zscore: null pointer");
     hipStream_t s = as_stream(stream);
+    m->h_stats = false;  // device values: no host copy to compare
     ADV_HIP(hipMemcpyAsync(m->mu, mu, sizeof(double) * NFEAT, hipMemcpyDeviceToDevice, s));
     ADV_HIP(hipMemcpyAsync(m->sigma, sigma, sizeof(double) * NFEAT, hipMemcpyDeviceToDevice, s));
     return ADVISOR_OK;
