@@ -66,6 +66,8 @@ def _load():
         lib.oracle_rmsprop.restype = None
         lib.oracle_enumerate.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_enumerate.restype = i64
+        lib.oracle_lower_variants.argtypes = [P, P, i64, i64, i64, P]
+        lib.oracle_lower_variants.restype = None
         lib.oracle_map_class.argtypes = [C.c_int]
         lib.oracle_map_class.restype = C.c_int
         lib.oracle_classify.argtypes = [P, P, P, i64, P, P, P, P]
@@ -249,6 +251,17 @@ def enumerate_variants(n_loops, sched_mask=7):
         rows[off[k]:off[k + 1], 0] = k
         rows[off[k]:off[k + 1], 1:] = blk
     return off, rows
+
+
+def lower_variants(kdesc, gen_rows, teams, threads):
+    """Generated variants (rows [k, x, d, c, schedule, data] of
+    enumerate_variants) as cost-model descriptor rows [n_v, 8]: the parallel
+    structure c + 8x + 64d + 512 schedule, the given default launch, and map
+    clauses from the data option (0: each array's analysed class, 1: tofrom)."""
+    kd, g = _c(kdesc, np.int64), _c(gen_rows, np.int64)
+    out = np.zeros((g.shape[0], 8), dtype=np.int64)
+    _load().oracle_lower_variants(_p(kd), _p(g), g.shape[0], int(teams), int(threads), _p(out))
+    return out
 
 
 def rank(kdesc, vdesc, offsets, widths, params, mu, sigma, n_threads=0, want_pred=True):

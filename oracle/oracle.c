@@ -50,6 +50,16 @@ static int map_allowed(int64_t req, int64_t m)
  * the kernel analysis records (section 4.1: loop nest, arrays, data classes)
  * and the variant's choices (section 4.1.3: collapse, teams, threads, map).
  * Returns 1 if the variant is valid, 0 (and a zero row) if it is not.
+ *
+ * The variant's parallel structure (column 1) is c + 8 x + 64 d + 512 s, the
+ * parameters of section 4.1.3: the parallel-for directive at loop x with
+ * collapse c, a teams-distribute collapse d, and the schedule s (0 static,
+ * 1 dynamic, 2 guided). At x = 0 the two directives are one combined
+ * directive over loops 0 .. c-1 (d = 0, 1 <= c <= D): its Pc iterations are
+ * spread over all T x H threads. At 1 <= x < D, teams distribute loops
+ * 0 .. d-1 (1 <= d <= x; Pt iterations over the T teams) and each team's H
+ * threads share loops x .. x+c-1 (1 <= c <= D - x; Pf iterations); the loops
+ * between (d .. x-1) and after (x+c ..) run serially.
  */
 static int featurize_row(const int64_t *kd, const int64_t *vd, int64_t n_k, int64_t *f)
 {
@@ -58,14 +68,18 @@ static int featurize_row(const int64_t *kd, const int64_t *vd, int64_t n_k, int6
     if (kid < 0 || kid >= n_k) return 0;
     kd += kid * KD_COLS;
     int64_t D = kd[0], A = kd[5], E = kd[6], fpi = kd[11];
-    int64_t c = vd[1], T = vd[2], H = vd[3];
+    int64_t cf = vd[1], T = vd[2], H = vd[3];
+    if (cf < 0 || cf >= 1536) return 0;
+    int64_t c = cf % 8, x = (cf / 8) % 8, d = (cf / 64) % 8, sched = cf / 512;
     if (D < 1 || D > 4) return 0;
     for (int i = 0; i < 4; i++) {
         if (kd[1 + i] < 1) return 0;
         if (i >= D && kd[1 + i] != 1) return 0;
     }
     if (A < 0 || A > 4 || E < 1 || E > 64 || fpi < 0) return 0;
-    if (c < 1 || c > D || T < 1 || H < 1) return 0;
+    if (T < 1 || H < 1 || sched > 2) return 0;
+    if (x == 0 && (d != 0 || c < 1 || c > D)) return 0;
+    if (x >= 1 && (x >= D || d < 1 || d > x || c < 1 || c > D - x)) return 0;
     for (int a = 0; a < A; a++) {
         if (kd[7 + a] < 0 || kd[7 + a] > 1) return 0;
         if (!map_allowed(kd[12 + a], vd[4 + a])) return 0;
@@ -75,13 +89,30 @@ static int featurize_row(const int64_t *kd, const int64_t *vd, int64_t n_k, int6
     for (int i = 0; i < 4; i++) N[i] = (uint64_t)kd[1 + i];
     /* iteration space and the part of it the collapsed loops expose */
     uint64_t I = N[0] * N[1] * N[2] * N[3];
-    uint64_t Pc = 1;
-    for (int i = 0; i < c; i++) Pc *= N[i];
-    uint64_t R = 1;                      /* iterations each collapsed index runs serially: */
-    for (int i = (int)c; i < 4; i++) R *= N[i];  /* the loops left out of the collapse */
     uint64_t TH = (uint64_t)T * (uint64_t)H;  /* hardware threads the launch asks for */
-    uint64_t busy = TH < Pc ? TH : Pc;        /* threads that get work */
-    uint64_t waves = Pc / TH + (Pc % TH != 0);/* rounds of collapsed iterations per thread */
+    uint64_t Pc = 1, R = 1, busy, waves, n_par;
+    if (x == 0) {
+        /* combined directive: loops 0..c-1 collapsed, the rest serial */
+        for (int i = 0; i < c; i++) Pc *= N[i];
+        for (int i = (int)c; i < 4; i++) R *= N[i];
+        busy = TH < Pc ? TH : Pc;        /* threads that get work */
+        waves = Pc / TH + (Pc % TH != 0);/* rounds of collapsed iterations per thread */
+        n_par = (uint64_t)c;             /* loops collapsed into parallel work */
+    } else {
+        /* teams over loops 0..d-1, a team's threads over loops x..x+c-1 */
+        uint64_t Pt = 1, Pf = 1;
+        for (int i = 0; i < d; i++) Pt *= N[i];
+        for (int i = (int)x; i < x + c; i++) Pf *= N[i];
+        for (int i = (int)d; i < x; i++) R *= N[i];
+        for (int i = (int)(x + c); i < 4; i++) R *= N[i];
+        Pc = Pt * Pf;
+        uint64_t bt = (uint64_t)T < Pt ? (uint64_t)T : Pt;
+        uint64_t bf = (uint64_t)H < Pf ? (uint64_t)H : Pf;
+        busy = bt * bf;
+        waves = (Pt / (uint64_t)T + (Pt % (uint64_t)T != 0)) *
+                (Pf / (uint64_t)H + (Pf % (uint64_t)H != 0));
+        n_par = (uint64_t)(d + c);
+    }
     uint64_t S = (uint64_t)E * I;             /* bytes of one array spanning the nest */
     uint64_t n_cls[4] = {0, 0, 0, 0};
     uint64_t ns = 0;
@@ -99,7 +130,7 @@ static int featurize_row(const int64_t *kd, const int64_t *vd, int64_t n_k, int6
     u[0] = (uint64_t)D;
     u[1] = N[0]; u[2] = N[1]; u[3] = N[2]; u[4] = N[3];
     u[5] = I;
-    u[6] = (uint64_t)c;
+    u[6] = n_par;
     u[7] = Pc;
     u[8] = R;
     u[9] = (uint64_t)T;
@@ -476,6 +507,32 @@ int64_t oracle_enumerate(int n, int sched_mask, int64_t *out)
                 }
     }
     return count;
+}
+
+/*
+ * A generated variant (section 4.1.3) as a cost-model descriptor row. gen row
+ * [k, x, d, c, schedule, data] -> vdesc row [k, c + 8 x + 64 d + 512 schedule,
+ * teams, threads, m0..m3]. The generated directives carry no num_teams or
+ * thread_limit clause, so teams and threads are the launch the target's
+ * runtime makes by default (given by the caller). The two data-transfer
+ * options: 0 maps every array with the class the data analysis gives it
+ * (section 4.1.2: enter/exit data of exactly what the kernel needs), 1 maps
+ * every array tofrom (the untransformed code that moves everything both
+ * ways). Arrays past the kernel's A are left 0.
+ */
+void oracle_lower_variants(const int64_t *kdesc, const int64_t *gen, int64_t n_v, int64_t teams,
+                           int64_t threads, int64_t *vdesc)
+{
+    for (int64_t i = 0; i < n_v; i++) {
+        const int64_t *g = gen + i * 6;
+        int64_t *v = vdesc + i * VD_COLS;
+        const int64_t *kd = kdesc + g[0] * KD_COLS;
+        v[0] = g[0];
+        v[1] = g[3] + 8 * g[1] + 64 * g[2] + 512 * g[4];
+        v[2] = teams;
+        v[3] = threads;
+        for (int a = 0; a < 4; a++) v[4 + a] = a < kd[5] ? (g[5] == 0 ? kd[12 + a] : CLS_TOFROM) : 0;
+    }
 }
 
 /*
