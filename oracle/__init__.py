@@ -15,7 +15,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY names another build of oracle.c to load (the sanitizer run)
+_LIB = os.environ.get("ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 NFEAT = 32
 
 _lib = None
@@ -33,10 +34,22 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_sanitized(out: str) -> str:
+    """oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer (ROCm's
+    clang, shared sanitizer runtime), for a CPU run of the tests with that
+    runtime preloaded."""
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off",
+           "-fPIC", "-shared", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-shared-libsan", _SRC, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 def _load():
     global _lib
     if _lib is None:
-        build()
+        if not os.environ.get("ORACLE_LIBRARY"):
+            build()
         lib = C.CDLL(_LIB)
         P = C.c_void_p
         i64 = C.c_int64
