@@ -27,10 +27,13 @@
  *        (0..4) of E bytes per element (1..64), s_a 1 for a stride-N walk,
  *        fpi flops per innermost iteration, req_a the data class found by
  *        the data analysis of section 4.1.2 (0 alloc, 1 to, 2 from, 3 tofrom)
- *      vdesc [n_variants, 8]: kernel_id, c, T, H, m0..m3
- *        c collapse depth of the combined teams-distribute-parallel-for
- *        (section 4.1.3), T teams, H threads per team, m_a the map clause of
- *        array a (same codes as req_a)
+ *      vdesc [n_variants, 8]: kernel_id, p, T, H, m0..m3
+ *        p the parallel structure c + 8 x + 64 d + 512 s (section 4.1.3):
+ *        the parallel-for directive at loop x with collapse c, teams
+ *        distribute with collapse d, schedule s (0 static, 1 dynamic,
+ *        2 guided); x = d = s = 0 is the combined teams-distribute-parallel-
+ *        for with collapse c, so p = c there. T teams, H threads per team,
+ *        m_a the map clause of array a (same codes as req_a)
  *      offsets [n_kernels + 1]: variants of kernel k are rows
  *        offsets[k] .. offsets[k+1]-1; offsets[0] = 0, offsets[n_kernels] =
  *        n_variants, non-decreasing (empty segments allowed).
@@ -145,18 +148,28 @@ int advisor_model_get_fp8_scales(const advisor_model *model, float *wscale, floa
  * invalid_out (device, uint8 [n_variants]) is not NULL, invalid_out[i] = 1
  * for an invalid variant (its feature row is all zero) and 0 otherwise.
  * A variant is invalid when its kernel_id is outside [0, n_kernels), its
- * kernel's D, N_i, A, E, s_a, req_a or fpi is out of range, c < 1 or c > D,
- * T < 1, H < 1, or a map clause m_a does not carry the data its class req_a
- * needs (to needs to/tofrom, from needs from/tofrom, tofrom needs tofrom).
- * Integer arithmetic is unsigned 64-bit modulo 2^64, exact while trip-count
- * products times 64 stay below 2^63.
- * Features: 0 D, 1-4 N0..N3, 5 I = prod N_i, 6 c, 7 Pc = prod_{i<c} N_i,
- * 8 R = prod_{i>=c} N_i, 9 T, 10 H, 11 TH = T*H, 12 busy = min(TH, Pc),
- * 13 waves = ceil(Pc/TH), 14 waves*R, 15 waves*TH - Pc, 16 A, 17 E,
+ * kernel's D, N_i, A, E, s_a, req_a or fpi is out of range, T < 1, H < 1,
+ * its parallel structure is not one of section 4.1.3 (p < 0 or s > 2; at
+ * x = 0: d != 0 or c outside 1..D; at x >= 1: x >= D, d outside 1..x or c
+ * outside 1..D-x), or a map clause m_a does not carry the data its class
+ * req_a needs (to needs to/tofrom, from needs from/tofrom, tofrom needs
+ * tofrom). Integer arithmetic is unsigned 64-bit modulo 2^64, exact while
+ * trip-count products times 64 stay below 2^63.
+ * Features: 0 D, 1-4 N0..N3, 5 I = prod N_i, 6 loops collapsed into parallel
+ * work, 7 Pc parallel iterations, 8 R = I / Pc serial iterations per
+ * parallel one, 9 T, 10 H, 11 TH = T*H, 12 busy threads, 13 waves rounds of
+ * parallel work per thread, 14 waves*R, 15 waves*TH - Pc, 16 A, 17 E,
  * 18 S = E*I, 19-22 arrays mapped to / from / tofrom / alloc,
  * 23 h2d = S*(n_to + n_tofrom), 24 d2h = S*(n_from + n_tofrom),
  * 25 h2d + d2h, 26 ns = number of strided arrays, 27 S*A,
  * 28 S*(A - ns) + (64/E)*S*ns, 29 fpi*I, 30 fpi, 31 S*n_alloc.
+ * At x = 0 (combined directive over loops 0..c-1): feature 6 = c,
+ * Pc = prod_{i<c} N_i, busy = min(TH, Pc), waves = ceil(Pc/TH). At x >= 1
+ * (teams over loops 0..d-1: Pt = prod_{i<d} N_i; a team's threads over loops
+ * x..x+c-1: Pf = prod_{x<=i<x+c} N_i): feature 6 = d + c, Pc = Pt*Pf,
+ * busy = min(T, Pt)*min(H, Pf), waves = ceil(Pt/T)*ceil(Pf/H). The schedule
+ * enters no feature: the paper's printed predictions come in groups of
+ * identical values, as variants differing only in such a choice would.
  */
 int advisor_featurize(const int64_t *kdesc, const int64_t *vdesc, int64_t n_kernels,
                       int64_t n_variants, int64_t *feat_out, uint8_t *invalid_out, void *stream);
@@ -409,6 +422,27 @@ int advisor_enumerate_variants(const int64_t *n_loops, const int64_t *offsets, i
                                void *stream);
 
 /*
+ * Generated variants as the cost model's descriptors, so that they go
+ * through featurize -> network -> per-kernel selection (section 3's
+ * prediction flow over section 4.1.3's variants). variants (device, int64
+ * [n_variants, 6], rows of advisor_enumerate_variants) -> vdesc_out
+ * (device, int64 [n_variants, 8]): [kernel, c + 8 x + 64 d + 512 schedule,
+ * teams, threads, m0, m1, m2, m3]. The generated directives carry no
+ * num_teams or thread_limit clause, so teams and threads (>= 1) are the
+ * launch the target runtime makes by default, stated by the caller. Data
+ * option 0 maps each array with the class kdesc records for it (the data
+ * analysis of section 4.1.2), option 1 maps every array tofrom (the
+ * untransformed code); arrays past the kernel's count get 0. A row whose
+ * kernel id is outside [0, n_kernels) (the -1 padding of a mismatched
+ * enumeration) keeps that id and is an invalid variant for advisor_featurize
+ * and advisor_rank. Variants that differ only in schedule get identical
+ * features (the schedule enters no feature; see advisor_featurize).
+ */
+int advisor_lower_variants(const int64_t *kdesc, const int64_t *variants, int64_t n_kernels,
+                           int64_t n_variants, int64_t teams, int64_t threads, int64_t *vdesc_out,
+                           void *stream);
+
+/*
  * Training (section 5.3: the network is fit to measured runtimes with a
  * squared-error loss; here Adam on the MSE, eq. RMSE squared). Only fp32 and
  * bf16 models train (bf16: bf16 operands, fp32 accumulation, fp32 master
@@ -487,7 +521,7 @@ int advisor_model_load_params(advisor_model *model, const float *w_master, void 
 int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
 
 /*
- * Tile-shape autotuner. The fused kernel is built in up to four tile shapes
+ * Tile-shape autotuner. The fused kernel is built in up to five tile shapes
  * per (precision, width) (rows per tile, waves, passes); advisor_autotune
  * times each on the given ranking workload (2 warm-up calls, then `reps`
  * timed advisor_rank calls on the stream, device buffers as for
@@ -500,7 +534,9 @@ int advisor_model_grads(const advisor_model *model, float *grads_out, void *stre
  * milliseconds (-1 where a shape is not built); *chosen (may be NULL) the
  * chosen shape. Synchronizes the stream and allocates a temporary buffer.
  * Shapes with the same number of waves give bit-identical predictions;
- * otherwise only the order of the output layer's fp32 sum differs.
+ * otherwise only the order of the output layer's fp32 sum differs. Shapes:
+ * 0 largest row tile, 1 half the rows, 2 two workgroups per CU, 3 ping-pong
+ * schedule, 4 128-row tiles with two waves per neuron range.
  */
 int advisor_autotune(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
                      const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int reps,

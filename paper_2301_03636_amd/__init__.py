@@ -14,8 +14,8 @@ from ._lib import (AdvisorError, PRECISIONS, advisor_featurize, advisor_model_cr
                    advisor_rank_plan_create, advisor_train_plan_create, advisor_plan_launch,
                    advisor_plan_destroy, advisor_autotune, advisor_model_set_tile_variant,
                    advisor_model_get_tile_variant, advisor_validate_offsets, advisor_topn_preds,
-                   advisor_rank_topn, advisor_train_step_rmsprop,
-                   advisor_count_variants, advisor_enumerate_variants, advisor_classify_maps,
+                   advisor_rank_topn, advisor_train_step_rmsprop, advisor_step_lr,
+                   advisor_count_variants, advisor_enumerate_variants, advisor_lower_variants, advisor_classify_maps,
                    advisor_rank_multi, advisor_train_plan_create_rmsprop,
                    advisor_train_plan_create_rmsprop_multi)
 from .model import Model, Plan  # noqa: F401

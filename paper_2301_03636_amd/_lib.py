@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libadvisor.so")
+# ADVISOR_LIBRARY names another build of the library to load (the sanitizer run)
+LIB_PATH = os.environ.get("ADVISOR_LIBRARY") or os.path.join(_HERE, "libadvisor.so")
 
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
@@ -94,6 +95,7 @@ def lib():
             "advisor_topn_preds": ([P, P, i64, i64, i32, P, P, P], i32),
             "advisor_rank_topn": ([P, P, P, P, i64, i64, i32, P, P, P, P], i32),
             "advisor_step_lr": ([i64, C.c_double, C.c_double, i64], C.c_double),
+            "advisor_lower_variants": ([P, P, i64, i64, i64, i64, P, P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -417,6 +419,21 @@ def advisor_enumerate_variants(n_loops, sched_mask=7, offsets=None, variants_out
     return offsets, variants_out
 
 
+def advisor_lower_variants(kdesc, variants, teams, threads, vdesc_out=None):
+    """Generated variants (rows of advisor_enumerate_variants) as cost-model
+    descriptor rows [n_v, 8] under the given default launch."""
+    _dev(kdesc, torch.int64, "kdesc")
+    _dev(variants, torch.int64, "variants")
+    nv = variants.shape[0]
+    if vdesc_out is None:
+        vdesc_out = torch.empty((nv, 8), dtype=torch.int64, device=variants.device)
+    _dev(vdesc_out, torch.int64, "vdesc_out")
+    _check(lib().advisor_lower_variants(_ptr(kdesc), _ptr(variants), kdesc.shape[0], nv,
+                                        int(teams), int(threads), _ptr(vdesc_out), _stream()),
+           "advisor_lower_variants")
+    return vdesc_out
+
+
 def _topn_outputs(nk, top_n, idx_out, val_out, device):
     if idx_out is None:
         idx_out = torch.empty((nk, top_n), dtype=torch.int64, device=device)
@@ -655,7 +672,7 @@ def advisor_plan_destroy(p):
 # --------------------------------------------------------------------------- autotuner
 
 
-def advisor_autotune(h, kdesc, vdesc, offsets, reps=5, max_variants=4):
+def advisor_autotune(h, kdesc, vdesc, offsets, reps=5, max_variants=5):
     for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
         _dev(t, torch.int64, nm)
     times = np.zeros(max_variants)

@@ -28,6 +28,11 @@ struct Feat {
 
 // Reads the variant row v (8 int64) and, if its kernel id is in range, the
 // kernel row. Returns false and zeroes the features for an invalid variant.
+// Column 1 is the parallel structure c + 8 x + 64 d + 512 s of section 4.1.3
+// (parallel for at loop x with collapse c, teams-distribute collapse d,
+// schedule s): x = 0 is the combined directive over loops 0 .. c-1; at
+// x >= 1 the teams share loops 0 .. d-1 and each team's threads loops
+// x .. x+c-1, the loops between and after running serially.
 __device__ __forceinline__ bool featurize_one(const int64_t *__restrict__ kdesc,
                                               const int64_t *__restrict__ vrow, int64_t n_k,
                                               Feat &out)
@@ -36,7 +41,8 @@ __device__ __forceinline__ bool featurize_one(const int64_t *__restrict__ kdesc,
     for (int j = 0; j < NFEAT; ++j) out.f[j] = 0;
     const longlong2 *v2 = reinterpret_cast<const longlong2 *>(vrow);
     longlong2 va = v2[0], vb = v2[1], vc = v2[2], vd = v2[3];
-    const int64_t kid = va.x, c = va.y, T = vb.x, H = vb.y;
+    const int64_t kid = va.x, cf = va.y, T = vb.x, H = vb.y;
+    const int64_t c = cf & 7, x = (cf >> 3) & 7, d = (cf >> 6) & 7, sch = cf >> 9;
     const int64_t m[4] = {vc.x, vc.y, vd.x, vd.y};
     if (kid < 0 || kid >= n_k) return false;
     const longlong2 *k2 = reinterpret_cast<const longlong2 *>(kdesc + kid * KD);
@@ -49,7 +55,8 @@ __device__ __forceinline__ bool featurize_one(const int64_t *__restrict__ kdesc,
     }
     const int64_t D = k[0], A = k[5], E = k[6], fpi = k[11];
     bool ok = D >= 1 && D <= 4 && A >= 0 && A <= 4 && E >= 1 && E <= 64 && fpi >= 0 &&
-              c >= 1 && c <= D && T >= 1 && H >= 1;
+              T >= 1 && H >= 1 && cf >= 0 && sch <= 2 && c >= 1 &&
+              (x == 0 ? (d == 0 && c <= D) : (x < D && d >= 1 && d <= x && c <= D - x));
 #pragma unroll
     for (int i = 0; i < 4; ++i) ok = ok && k[1 + i] >= 1 && (i < D || k[1 + i] == 1);
 #pragma unroll
@@ -59,15 +66,38 @@ __device__ __forceinline__ bool featurize_one(const int64_t *__restrict__ kdesc,
 
     const uint64_t N0 = k[1], N1 = k[2], N2 = k[3], N3 = k[4];
     const uint64_t I = N0 * N1 * N2 * N3;
-    // collapsed loops 0..c-1 form the parallel space, the rest run serially
-    uint64_t Pc = N0, R = N1 * N2 * N3;
-    if (c >= 2) { Pc *= N1; R = N2 * N3; }
-    if (c >= 3) { Pc *= N2; R = N3; }
-    if (c >= 4) { Pc *= N3; R = 1; }
     const uint64_t TH = (uint64_t)T * (uint64_t)H;
-    const uint64_t busy = TH < Pc ? TH : Pc;
-    const uint64_t q = Pc / TH;
-    const uint64_t waves = q + (Pc - q * TH != 0);
+    uint64_t Pc, R, busy, waves, npar;
+    if (x == 0) {
+        // collapsed loops 0..c-1 form the parallel space, the rest run serially
+        Pc = N0;
+        R = N1 * N2 * N3;
+        if (c >= 2) { Pc *= N1; R = N2 * N3; }
+        if (c >= 3) { Pc *= N2; R = N3; }
+        if (c >= 4) { Pc *= N3; R = 1; }
+        busy = TH < Pc ? TH : Pc;
+        const uint64_t q = Pc / TH;
+        waves = q + (Pc - q * TH != 0);
+        npar = c;
+    } else {
+        // teams over loops 0..d-1, a team's threads over loops x..x+c-1
+        const uint64_t Nv[4] = {N0, N1, N2, N3};
+        uint64_t Pt = 1, Pf = 1;
+        R = 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool team = i < d, thr = i >= x && i < x + c;
+            Pt *= team ? Nv[i] : 1;
+            Pf *= thr ? Nv[i] : 1;
+            R *= (team || thr) ? 1 : Nv[i];
+        }
+        Pc = Pt * Pf;
+        const uint64_t T64 = (uint64_t)T, H64 = (uint64_t)H;
+        busy = (T64 < Pt ? T64 : Pt) * (H64 < Pf ? H64 : Pf);
+        const uint64_t qt = Pt / T64, qf = Pf / H64;
+        waves = (qt + (Pt - qt * T64 != 0)) * (qf + (Pf - qf * H64 != 0));
+        npar = d + c;
+    }
     const uint64_t S = (uint64_t)E * I;
     // arrays per map clause and strided arrays (no indexed register arrays)
     uint64_t c_alloc = 0, c_to = 0, c_from = 0, c_tofrom = 0, ns = 0;
@@ -89,7 +119,7 @@ __device__ __forceinline__ bool featurize_one(const int64_t *__restrict__ kdesc,
     f[0] = D;
     f[1] = N0; f[2] = N1; f[3] = N2; f[4] = N3;
     f[5] = I;
-    f[6] = c;
+    f[6] = npar;
     f[7] = Pc;
     f[8] = R;
     f[9] = T;

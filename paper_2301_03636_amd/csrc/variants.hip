@@ -178,11 +178,66 @@ int check_variant_args(const int64_t *n_loops, int64_t n_k, int sched_mask)
     return ADVISOR_OK;
 }
 
+// A generated variant as a cost-model descriptor row (one thread per row):
+// [k, x, d, c, s, data] -> [k, c + 8 x + 64 d + 512 s, teams, threads, maps],
+// the maps being the kernel's analysed classes (data option 0) or tofrom for
+// every array (option 1), 0 past the kernel's arrays. A row whose kernel id
+// is out of range keeps that id (the featurizer marks it invalid).
+__global__ __launch_bounds__(VG_THREADS) void vg_lower_kernel(
+    const int64_t *__restrict__ kdesc, const int64_t *__restrict__ gen, int64_t n_k, int64_t n_v,
+    int64_t teams, int64_t threads, int64_t *__restrict__ vdesc)
+{
+    const int64_t i = (int64_t)blockIdx.x * VG_THREADS + threadIdx.x;
+    if (i >= n_v) return;
+    const int64_t *g = gen + i * ADVISOR_VARIANT_COLS;
+    const int64_t k = g[0], x = g[1], d = g[2], c = g[3], sch = g[4], data = g[5];
+    longlong2 r0, r1, r2, r3;
+    r0.x = k;
+    r0.y = c + 8 * x + 64 * d + 512 * sch;
+    r1.x = teams;
+    r1.y = threads;
+    int64_t m[4] = {0, 0, 0, 0};
+    if (k >= 0 && k < n_k) {
+        const int64_t *kd = kdesc + k * KD;
+        const int64_t A = kd[5];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) m[a] = a < A ? (data == 0 ? kd[12 + a] : 3) : 0;
+    }
+    r2.x = m[0];
+    r2.y = m[1];
+    r3.x = m[2];
+    r3.y = m[3];
+    longlong2 *out = reinterpret_cast<longlong2 *>(vdesc + i * VD);
+    out[0] = r0;
+    out[1] = r1;
+    out[2] = r2;
+    out[3] = r3;
+}
+
 }  // namespace
 
 }  // namespace adv
 
 using namespace adv;
+
+extern "C" int advisor_lower_variants(const int64_t *kdesc, const int64_t *variants,
+                                      int64_t n_kernels, int64_t n_variants, int64_t teams,
+                                      int64_t threads, int64_t *vdesc_out, void *stream)
+{
+    clear_error();
+    if (n_kernels < 0 || n_variants < 0) return fail(ADVISOR_ESHAPE, "negative size");
+    if (n_variants >= (int64_t)1 << 32) return fail(ADVISOR_ESHAPE, "n_variants must be < 2^32");
+    if (teams < 1 || threads < 1) return fail(ADVISOR_EINVAL, "teams and threads must be >= 1");
+    if (n_variants == 0) return ADVISOR_OK;
+    if (!variants || !vdesc_out || (n_kernels > 0 && !kdesc))
+        return fail(ADVISOR_EINVAL, "advisor_lower_variants: null pointer");
+    const int64_t blocks = (n_variants + VG_THREADS - 1) / VG_THREADS;
+    hipLaunchKernelGGL(vg_lower_kernel, dim3((unsigned)blocks), dim3(VG_THREADS), 0,
+                       as_stream(stream), kdesc, variants, n_kernels, n_variants, teams, threads,
+                       vdesc_out);
+    ADV_LAUNCHED("vg_lower_kernel");
+    return ADVISOR_OK;
+}
 
 extern "C" int advisor_count_variants(const int64_t *n_loops, int64_t n_kernels, int sched_mask,
                                       int64_t *offsets_out, void *stream)
