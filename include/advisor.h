@@ -521,7 +521,7 @@ int advisor_model_load_params(advisor_model *model, const float *w_master, void 
 int advisor_model_grads(const advisor_model *model, float *grads_out, void *stream);
 
 /*
- * Tile-shape autotuner. The fused kernel is built in up to five tile shapes
+ * Tile-shape autotuner. The fused kernel is built in up to four tile shapes
  * per (precision, width) (rows per tile, waves, passes); advisor_autotune
  * times each on the given ranking workload (2 warm-up calls, then `reps`
  * timed advisor_rank calls on the stream, device buffers as for
@@ -536,7 +536,7 @@ int advisor_model_grads(const advisor_model *model, float *grads_out, void *stre
  * Shapes with the same number of waves give bit-identical predictions;
  * otherwise only the order of the output layer's fp32 sum differs. Shapes:
  * 0 largest row tile, 1 half the rows, 2 two workgroups per CU, 3 ping-pong
- * schedule, 4 128-row tiles with two waves per neuron range.
+ * schedule.
  */
 int advisor_autotune(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
                      const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int reps,

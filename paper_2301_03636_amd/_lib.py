@@ -672,7 +672,7 @@ def advisor_plan_destroy(p):
 # --------------------------------------------------------------------------- autotuner
 
 
-def advisor_autotune(h, kdesc, vdesc, offsets, reps=5, max_variants=5):
+def advisor_autotune(h, kdesc, vdesc, offsets, reps=5, max_variants=4):
     for t, nm in ((kdesc, "kdesc"), (vdesc, "vdesc"), (offsets, "offsets")):
         _dev(t, torch.int64, nm)
     times = np.zeros(max_variants)

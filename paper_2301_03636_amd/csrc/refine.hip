@@ -73,6 +73,7 @@ CascadeLayout cascade_layout(int64_t n_v, int64_t n_k, const int *keep, int n_st
 }
 
 constexpr int RF_WAVES = 4;
+constexpr int RF_UNROLL = 16;
 
 // order-preserving key of (prediction, row): smaller prediction first, then
 // lower row; -0 equals +0
@@ -111,17 +112,29 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
     uint64_t top[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) top[q] = ~0ull;
-    for (int64_t i = lo + lane; i < hi; i += 64) {
-        const float p = pred[i];
-        if (__builtin_isnan(p)) continue;
-        uint64_t x = rf_key(p, (uint32_t)i);
-        // insertion into the sorted list (compile-time indices only)
+    // RF_UNROLL loads per lane in flight per pass (a segment of up to
+    // 64 * RF_UNROLL variants in one round trip), then their insertions
+    for (int64_t base = lo + lane; base < hi; base += 64 * RF_UNROLL) {
+        float pv[RF_UNROLL];
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            const uint64_t t = top[q];
-            const bool less = x < t;
-            top[q] = less ? x : t;
-            x = less ? t : x;
+        for (int u = 0; u < RF_UNROLL; ++u) {
+            const int64_t i = base + 64 * u;
+            pv[u] = i < hi ? pred[i] : __builtin_nanf("");
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < RF_UNROLL; ++u) {
+            if (__builtin_isnan(pv[u])) continue;
+            uint64_t x = rf_key(pv[u], (uint32_t)(base + 64 * u));
+            if (x >= top[K - 1]) continue;
+            // insertion into the sorted list (compile-time indices only)
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const uint64_t t = top[q];
+                const bool less = x < t;
+                top[q] = less ? x : t;
+                x = less ? t : x;
+            }
         }
     }
     // K rounds: the wave-wide minimum of the lanes' heads (the same value in

@@ -171,10 +171,26 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
     return ab < cd ? ab : cd;
 }
 
-// loads in flight per lane in the selection kernels' scans
-constexpr int SEL_UNROLL = 4;
+// Loads in flight per lane in the selection kernels' scans: a segment of up
+// to 64 * SEL_UNROLL = 1024 variants is read in one round trip (the loads of
+// a pass are all issued before the first compare), so a wave's time is one
+// latency of its offsets and one of its predictions rather than a chain.
+constexpr int SEL_UNROLL = 16;
 
 constexpr int AM_WAVES = 4;
+
+// The predictions pred[base + 64 u] (u < SEL_UNROLL) of one pass, NaN past hi.
+__device__ __forceinline__ void load_pass(const float *__restrict__ pred, int64_t base, int64_t hi,
+                                          float (&p)[SEL_UNROLL])
+{
+#pragma unroll
+    for (int u = 0; u < SEL_UNROLL; ++u) {
+        const int64_t i = base + 64 * u;
+        p[u] = i < hi ? pred[i] : __builtin_nanf("");
+    }
+    // keep every load of the pass ahead of the compares that use them
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
     const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
@@ -182,22 +198,15 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
 {
     const int lane = threadIdx.x & 63;
     const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
-    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + (threadIdx.x >> 6); k < n_k;
-         k += nwaves_total) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + wave; k < n_k; k += nwaves_total) {
         // clamp to the prediction array so malformed offsets cannot read out of bounds
         const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
         const int64_t hi = max(lo, min(offsets[k + 1], n_v));
         uint64_t key = ~0ull;
         for (int64_t base = lo + lane; base < hi; base += 64 * SEL_UNROLL) {
             float p[SEL_UNROLL];
-#pragma unroll
-            for (int u = 0; u < SEL_UNROLL; ++u) {
-                // unconditional loads at a clamped index (hi > base >= 0),
-                // so all of them are in flight before the first compare
-                const int64_t i = base + 64 * u;
-                const float v = pred[i < hi ? i : hi - 1];
-                p[u] = i < hi ? v : __builtin_nanf("");
-            }
+            load_pass(pred, base, hi, p);
 #pragma unroll
             for (int u = 0; u < SEL_UNROLL; ++u) {
                 if (!__builtin_isnan(p[u])) {
@@ -226,8 +235,8 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
 {
     const int lane = threadIdx.x & 63;
     const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
-    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + (threadIdx.x >> 6); k < n_k;
-         k += nwaves_total) {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + wave; k < n_k; k += nwaves_total) {
         const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
         const int64_t hi = max(lo, min(offsets[k + 1], n_v));
         uint64_t top[K];
@@ -235,14 +244,7 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
         for (int q = 0; q < K; ++q) top[q] = ~0ull;
         for (int64_t base = lo + lane; base < hi; base += 64 * SEL_UNROLL) {
             float p[SEL_UNROLL];
-#pragma unroll
-            for (int u = 0; u < SEL_UNROLL; ++u) {
-                // unconditional loads at a clamped index (hi > base >= 0),
-                // so all of them are in flight before the first compare
-                const int64_t i = base + 64 * u;
-                const float v = pred[i < hi ? i : hi - 1];
-                p[u] = i < hi ? v : __builtin_nanf("");
-            }
+            load_pass(pred, base, hi, p);
 #pragma unroll
             for (int u = 0; u < SEL_UNROLL; ++u) {
                 if (__builtin_isnan(p[u])) continue;
