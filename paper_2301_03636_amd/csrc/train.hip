@@ -1227,9 +1227,7 @@ extern "C" double advisor_step_lr(int64_t epoch, double lr0, double gamma, int64
         fail(ADVISOR_EINVAL, "advisor_step_lr: need epoch >= 0, every >= 1, lr0 > 0, 0 < gamma <= 1");
         return __builtin_nan("");
     }
-    double lr = lr0;
-    for (int64_t k = epoch / every; k > 0; --k) lr *= gamma;
-    return lr;
+    return lr0 * pow(gamma, (double)(epoch / every));
 }
 
 // Replace the fp32 master parameters from a device buffer (for optimizers

@@ -215,6 +215,8 @@ def test_step_lr_schedule_from_the_library():
     assert np.isclose(adv.step_lr(30), 1e-3, rtol=1e-15, atol=0)
     assert np.isclose(adv.step_lr(149), 1e-6, rtol=1e-14, atol=0)
     assert adv.step_lr(59, lr0=0.5, gamma=0.5, every=20) == 0.125
+    import oracle
+    assert all(adv.step_lr(e) == oracle.step_lr(e) for e in range(300))
     for bad in ((-1, 1e-2, 0.1, 30), (0, 0.0, 0.1, 30), (0, 1e-2, 1.5, 30), (0, 1e-2, 0.1, 0)):
         with pytest.raises(adv.AdvisorError):
             adv.step_lr(*bad)
