@@ -113,7 +113,9 @@ struct TileLaunch {
     static constexpr int NW = S::NW;
     static constexpr int NS = S::NS;
     using C = TileCfg<P, W, M, NW, NS,
-                      SRC == SRC_DESC && SINK != SINK_GROUP && tile_vdesc_prefetch<P, W, M, NW>()>;
+                      SRC == SRC_DESC && SINK != SINK_GROUP && tile_vdesc_prefetch<P, W, M, NW>(),
+                      SINK != SINK_GROUP && SINK != SINK_TRAIN && !S::PP &&
+                          tile_bias_lds<P, W, M, NW>()>;
     static constexpr auto kern = TileKernel<S, P, W, SRC, SINK>::kern;
     static inline std::once_flag once;
     static inline int blocks_per_cu = 1;

@@ -170,7 +170,7 @@ __device__ __forceinline__ void save_elem(void *base, int64_t idx, float v)
         reinterpret_cast<__bf16 *>(base)[idx] = (__bf16)v;
 }
 
-template <int P, int W, int M, int NWAVES, int NSPLIT_ = 1, bool VPF_ = false>
+template <int P, int W, int M, int NWAVES, int NSPLIT_ = 1, bool VPF_ = false, bool BL_ = false>
 struct TileCfg {
     static constexpr int NSPLIT = NSPLIT_;                 // passes over a wave's neurons
     using G = Geo<P>;
@@ -196,8 +196,13 @@ struct TileCfg {
     // the output-layer weights
     static constexpr bool VPF = VPF_;
     static constexpr size_t VST_BYTES = VPF ? (size_t)M * 64 : 0;
-    static constexpr size_t HW_BYTES = VPF ? (size_t)W * 4 : 0;
-    static constexpr size_t LDS = LDS_BASE + VST_BYTES + HW_BYTES;
+    // bias staging (BL): every hidden layer's bias and the output-layer
+    // weights copied into LDS once per workgroup, for epilogues that add the
+    // bias after the products (fp8)
+    static constexpr bool BL = BL_;
+    static constexpr size_t HW_BYTES = (VPF || BL) ? (size_t)W * 4 : 0;
+    static constexpr size_t BIAS_BYTES = BL ? (size_t)(MAX_LAYERS - 1) * W * 4 : 0;
+    static constexpr size_t LDS = LDS_BASE + VST_BYTES + HW_BYTES + BIAS_BYTES;
     static_assert(M % 32 == 0 && (M * XS) % 16 == 0 && ACT_BYTES % 16 == 0, "LDS alignment");
     static_assert(LDS <= 160 * 1024, "tile does not fit the 160 KiB of LDS");
 };
@@ -235,6 +240,23 @@ constexpr bool tile_vdesc_prefetch()
     constexpr int r = by_regs < 1 ? 1 : by_regs;
     constexpr int b0 = (int)((160 * 1024) / base), b1 = (int)((160 * 1024) / (base + extra));
     return P != PREC_FP8 && base + extra <= 160 * 1024 && (b0 < r ? b0 : r) == (b1 < r ? b1 : r);
+}
+
+// Whether an fp8 tile kernel stages its biases and output-layer weights in
+// LDS (their epilogues read the bias after the products): only where that
+// leaves the workgroups per CU unchanged.
+template <int P, int W, int M, int NWAVES>
+constexpr bool tile_bias_lds()
+{
+    constexpr int xs = 32 * Geo<FirstP<P>::value>::EB + Geo<FirstP<P>::value>::PAD;
+    constexpr int as = W * Geo<P>::EB + Geo<P>::PAD;
+    constexpr int wn = W / 32 < NWAVES ? W / 32 : NWAVES;
+    constexpr size_t base = (size_t)M * xs + (size_t)M * as + (size_t)wn * M * 4 + M * 8;
+    constexpr size_t extra = (size_t)W * 4 + (size_t)(MAX_LAYERS - 1) * W * 4;
+    constexpr int by_regs = tile_waves_per_simd<P, W, M, NWAVES>() * 4 / NWAVES;
+    constexpr int r = by_regs < 1 ? 1 : by_regs;
+    constexpr int b0 = (int)((160 * 1024) / base), b1 = (int)((160 * 1024) / (base + extra));
+    return P == PREC_FP8 && base + extra <= 160 * 1024 && (b0 < r ? b0 : r) == (b1 < r ? b1 : r);
 }
 
 // 16-byte-aligned LDS vector load (an fp8 vector is two 16-byte halves).
@@ -776,7 +798,9 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
     constexpr int SK = SINK == SINK_GROUP ? SINK_RANK : SINK;
     constexpr bool VPF = SRC == SRC_DESC && SINK != SINK_GROUP &&
                          tile_vdesc_prefetch<P, W, M, NWAVES>();
-    using C = TileCfg<P, W, M, NWAVES, NSPLIT, VPF>;
+    constexpr bool BL = SINK != SINK_GROUP && SINK != SINK_TRAIN &&
+                        tile_bias_lds<P, W, M, NWAVES>();
+    using C = TileCfg<P, W, M, NWAVES, NSPLIT, VPF, BL>;
     using G = typename C::G;
     constexpr int P0 = FirstP<P>::value;
     using G0 = Geo<P0>;
@@ -787,7 +811,8 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
     int *meta_ok = reinterpret_cast<int *>(hpart + C::WN * M);  // [M]
     int *meta_kid = meta_ok + M;                                // [M]
     unsigned char *vst = lds + C::LDS_BASE;                     // [M][64 B] (VPF)
-    float *hw_lds = reinterpret_cast<float *>(vst + C::VST_BYTES);  // [W] (VPF)
+    float *hw_lds = reinterpret_cast<float *>(vst + C::VST_BYTES);  // [W] (VPF or BL)
+    float *bias_lds = hw_lds + (C::HW_BYTES / 4);               // [MAX_LAYERS - 1][W] (BL)
 
     const int tid0 = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid0 >> 6);
@@ -841,6 +866,12 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
         for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = args.net.head_w[i];
         if ((int64_t)blockIdx.x < ntiles) issue_vdesc(blockIdx.x);
     }
+    if constexpr (BL) {
+        // read before the first tile's barriers, which order them for every wave
+        for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = args.net.head_w[i];
+        for (int l = 0; l < args.net.n_hidden; ++l)
+            for (int i = tid; i < W; i += C::THREADS) bias_lds[l * W + i] = args.net.b[l][i];
+    }
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row0 = tile * M;
@@ -885,9 +916,9 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                 const float qinv = net.qinv[l];
                 typename Held<P>::T held[C::NSPLIT > 1 ? C::NSPLIT - 1 : 1][C::NBP][4][C::MBW];
                 float srow[C::MBW];
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < C::MBW; ++j) srow[j] = 0.0f;
-    #pragma unroll
+#pragma unroll
                 for (int ps = 0; ps < C::NSPLIT; ++ps) {
                     const int nbp0 = nb0 + ps * C::NBP;
                     const bool final_pass = ps + 1 == C::NSPLIT;
@@ -925,13 +956,13 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                     constexpr bool keep_last = SINK == SINK_TRAIN;
                     if (final_pass && (!last || keep_last)) {
                         if (l > 0) __syncthreads();  // every wave finished reading this layer's input
-    #pragma unroll
+#pragma unroll
                         for (int hp = 0; hp + 1 < C::NSPLIT; ++hp)
-    #pragma unroll
+#pragma unroll
                             for (int i = 0; i < C::NBP; ++i)
-    #pragma unroll
+#pragma unroll
                                 for (int j = 0; j < C::MBW; ++j)
-    #pragma unroll
+#pragma unroll
                                     for (int g = 0; g < 4; ++g) {
                                         const int nn = (nb0 + hp * C::NBP + i) * 32 + 8 * g + 4 * half;
                                         const int m = (mb0 + j) * 32 + col;
@@ -941,26 +972,28 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                     // one 32-neuron block at a time: its bias (and output-layer
                     // weight) vectors are loaded together, and the fence keeps the
                     // next block's loads from being hoisted
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < C::NBP; ++i) {
                         v4f bias_r[4], hw_r[4];
-    #pragma unroll
+#pragma unroll
                         for (int g = 0; g < 4; ++g) {
                             const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
-                            if (scaled) bias_r[g] = *reinterpret_cast<const v4f *>(bias + nn);
+                            if (scaled)
+                                bias_r[g] = BL ? *reinterpret_cast<const v4f *>(bias_lds + l * W + nn)
+                                               : *reinterpret_cast<const v4f *>(bias + nn);
                             if (last)
-                                hw_r[g] = VPF ? *reinterpret_cast<const v4f *>(hw_lds + nn)
-                                              : *reinterpret_cast<const v4f *>(net.head_w + nn);
+                                hw_r[g] = (VPF || BL) ? *reinterpret_cast<const v4f *>(hw_lds + nn)
+                                                      : *reinterpret_cast<const v4f *>(net.head_w + nn);
                         }
-    #pragma unroll
+#pragma unroll
                         for (int j = 0; j < C::MBW; ++j) {
                             const int m = (mb0 + j) * 32 + col;
                             uint32_t mbits = 0;  // training: ReLU mask of this lane's 16 neurons
-    #pragma unroll
+#pragma unroll
                             for (int g = 0; g < 4; ++g) {
                                 const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
                                 v4f v;
-    #pragma unroll
+#pragma unroll
                                 for (int e = 0; e < 4; ++e) {
                                     const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
                                                            : acc[i][j][4 * g + e];
@@ -976,7 +1009,7 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                                     uint32_t nib;
                                     if constexpr (P == PREC_FP32) {
                                         nib = 0;
-    #pragma unroll
+#pragma unroll
                                         for (int e = 0; e < 4; ++e)
                                             nib |= min(__float_as_uint(hv[e]), 1u) << e;
                                     } else {
@@ -990,7 +1023,7 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                                 }
                                 if (last) {
                                     // output layer: fixed order over blocks, groups, elements
-    #pragma unroll
+#pragma unroll
                                     for (int e = 0; e < 4; ++e) srow[j] += v[e] * hw_r[g][e];
                                 }
                                 if (!last || keep_last) {
@@ -1021,7 +1054,7 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                             args.save_ld, row0, n, tid);
                 }
                 if (last) {
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < C::MBW; ++j) {
                         float sj = srow[j];
                         sj += __shfl_xor(sj, 32, 64);  // the two lane halves hold different neurons
