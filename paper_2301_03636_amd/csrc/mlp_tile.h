@@ -869,8 +869,10 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
     if constexpr (BL) {
         // read before the first tile's barriers, which order them for every wave
         for (int i = tid; i < W; i += C::THREADS) hw_lds[i] = args.net.head_w[i];
-        for (int l = 0; l < args.net.n_hidden; ++l)
-            for (int i = tid; i < W; i += C::THREADS) bias_lds[l * W + i] = args.net.b[l][i];
+        for (int l = 0; l < args.net.n_hidden; ++l) {
+            const float sc = l + 1 < args.net.n_hidden ? args.net.qinv[l] : 1.0f;
+            for (int i = tid; i < W; i += C::THREADS) bias_lds[l * W + i] = args.net.b[l][i] * sc;
+        }
     }
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -993,6 +995,30 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                             for (int g = 0; g < 4; ++g) {
                                 const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
                                 v4f v;
+                                if constexpr (BL) {
+                                    if (!last) {
+                                        // quantized output in one step: the product and
+                                        // bias already in the next layer's activation
+                                        // scale, clamped to [0, 448] (ReLU and saturation)
+                                        const float sq = scaled ? qs * qinv : qinv;
+#pragma unroll
+                                        for (int e = 0; e < 4; ++e) {
+                                            const float a = acc[i][j][4 * g + e];
+                                            v[e] = __builtin_amdgcn_fmed3f(
+                                                scaled ? __builtin_fmaf(a, sq, bias_r[g][e]) : a * sq,
+                                                0.0f, 448.0f);
+                                        }
+                                        const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+                                        const uint32_t q = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
+                                        if (final_pass)
+                                            store_held<P>(act + (size_t)m * C::AS, nn,
+                                                          *reinterpret_cast<const typename Held<P>::T *>(&q));
+                                        else
+                                            held[final_pass ? 0 : ps][i][g][j] =
+                                                *reinterpret_cast<const typename Held<P>::T *>(&q);
+                                        continue;
+                                    }
+                                }
 #pragma unroll
                                 for (int e = 0; e < 4; ++e) {
                                     const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
