@@ -481,6 +481,21 @@ __device__ __forceinline__ void store4(unsigned char *row, int n, v4f v, float q
     store_held<P>(row, n, pack4<P>(v, qinv));
 }
 
+// An fp8 layer's output that feeds another fp8 layer, quantized in one step:
+// with sq = qs / s_next (or 1 / s_next for the unscaled first layer) and the
+// bias bq already divided by s_next, the e4m3 codes of
+// clamp(acc * sq + bq, 0, 448) (ReLU and saturation in one clamp).
+__device__ __forceinline__ uint32_t quant4_fp8(v4f acc, bool scaled, float sq, v4f bq)
+{
+    v4f v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        v[e] = __builtin_amdgcn_fmed3f(scaled ? __builtin_fmaf(acc[e], sq, bq[e]) : acc[e] * sq, 0.0f,
+                                       448.0f);
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
+}
+
 // Transposed access to a tile's activations: an LDS tile is row-major
 // ([M][W], rows of stride AS), the saved layouts are neuron-major
 // (dst[n * ld + row], rows contiguous). The work unit of a thread is four
@@ -995,27 +1010,22 @@ mlp_tiles_kernel(typename KernelArgs<SINK>::type kargs)
                             for (int g = 0; g < 4; ++g) {
                                 const int nn = (nbp0 + i) * 32 + 8 * g + 4 * half;
                                 v4f v;
-                                if constexpr (BL) {
+                                if constexpr (P == PREC_FP8) {
                                     if (!last) {
-                                        // quantized output in one step: the product and
-                                        // bias already in the next layer's activation
-                                        // scale, clamped to [0, 448] (ReLU and saturation)
-                                        const float sq = scaled ? qs * qinv : qinv;
+                                        // the next fp8 layer's input in one step; the
+                                        // staged biases are already divided by its scale
+                                        v4f a, bq;
 #pragma unroll
                                         for (int e = 0; e < 4; ++e) {
-                                            const float a = acc[i][j][4 * g + e];
-                                            v[e] = __builtin_amdgcn_fmed3f(
-                                                scaled ? __builtin_fmaf(a, sq, bias_r[g][e]) : a * sq,
-                                                0.0f, 448.0f);
+                                            a[e] = acc[i][j][4 * g + e];
+                                            bq[e] = BL ? bias_r[g][e] : bias_r[g][e] * qinv;
                                         }
-                                        const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
-                                        const uint32_t q = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
+                                        const uint32_t q = quant4_fp8(a, scaled, scaled ? qs * qinv : qinv, bq);
+                                        const typename Held<P>::T hq = *reinterpret_cast<const typename Held<P>::T *>(&q);
                                         if (final_pass)
-                                            store_held<P>(act + (size_t)m * C::AS, nn,
-                                                          *reinterpret_cast<const typename Held<P>::T *>(&q));
+                                            store_held<P>(act + (size_t)m * C::AS, nn, hq);
                                         else
-                                            held[final_pass ? 0 : ps][i][g][j] =
-                                                *reinterpret_cast<const typename Held<P>::T *>(&q);
+                                            held[final_pass ? 0 : ps][i][g][j] = hq;
                                         continue;
                                     }
                                 }
@@ -1209,6 +1219,19 @@ mlp_pp_kernel(TileArgs args)
                 for (int g = 0; g < 4; ++g) {
                     const int nn = (nb0 + i) * 32 + 8 * g + 4 * half;
                     v4f v;
+                    if constexpr (P == PREC_FP8) {
+                        if (!last) {  // as in mlp_tiles_kernel: the same bits
+                            v4f a, bq;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                a[e] = acc[i][j][4 * g + e];
+                                bq[e] = bias_r[g][e] * qinv;
+                            }
+                            const uint32_t q = quant4_fp8(a, scaled, scaled ? qs * qinv : qinv, bq);
+                            store_held<P>(act + (size_t)m * C::AS, nn, q);
+                            continue;
+                        }
+                    }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const float z = scaled ? acc[i][j][4 * g + e] * qs + bias_r[g][e]
