@@ -220,25 +220,115 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
     }
 }
 
+// Ascending bitonic sort of one 64-bit key per lane over the 64 lanes of a
+// wave (lane r ends with the r-th smallest key): 21 compare-exchange steps
+// with the partner lane (lane xor j), whose key arrives as two 32-bit halves.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v, int lane)
+{
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t olo = (uint32_t)__shfl_xor((int)(uint32_t)v, j, 64);
+            const uint32_t ohi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j, 64);
+            const uint64_t o = ((uint64_t)ohi << 32) | olo;
+            // the lower lane of a pair keeps the smaller key in an ascending
+            // run (lane & k clear) and the larger in a descending one
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            v = ((o < v) == keep_min) ? o : v;
+        }
+    }
+    return v;
+}
+
+// The prediction a key was made from (pred_key inverted; -0 comes back as +0).
+__device__ __forceinline__ float key_pred(uint64_t key)
+{
+    const uint32_t u = (uint32_t)(key >> 32);
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
 // The top-N list of the prediction flow (section 3: the predicted runtimes
 // are sorted and the N best variants kept). One wave per kernel segment, in a
-// grid-stride loop over kernels: every lane keeps the K smallest keys it has
-// seen (a sorted list held in registers, compile-time indices only, entered
-// only by keys that beat its current K-th), then N rounds of a wave-wide
-// minimum pop the segment's best keys in ascending order (keys are unique, so
-// exactly one lane pops each). Lane r writes rank r: the variant index and
+// grid-stride loop over kernels. Lane r writes rank r: the variant index and
 // its prediction, or -1 and NaN past the end of the eligible variants.
+//
+// A segment of at most 64 * SEL_UNROLL variants (one load pass) takes the
+// threshold path when K >= 8: every lane's minimum key goes into one wave
+// sort, whose N-th smallest value t bounds the segment's N-th smallest key
+// from above (the N lane minima at or below t are N eligible variants);
+// only keys <= t can rank, and when there are at most 64 of them they are
+// gathered through LDS (each lane's at its rank among the wave's
+// candidates, counted per load slot with a ballot) and one more wave sort
+// puts them in order. Every other segment (longer ones, more than 64
+// candidates, small K): each lane keeps the K smallest keys it has seen (a
+// sorted list held in registers, compile-time indices only, entered only by
+// keys that beat its current K-th), then N rounds of a wave-wide minimum pop
+// the segment's best keys in ascending order (keys are unique, so exactly one
+// lane pops each).
 template <int K>
 __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
     const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
     int64_t n_v, int N, int64_t *__restrict__ idx_out, float *__restrict__ val_out)
 {
+    __shared__ uint64_t cand_lds[AM_WAVES][64];
     const int lane = threadIdx.x & 63;
     const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + wave; k < n_k; k += nwaves_total) {
         const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
         const int64_t hi = max(lo, min(offsets[k + 1], n_v));
+        if constexpr (K >= 8) {
+            if (hi - lo <= 64 * SEL_UNROLL) {  // the same for every lane
+                float p[SEL_UNROLL];
+                load_pass(pred, lo + lane, hi, p);
+                uint64_t x[SEL_UNROLL];
+                uint64_t m = ~0ull;
+#pragma unroll
+                for (int u = 0; u < SEL_UNROLL; ++u) {
+                    x[u] = __builtin_isnan(p[u]) ? ~0ull
+                                                 : pred_key(p[u], (uint32_t)(lo + lane + 64 * u));
+                    m = x[u] < m ? x[u] : m;
+                }
+                const uint64_t t = read_lane_u64(wave_sort_u64(m, lane), N - 1);
+                // no eligible key is ~0 (its high half would be a NaN's)
+                uint64_t mask[SEL_UNROLL];
+                uint32_t total = 0;
+#pragma unroll
+                for (int u = 0; u < SEL_UNROLL; ++u) {
+                    mask[u] = __ballot(x[u] <= t && x[u] != ~0ull);
+                    total += (uint32_t)__popcll(mask[u]);
+                }
+                if (total <= 64) {
+                    uint64_t *slot = cand_lds[wave];
+                    uint32_t at = 0;
+#pragma unroll
+                    for (int u = 0; u < SEL_UNROLL; ++u) {
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(mask[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask[u], 0u));
+                        if ((mask[u] >> lane) & 1ull) slot[at + below] = x[u];
+                        at += (uint32_t)__popcll(mask[u]);
+                    }
+                    // this wave's LDS writes are done before its reads below
+                    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+                    uint64_t v = (uint32_t)lane < total ? slot[lane] : ~0ull;
+                    v = wave_sort_u64(v, lane);
+                    if (lane < N) {
+                        const int64_t s_ = k * N + lane;
+                        const bool some = v != ~0ull;
+                        const int64_t mine = some ? (int64_t)(v & 0xffffffffull) : -1;
+                        idx_out[s_] = mine;
+                        if (val_out) {
+                            // a zero key may stand for -0: read the stored value
+                            float pv = some ? key_pred(v) : __builtin_nanf("");
+                            if (some && pv == 0.0f) pv = pred[mine];
+                            val_out[s_] = pv;
+                        }
+                    }
+                    continue;
+                }
+            }
+        }
         uint64_t top[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) top[q] = ~0ull;

@@ -72,6 +72,37 @@ def test_topn_preds_long_segments(n):
     _check_values(idx, val, pred)
 
 
+@pytest.mark.parametrize("n", [8, 10, 32])
+def test_topn_preds_one_pass_segments(n):
+    """Segments of up to 1024 variants (one load pass: the threshold path for
+    lists of eight or more) against the oracle, with the lengths around the
+    pass boundary, and segments built so that more than 64 variants lie at
+    or below the threshold (the lane-list path takes over): nine lanes full
+    of small values and a tenth whose smallest is larger than all of them,
+    and fewer eligible lanes than N with many eligible variants each."""
+    rng = np.random.default_rng(80 + n)
+    lens = [1, 2, 63, 64, 65, 577, 1023, 1024, 1025, 2048]
+    lens += [int(x) for x in rng.integers(1, 1025, size=300)]
+    segs = [rng.standard_normal(L).astype(np.float32) for L in lens]
+    lane = np.arange(1024) % 64
+    crowd = np.full(1024, 5.0, dtype=np.float32)
+    crowd[lane < 9] = rng.random(int(np.sum(lane < 9))).astype(np.float32)
+    crowd[lane == 9] = 1.0 + rng.random(16).astype(np.float32)
+    segs.append(crowd)
+    few = np.full(1024, np.nan, dtype=np.float32)
+    few[lane < 20] = rng.standard_normal(int(np.sum(lane < 20))).astype(np.float32)
+    segs.append(few)
+    ties = np.round(rng.standard_normal(1000), 1).astype(np.float32)  # many equal values
+    segs.append(ties)
+    pred = np.concatenate(segs)
+    pred[rng.random(pred.size) < 0.02] = np.nan
+    off = np.concatenate([[0], np.cumsum([x.size for x in segs])]).astype(np.int64)
+    say("topn one-pass segments N=%d n_k=%d" % (n, off.size - 1))
+    idx, val = _gpu_topn(pred, off, n)
+    assert np.array_equal(idx, oracle.topn(pred.astype(np.float64), off, n))
+    _check_values(idx, val, pred)
+
+
 def test_topn_preds_summit_worked_example():
     """The 84 printed Summit predictions of the Wilson Dslash variants: the
     predicted top ten, numbered 1..84 in order of measured runtime, with
