@@ -40,6 +40,9 @@ import workload  # noqa: E402
 
 # MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
+# a bf16x3 product is three bf16 matrix-core products: its peak in the
+# network's own flops is a third of bf16's
+PEAK_TFLOPS["bf16x3"] = PEAK_TFLOPS["bf16"] / 3
 PEAK_HBM_GBS = 8000.0
 # Ranking paths timed per workload: name -> (precision of each stage,
 # candidates per kernel handed on by each cut). A single precision is the
@@ -54,7 +57,9 @@ PATHS = {
         "bf16>fp32:8": (("bf16", "fp32"), (8,)),
         "fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
         "fp8>bf16:16>fp32:4": (("fp8", "bf16", "fp32"), (16, 4)),
-        "fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4))},
+        "fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4)),
+        "bf16>bf16x3:4": (("bf16", "bf16x3"), (4,)),
+        "fp8>bf16:32>bf16x3:4": (("fp8", "bf16", "bf16x3"), (32, 4))},
     5: {"fp32": (("fp32",), ()), "bf16": (("bf16",), ()), "fp8": (("fp8",), ()),
         "bf16>fp32:2": (("bf16", "fp32"), (2,)), "bf16>fp32:4": (("bf16", "fp32"), (4,)),
         "fp8>fp32:16": (("fp8", "fp32"), (16,)),
@@ -62,10 +67,12 @@ PATHS = {
         "fp8>bf16:16>fp32:2": (("fp8", "bf16", "fp32"), (16, 2)),
         "fp8>bf16:16>fp32:4": (("fp8", "bf16", "fp32"), (16, 4)),
         "fp8>bf16:32>fp32:2": (("fp8", "bf16", "fp32"), (32, 2)),
-        "fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4))},
+        "fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4)),
+        "fp8>bf16:16>bf16x3:4": (("fp8", "bf16", "bf16x3"), (16, 4)),
+        "fp8>bf16:32>bf16x3:4": (("fp8", "bf16", "bf16x3"), (32, 4))},
 }
 AGREEMENT_BAR = 0.995
-DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}
+DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3", "bf16x3": "bf16x3"}
 WORKLOAD_NAME = {
     1: "single kernel x 256 variants, 32-64-64-1",
     2: "4096 kernels x U[16,1024] variants (2.1M), 32-256x3-1",
@@ -453,7 +460,8 @@ def run_workload(adv, torch, d, cfg, steps, warmup, paths=None):
                     "autotune_ms": [round(t, 4) for t in shape_ms[:4]],
                     "tflops": fl * nv / (kms / 1e3) / 1e12,
                     "roofline_frac": fl * nv / (kms / 1e3) / 1e12 / roofline_peak(widths, p),
-                    "mfma_peak_measured": adv.advisor_mfma_peak(p, iters=100000)}
+                    "mfma_peak_measured": (adv.advisor_mfma_peak(p, iters=100000) if p != "bf16x3"
+                                           else adv.advisor_mfma_peak("bf16", iters=100000) / 3)}
         models[p] = m
     del feat_cal, inv_cal, pred
     results = {}
@@ -476,7 +484,9 @@ def run_workload(adv, torch, d, cfg, steps, warmup, paths=None):
         say("cfg %d %-22s %9.3f ms  %.3e variants/s  agreement %s"
             % (cfg, name, ms, nv / (ms / 1e3), r.get("argmin_agreement")))
     ok = [n for n, r in results.items() if r.get("argmin_agreement", 0.0) >= AGREEMENT_BAR]
-    head = min(ok, key=lambda n: results[n]["ms_per_step"]) if ok else "fp32"
+    # none at the bar (a run restricted to some paths): fp32 if measured, else the fastest
+    fallback = "fp32" if "fp32" in results else min(results, key=lambda n: results[n]["ms_per_step"])
+    head = min(ok, key=lambda n: results[n]["ms_per_step"]) if ok else fallback
     return dict(kd=kd, vd=vd, off=off, kdd=kdd, vdd=vdd, offd=offd, params=params, mu=mu, sd=sd,
                 widths=widths, models=models, results=results, tiles=tiles, head=head, best=best,
                 gold=gold)

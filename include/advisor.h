@@ -60,7 +60,12 @@ enum advisor_status {
 enum advisor_precision {
     ADVISOR_FP32 = 0,      /* fp32 weights and activations, fp32 matrix cores */
     ADVISOR_BF16 = 1,      /* bf16 weights and activations, fp32 accumulation */
-    ADVISOR_FP8_E4M3 = 2   /* OCP e4m3 hidden layers with per-tensor scales, first layer bf16 */
+    ADVISOR_FP8_E4M3 = 2,  /* OCP e4m3 hidden layers with per-tensor scales, first layer bf16 */
+    ADVISOR_BF16X3 = 3     /* fp32 weights and activations as bf16 pairs (high part, rounded
+                              remainder), three bf16 matrix-core products per product
+                              (hi*hi + hi*lo + lo*hi), fp32 accumulation: close to fp32
+                              (each product within about 2^-16 relative) at bf16 matrix-core
+                              speed; inference only (no training entry points) */
 };
 
 #define ADVISOR_NFEAT 32
@@ -536,7 +541,7 @@ int advisor_model_grads(const advisor_model *model, float *grads_out, void *stre
  * Shapes with the same number of waves give bit-identical predictions;
  * otherwise only the order of the output layer's fp32 sum differs. Shapes:
  * 0 largest row tile, 1 half the rows, 2 two workgroups per CU, 3 ping-pong
- * schedule.
+ * schedule. ADVISOR_BF16X3 models are built in shape 0 only.
  */
 int advisor_autotune(advisor_model *model, const int64_t *kdesc, const int64_t *vdesc,
                      const int64_t *offsets, int64_t n_kernels, int64_t n_variants, int reps,

@@ -18,8 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # ADVISOR_LIBRARY names another build of the library to load (the sanitizer run)
 LIB_PATH = os.environ.get("ADVISOR_LIBRARY") or os.path.join(_HERE, "libadvisor.so")
 
-FP32, BF16, FP8_E4M3 = 0, 1, 2
-PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+FP32, BF16, FP8_E4M3, BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "bf16x3": BF16X3}
 NFEAT = 32
 
 _lib = None

@@ -41,8 +41,10 @@ template <int P, int W, int V> struct TileShape;
 template <int P, int W> struct TileShape<P, W, 0> {
     static constexpr bool exists = true;
     static constexpr bool PP = false;
-    static constexpr int M = P == PREC_FP32 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
-                                            : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
+    // bf16x3 tiles hold activations of fp32 size: the fp32 rows per tile
+    static constexpr int M = (P == PREC_FP32 || P == PREC_X3)
+                                 ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
+                                 : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
     static constexpr int NW = (W == 1024 && P == PREC_FP8) ? 4 : 8;
     static constexpr int NS = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1)) : 1;
 };
@@ -181,6 +183,7 @@ bool tile_shape_exists(int precision, int W, int V)
     ADV_EW(PREC_FP32)
     ADV_EW(PREC_BF16)
     ADV_EW(PREC_FP8)
+    ADV_EW(PREC_X3)
 #undef ADV_EW
 #undef ADV_E
     return false;
@@ -192,7 +195,7 @@ int prepare_model_kernels(int precision, int tile_w)
     if (precision == P && tile_w == WW) {                                              \
         int rc = TileLaunch<P, WW, 0, SRC_DESC, SINK_RANK>::setup();                   \
         if (!rc) rc = TileLaunch<P, WW, 0, SRC_FEAT, SINK_PRED>::setup();              \
-        if constexpr (P != PREC_FP8)                                                   \
+        if constexpr (P == PREC_FP32 || P == PREC_BF16)                                \
             if (!rc) rc = TileLaunch<P, WW, 0, SRC_FEAT, SINK_TRAIN>::setup();         \
         if constexpr (TileShape<P, WW, 1>::exists) {                                   \
             if (!rc) rc = TileLaunch<P, WW, 1, SRC_DESC, SINK_RANK>::setup();          \
@@ -212,6 +215,7 @@ int prepare_model_kernels(int precision, int tile_w)
     ADV_PW(PREC_FP32)
     ADV_PW(PREC_BF16)
     ADV_PW(PREC_FP8)
+    ADV_PW(PREC_X3)
 #undef ADV_PW
 #undef ADV_P
     return fail(ADVISOR_EUNSUPPORTED, "no tile kernel for this precision and width");
@@ -235,6 +239,7 @@ int dispatch_tiles(int precision, int W, int variant, const typename KernelArgs<
     ADV_WIDTHS(PREC_FP32)
     ADV_WIDTHS(PREC_BF16)
     ADV_WIDTHS(PREC_FP8)
+    ADV_WIDTHS(PREC_X3)
 #undef ADV_WIDTHS
 #undef ADV_CASE
     return fail(ADVISOR_EUNSUPPORTED, "no tile kernel for this precision and width");

@@ -29,8 +29,14 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef __bf16 v16bf __attribute__((ext_vector_type(16)));
 
-enum { PREC_FP32 = ADVISOR_FP32, PREC_BF16 = ADVISOR_BF16, PREC_FP8 = ADVISOR_FP8_E4M3 };
+enum {
+    PREC_FP32 = ADVISOR_FP32,
+    PREC_BF16 = ADVISOR_BF16,
+    PREC_FP8 = ADVISOR_FP8_E4M3,
+    PREC_X3 = ADVISOR_BF16X3
+};
 enum { SRC_DESC = 0, SRC_FEAT = 1 };
 // SINK_GROUP: several models that share the input tile (same precision,
 // tile width and Z-score statistics) ranked in one pass, each exactly as
@@ -57,6 +63,22 @@ template <> struct Geo<PREC_FP8> {
     using Vec = v8i;
     static constexpr int KV = 32, KL = 32, KG = 64, EB = 1, PAD = 16;
 };
+// bf16x3: every value is a pair of bf16 (its rounding hi and the rounding lo
+// of the remainder). Storage runs in chunks of 8 consecutive k (or neuron)
+// values: 16 bytes of hi parts, then 16 bytes of lo parts, so EB = 4 and the
+// fp32 address arithmetic of a k-group holds; a vector is one chunk (the
+// 8 hi parts in elements 0-7, the lo parts in 8-15).
+template <> struct Geo<PREC_X3> {
+    using Vec = v16bf;
+    static constexpr int KV = 8, KL = 8, KG = 16, EB = 4, PAD = 16;
+};
+
+// Byte offset of the hi part of value i in bf16x3 storage (its lo part is 16
+// bytes further on).
+__host__ __device__ __forceinline__ constexpr int64_t x3_off(int64_t i)
+{
+    return (i >> 3) * 32 + (i & 7) * 2;
+}
 
 __device__ __forceinline__ v16f mma(float a, float b, v16f c)
 {
@@ -66,15 +88,30 @@ __device__ __forceinline__ v16f mma(v8bf a, v8bf b, v16f c)
 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
+// bf16x3: a*b ~ hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b) (lo*lo, about 2^-18 of
+// the product, is dropped), the small terms first
+__device__ __forceinline__ v16f mma(v16bf a, v16bf b, v16f c)
+{
+    const v8bf ah = __builtin_shufflevector(a, a, 0, 1, 2, 3, 4, 5, 6, 7);
+    const v8bf al = __builtin_shufflevector(a, a, 8, 9, 10, 11, 12, 13, 14, 15);
+    const v8bf bh = __builtin_shufflevector(b, b, 0, 1, 2, 3, 4, 5, 6, 7);
+    const v8bf bl = __builtin_shufflevector(b, b, 8, 9, 10, 11, 12, 13, 14, 15);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
+}
 __device__ __forceinline__ v16f mma(v8i a, v8i b, v16f c)
 {
     // OCP e4m3 for both operands, no block scales
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
-// Precision of the first layer (K = 32 input features): fp32 for the fp32
-// model, bf16 otherwise (the fp8 k-step of 64 does not fit 32 inputs).
-template <int P> struct FirstP { static constexpr int value = P == PREC_FP32 ? PREC_FP32 : PREC_BF16; };
+// Precision of the first layer (K = 32 input features): the model's own
+// for fp32 and bf16x3, bf16 otherwise (the fp8 k-step of 64 does not fit 32
+// inputs).
+template <int P> struct FirstP {
+    static constexpr int value = (P == PREC_FP32 || P == PREC_X3) ? P : PREC_BF16;
+};
 
 // Packed weight index of element (n, k) of a layer with Kp (padded) inputs:
 // fragment-major, [n-block][k-group][lane][KV].
@@ -259,7 +296,8 @@ constexpr bool tile_bias_lds()
     return P == PREC_FP8 && base + extra <= 160 * 1024 && (b0 < r ? b0 : r) == (b1 < r ? b1 : r);
 }
 
-// 16-byte-aligned LDS vector load (an fp8 vector is two 16-byte halves).
+// 16-byte-aligned LDS vector load (an fp8 or bf16x3 vector is two 16-byte
+// halves).
 template <int P>
 __device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
 {
@@ -271,7 +309,7 @@ __device__ __forceinline__ typename Geo<P>::Vec lds_vec(const unsigned char *p)
         v8i r;
         r[0] = lo[0]; r[1] = lo[1]; r[2] = lo[2]; r[3] = lo[3];
         r[4] = hi[0]; r[5] = hi[1]; r[6] = hi[2]; r[7] = hi[3];
-        return r;
+        return __builtin_bit_cast(V, r);
     } else {
         return *reinterpret_cast<const V *>(p);
     }
@@ -442,6 +480,7 @@ template <int P> struct Held;
 template <> struct Held<PREC_FP32> { using T = v4f; };
 template <> struct Held<PREC_BF16> { using T = v4bf; };
 template <> struct Held<PREC_FP8> { using T = uint32_t; };
+template <> struct Held<PREC_X3> { using T = v8bf; };  // hi parts in 0-3, lo parts in 4-7
 
 template <int P>
 __device__ __forceinline__ typename Held<P>::T pack4(v4f v, float qinv)
@@ -454,6 +493,14 @@ __device__ __forceinline__ typename Held<P>::T pack4(v4f v, float qinv)
         o[1] = (__bf16)v[1];
         o[2] = (__bf16)v[2];
         o[3] = (__bf16)v[3];
+        return o;
+    } else if constexpr (P == PREC_X3) {
+        v8bf o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            o[e] = (__bf16)v[e];
+            o[4 + e] = (__bf16)(v[e] - (float)o[e]);  // the remainder is exact in fp32
+        }
         return o;
     } else {
         // the values are ReLU outputs (>= 0, never NaN): clamping at 448
@@ -470,7 +517,13 @@ __device__ __forceinline__ typename Held<P>::T pack4(v4f v, float qinv)
 template <int P>
 __device__ __forceinline__ void store_held(unsigned char *row, int n, typename Held<P>::T h)
 {
-    *reinterpret_cast<typename Held<P>::T *>(row + n * Geo<P>::EB) = h;
+    if constexpr (P == PREC_X3) {
+        // n is a multiple of 4: the four hi parts, and the lo parts 16 bytes on
+        *reinterpret_cast<v4bf *>(row + x3_off(n)) = __builtin_shufflevector(h, h, 0, 1, 2, 3);
+        *reinterpret_cast<v4bf *>(row + x3_off(n) + 16) = __builtin_shufflevector(h, h, 4, 5, 6, 7);
+    } else {
+        *reinterpret_cast<typename Held<P>::T *>(row + n * Geo<P>::EB) = h;
+    }
 }
 
 // Bias + ReLU have been applied; store four consecutive neurons of one
@@ -735,10 +788,16 @@ __device__ __forceinline__ void tile_input(const TileArgs &args, int64_t row0, i
         for (int q = 0; q < C::FPP; ++q) {
             const int j = part * C::FPP + q;
             const float x = ok ? zscore_fast((int64_t)fsel[q], net.mu[j], net.sigma[j]) : 0.0f;
-            if constexpr (P0 == PREC_FP32)
+            if constexpr (P0 == PREC_FP32) {
                 reinterpret_cast<float *>(xr)[q] = x;
-            else
+            } else if constexpr (P0 == PREC_X3) {
+                unsigned char *xe = xin + (size_t)r * C::XS + x3_off(j);
+                const __bf16 h = (__bf16)x;
+                *reinterpret_cast<__bf16 *>(xe) = h;
+                *reinterpret_cast<__bf16 *>(xe + 16) = (__bf16)(x - (float)h);
+            } else {
                 reinterpret_cast<__bf16 *>(xr)[q] = (__bf16)x;
+            }
             if constexpr (SINK == SINK_TRAIN)
                 save_elem<P0>(args.save_x, (int64_t)j * args.save_ld + row, inrow ? x : 0.0f);
         }

@@ -63,14 +63,19 @@ static int layer_prec(const advisor_model *m, int l)
 {
     if (m->precision == PREC_FP32) return PREC_FP32;
     if (m->precision == PREC_BF16) return PREC_BF16;
+    if (m->precision == PREC_X3) return PREC_X3;
     return l == 0 ? PREC_BF16 : PREC_FP8;
 }
 
-static size_t prec_bytes(int p) { return p == PREC_FP32 ? 4 : (p == PREC_BF16 ? 2 : 1); }
+static size_t prec_bytes(int p)
+{
+    return (p == PREC_FP32 || p == PREC_X3) ? 4 : (p == PREC_BF16 ? 2 : 1);
+}
 
 // Scatter one layer's fp32 master weights (zero-padded to tile_w x Kp) into
 // the fragment-major packed layout, converted to the layer's precision
-// (fp8: divided by the per-tensor weight scale first).
+// (fp8: divided by the per-tensor weight scale first; bf16x3: the bf16
+// rounding of the weight and of its remainder, in their chunk places).
 template <int P>
 __global__ void pack_layer_kernel(const float *__restrict__ w, int out, int in, int tile_w,
                                   int kp, float inv_scale, void *__restrict__ dst)
@@ -84,6 +89,11 @@ __global__ void pack_layer_kernel(const float *__restrict__ w, int out, int in, 
         reinterpret_cast<float *>(dst)[at] = v;
     } else if constexpr (P == PREC_BF16) {
         reinterpret_cast<__bf16 *>(dst)[at] = (__bf16)v;
+    } else if constexpr (P == PREC_X3) {
+        unsigned char *e = reinterpret_cast<unsigned char *>(dst) + x3_off(at);
+        const __bf16 h = (__bf16)v;
+        *reinterpret_cast<__bf16 *>(e) = h;
+        *reinterpret_cast<__bf16 *>(e + 16) = (__bf16)(v - (float)h);
     } else {
         reinterpret_cast<uint8_t *>(dst)[at] = (uint8_t)f32_to_e4m3(v * inv_scale);
     }
@@ -123,6 +133,9 @@ int repack(advisor_model *m, hipStream_t s)
                                m->widths[l + 1], m->widths[l], m->tile_w, kp, inv, m->wpack[l]);
         else if (p == PREC_BF16)
             hipLaunchKernelGGL(pack_layer_kernel<PREC_BF16>, dim3(blocks), dim3(256), 0, s, w,
+                               m->widths[l + 1], m->widths[l], m->tile_w, kp, inv, m->wpack[l]);
+        else if (p == PREC_X3)
+            hipLaunchKernelGGL(pack_layer_kernel<PREC_X3>, dim3(blocks), dim3(256), 0, s, w,
                                m->widths[l + 1], m->widths[l], m->tile_w, kp, inv, m->wpack[l]);
         else
             hipLaunchKernelGGL(pack_layer_kernel<PREC_FP8>, dim3(blocks), dim3(256), 0, s, w,
@@ -170,7 +183,8 @@ extern "C" int advisor_model_create(const int32_t *widths, int n_widths, int pre
     if (!out) return fail(ADVISOR_EINVAL, "advisor_model_create: out is null");
     *out = nullptr;
     if (!widths) return fail(ADVISOR_EINVAL, "advisor_model_create: widths is null");
-    if (precision != PREC_FP32 && precision != PREC_BF16 && precision != PREC_FP8)
+    if (precision != PREC_FP32 && precision != PREC_BF16 && precision != PREC_FP8 &&
+        precision != PREC_X3)
         return fail(ADVISOR_EINVAL, "unknown precision");
     if (n_widths < 3 || n_widths > ADVISOR_MAX_LAYERS + 1)
         return fail(ADVISOR_ESHAPE, "need 32, 1 to 8 hidden widths, then 1");
@@ -247,7 +261,8 @@ extern "C" int advisor_model_create(const int32_t *widths, int n_widths, int pre
     }
     if (!rc) rc = prepare_model_kernels(precision, tw);
     if (!rc) m->tile_variant = tuned_variant(m);
-    if (!rc && precision != PREC_FP8) rc = prepare_train_kernels(precision, tw);
+    if (!rc && (precision == PREC_FP32 || precision == PREC_BF16))
+        rc = prepare_train_kernels(precision, tw);
     if (rc) {
         advisor_model_destroy(m);
         return rc;

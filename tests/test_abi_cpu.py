@@ -116,7 +116,12 @@ def test_python_binding_names_match_c():
         if n in ("advisor_last_error", "advisor_version"):
             continue
         assert hasattr(_lib, n), n
-    assert adv.PRECISIONS == {"fp32": 0, "bf16": 1, "fp8": 2}
+    assert adv.PRECISIONS == {"fp32": 0, "bf16": 1, "fp8": 2, "bf16x3": 3}
+    # the codes are the header's enum values
+    hdr = open(os.path.join(ROOT, "include", "advisor.h")).read()
+    for name, code in (("ADVISOR_FP32", 0), ("ADVISOR_BF16", 1), ("ADVISOR_FP8_E4M3", 2),
+                       ("ADVISOR_BF16X3", 3)):
+        assert re.search(r"\b%s = %d\b" % (name, code), hdr), name
 
 
 def test_mfma_peak_argument_checks():

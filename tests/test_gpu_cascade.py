@@ -75,6 +75,7 @@ def _models(widths, precs, p, f_cal, mu, sd):
 @pytest.mark.parametrize("precs, keeps", [
     (("fp8", "bf16", "fp32"), [(16, 4), (32, 2), (8, 8), (4, 1), (32, 32)]),
     (("fp8", "fp32"), [(1,), (16,), (32,)]),
+    (("fp8", "bf16", "bf16x3"), [(32, 4), (16, 2)]),
     (("bf16", "fp8", "bf16", "fp32"), [(16, 8, 2), (32, 4, 4)]),
     (("fp32",), [()]),
 ])
@@ -174,15 +175,20 @@ def test_agreement_with_oracle_1024_wide():
     stored kernel; fp8 alone does not (its 3-bit mantissas scatter the
     near-ties), which is why the cut exists."""
     paths = {"fp8>bf16:32>fp32:4": (("fp8", "bf16", "fp32"), (32, 4)),
+             "fp8>bf16:32>bf16x3:4": (("fp8", "bf16", "bf16x3"), (32, 4)),
              "fp8": (("fp8",), ())}
     res, gold = _stored_agreement(5, paths)
     assert res["fp8>bf16:32>fp32:4"][0] >= AGREEMENT_BAR
+    # a bf16x3 last stage (about 1e-5 relative per product) picks as fp32 does
+    assert res["fp8>bf16:32>bf16x3:4"][0] >= AGREEMENT_BAR
     assert res["fp8"][0] < res["fp8>bf16:32>fp32:4"][0]
 
 
 def test_agreement_with_oracle_512_wide():
     """The 16384-kernel, 8.9M-variant workload on 32-512x4-1 in bf16 with
     an fp32 cut, against the oracle's picks on 8192 stored kernels."""
-    paths = {"bf16>fp32:4": (("bf16", "fp32"), (4,)), "bf16": (("bf16",), ())}
+    paths = {"bf16>fp32:4": (("bf16", "fp32"), (4,)), "bf16": (("bf16",), ()),
+             "bf16>bf16x3:4": (("bf16", "bf16x3"), (4,))}
     res, gold = _stored_agreement(3, paths)
     assert res["bf16>fp32:4"][0] >= AGREEMENT_BAR
+    assert res["bf16>bf16x3:4"][0] >= AGREEMENT_BAR
