@@ -618,6 +618,15 @@ int advisor_validate_offsets(const int64_t *offsets, int64_t n_kernels, int64_t 
  */
 int advisor_profile_enable(int on);
 int advisor_profile_read(int64_t *launches, double *total_ms);
+/*
+ * advisor_profile_read with every bracketed launch's own duration: ms_out
+ * (host, double [cap], may be NULL) receives the first min(cap, launches)
+ * durations in milliseconds in launch order (a multi-stage call launches
+ * the tile kernel once per stage); *launches (may be NULL) the number of
+ * bracketed launches. Waits for the recorded events and forgets them;
+ * EINVAL if cap < 0.
+ */
+int advisor_profile_read_each(double *ms_out, int64_t cap, int64_t *launches);
 
 /*
  * Measurement aid (not part of the method): the sustained matrix-core rate

@@ -6,7 +6,7 @@ from ._lib import (AdvisorError, PRECISIONS, advisor_featurize, advisor_model_cr
                    advisor_model_destroy, advisor_model_get_adam, advisor_model_get_params,
                    advisor_model_param_count, advisor_model_set_adam, advisor_model_set_params,
                    advisor_model_set_zscore, advisor_mfma_peak, advisor_predict, advisor_profile_enable,
-                   advisor_profile_read, advisor_rank, advisor_rank_preds, advisor_rank_refined,
+                   advisor_profile_read, advisor_profile_read_each, advisor_rank, advisor_rank_preds, advisor_rank_refined,
                    advisor_rank_cascade, advisor_rank_cascade_noalloc,
                    advisor_zscore_fit, last_error, advisor_mlp_saved_bytes, advisor_mlp_forward,
                    advisor_mlp_backward, advisor_train_step, advisor_model_load_params,

@@ -78,6 +78,8 @@ def lib():
             "advisor_model_get_tile_variant": ([P], i32),
             "advisor_profile_enable": ([i32], i32),
             "advisor_profile_read": ([C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
+            "advisor_profile_read_each": ([C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)],
+                                          i32),
             "advisor_mfma_peak": ([i32, i64, i32, C.POINTER(C.c_double), P], i32),
             "advisor_validate_offsets": ([P, i64, i64, C.POINTER(C.c_int64), P], i32),
             "advisor_train_step_rmsprop": ([P, P, P, i64, C.c_float, C.c_float, C.c_float,
@@ -489,6 +491,15 @@ def advisor_profile_read():
     ms = C.c_double(0.0)
     _check(lib().advisor_profile_read(C.byref(n), C.byref(ms)), "advisor_profile_read")
     return n.value, ms.value
+
+
+def advisor_profile_read_each(cap=4096):
+    """Durations (ms, launch order) of the tile-kernel launches bracketed
+    since profiling was enabled or last read (at most `cap` of them)."""
+    n = C.c_int64(0)
+    buf = (C.c_double * max(int(cap), 1))()
+    _check(lib().advisor_profile_read_each(buf, int(cap), C.byref(n)), "advisor_profile_read_each")
+    return [buf[i] for i in range(min(n.value, int(cap)))]
 
 
 def advisor_mfma_peak(precision, iters=20000, workgroups_per_cu=2) -> float:

@@ -484,6 +484,24 @@ extern "C" int advisor_profile_enable(int on)
     return ADVISOR_OK;
 }
 
+extern "C" int advisor_profile_read_each(double *ms_out, int64_t cap, int64_t *launches)
+{
+    clear_error();
+    if (cap < 0) return fail(ADVISOR_EINVAL, "negative capacity");
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    int64_t i = 0;
+    for (auto &e : g_prof_events) {
+        ADV_HIP(hipEventSynchronize(e.second));
+        float ms = 0.0f;
+        ADV_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        if (ms_out && i < cap) ms_out[i] = ms;
+        ++i;
+    }
+    if (launches) *launches = (int64_t)g_prof_events.size();
+    prof_clear_locked();
+    return ADVISOR_OK;
+}
+
 extern "C" int advisor_profile_read(int64_t *launches, double *total_ms)
 {
     clear_error();

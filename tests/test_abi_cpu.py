@@ -124,6 +124,17 @@ def test_python_binding_names_match_c():
         assert re.search(r"\b%s = %d\b" % (name, code), hdr), name
 
 
+def test_profile_read_each_argument_checks():
+    L = _lib.lib()
+    n = C.c_int64(-5)
+    assert L.advisor_profile_read_each(None, -1, C.byref(n)) == EINVAL
+    # nothing bracketed (profiling never enabled): no launches, no device work
+    buf = (C.c_double * 4)(7.0, 7.0, 7.0, 7.0)
+    assert L.advisor_profile_read_each(buf, 4, C.byref(n)) == 0
+    assert n.value == 0 and list(buf) == [7.0] * 4
+    assert _lib.advisor_profile_read_each(8) == []
+
+
 def test_mfma_peak_argument_checks():
     L = _lib.lib()
     out = C.c_double(0.0)
