@@ -220,25 +220,56 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
     }
 }
 
+// The key of lane (lane xor J). Inside a row of 16 lanes the exchange is a
+// DPP move (xor 1 and 2: quad permutations; xor 4: the mirror image inside
+// each 8-lane half-row, then each quad reversed; xor 8: a rotation of the row
+// by 8); across rows it goes through the LDS crossbar (ds_bpermute).
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t x)
+{
+    const int v = (int)x;
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false);
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false);
+    else if constexpr (J == 4) {
+        const int m = __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_update_dpp(m, m, 0x1B, 0xf, 0xf, false);  // quad [3,2,1,0]
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    } else {
+        return (uint32_t)__shfl_xor(v, J, 64);
+    }
+}
+
+// One compare-exchange step of a bitonic sort over the wave: runs of K lanes
+// alternate ascending and descending, partners are J lanes apart; the lower
+// lane of a pair keeps the smaller key in an ascending run and the larger
+// in a descending one.
+template <int K, int J>
+__device__ __forceinline__ uint64_t bitonic_step(uint64_t v, int lane)
+{
+    const uint32_t olo = xor_lane_u32<J>((uint32_t)v);
+    const uint32_t ohi = xor_lane_u32<J>((uint32_t)(v >> 32));
+    const uint64_t o = ((uint64_t)ohi << 32) | olo;
+    const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
+    v = ((o < v) == keep_min) ? o : v;
+    if constexpr (J > 1) return bitonic_step<K, J / 2>(v, lane);
+    else return v;
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t bitonic_from(uint64_t v, int lane)
+{
+    v = bitonic_step<K, K / 2>(v, lane);
+    if constexpr (K < 64) return bitonic_from<2 * K>(v, lane);
+    else return v;
+}
+
 // Ascending bitonic sort of one 64-bit key per lane over the 64 lanes of a
-// wave (lane r ends with the r-th smallest key): 21 compare-exchange steps
-// with the partner lane (lane xor j), whose key arrives as two 32-bit halves.
+// wave (lane r ends with the r-th smallest key): 21 compare-exchange steps,
+// 18 of them DPP moves inside rows of 16 lanes. Every lane must be active.
 __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v, int lane)
 {
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t olo = (uint32_t)__shfl_xor((int)(uint32_t)v, j, 64);
-            const uint32_t ohi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j, 64);
-            const uint64_t o = ((uint64_t)ohi << 32) | olo;
-            // the lower lane of a pair keeps the smaller key in an ascending
-            // run (lane & k clear) and the larger in a descending one
-            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-            v = ((o < v) == keep_min) ? o : v;
-        }
-    }
-    return v;
+    return bitonic_from<2>(v, lane);
 }
 
 // The prediction a key was made from (pred_key inverted; -0 comes back as +0).

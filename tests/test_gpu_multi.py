@@ -49,7 +49,8 @@ def test_rank_multi_grouped_pass_equals_separate_calls():
     statistics (the statistics describe the variants, not the machine) run
     in grouped passes that build each input tile once: nine paper-sized
     targets sharing statistics (two groups, eight and one), one with its own
-    statistics and one of another precision. Every row equals a separate
+    statistics, one of another precision and two bf16x3 targets (a group of
+    their own). Every row equals a separate
     advisor_rank bit for bit, predictions included."""
     kd, vd, off = workload.make_descriptors(400, 0, 700, 95, invalid_frac=0.05)
     f, inv = oracle.featurize(kd, vd)
@@ -59,7 +60,9 @@ def test_rank_multi_grouped_pass_equals_separate_calls():
     specs = [((32, 64, 128, 64, 32, 1), "fp32", 100 + t, mu, sd) for t in range(9)]
     specs += [((32, 64, 128, 64, 32, 1), "fp32", 120, mu2, sd2),
               ((32, 64, 128, 64, 32, 1), "bf16", 121, mu, sd),
-              ((32, 48, 24, 40, 1), "fp32", 122, mu, sd)]   # same tile width 64
+              ((32, 48, 24, 40, 1), "fp32", 122, mu, sd),   # same tile width 64
+              ((32, 64, 128, 64, 32, 1), "bf16x3", 123, mu, sd),   # a bf16x3 group of two
+              ((32, 64, 128, 64, 32, 1), "bf16x3", 124, mu, sd)]
     models = []
     for w, prec, seed, m_, s_ in specs:
         m = adv.Model(w, prec)
