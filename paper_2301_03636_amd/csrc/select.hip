@@ -284,20 +284,28 @@ __device__ __forceinline__ float key_pred(uint64_t key)
 // grid-stride loop over kernels. Lane r writes rank r: the variant index and
 // its prediction, or -1 and NaN past the end of the eligible variants.
 //
+// Lists of 8 or more (K >= 8) take two launches. The first (TOPN_FAST)
+// holds only the threshold path, in few registers, and marks each segment it
+// leaves undone with -2 in the first slot of its list; the second
+// (TOPN_MARKED) runs the per-lane lists on the marked segments. Shorter lists
+// take one launch (TOPN_ALL) of the per-lane lists.
+//
 // A segment of at most 64 * SEL_UNROLL variants (one load pass) takes the
-// threshold path when K >= 8: every lane's minimum key goes into one wave
+// threshold path: every lane's minimum key goes into one wave
 // sort, whose N-th smallest value t bounds the segment's N-th smallest key
 // from above (the N lane minima at or below t are N eligible variants);
 // only keys <= t can rank, and when there are at most 64 of them they are
 // gathered through LDS (each lane's at its rank among the wave's
 // candidates, counted per load slot with a ballot) and one more wave sort
 // puts them in order. Every other segment (longer ones, more than 64
-// candidates, small K): each lane keeps the K smallest keys it has seen (a
+// candidates): each lane keeps the K smallest keys it has seen (a
 // sorted list held in registers, compile-time indices only, entered only by
 // keys that beat its current K-th), then N rounds of a wave-wide minimum pop
 // the segment's best keys in ascending order (keys are unique, so exactly one
 // lane pops each).
-template <int K>
+enum { TOPN_ALL = 0, TOPN_FAST = 1, TOPN_MARKED = 2 };
+
+template <int K, int MODE>
 __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
     const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
     int64_t n_v, int N, int64_t *__restrict__ idx_out, float *__restrict__ val_out)
@@ -307,9 +315,12 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
     const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + wave; k < n_k; k += nwaves_total) {
+        if constexpr (MODE == TOPN_MARKED) {
+            if (idx_out[k * N] != -2) continue;  // done by the threshold path
+        }
         const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
         const int64_t hi = max(lo, min(offsets[k + 1], n_v));
-        if constexpr (K >= 8) {
+        if constexpr (MODE == TOPN_FAST) {
             if (hi - lo <= 64 * SEL_UNROLL) {  // the same for every lane
                 float p[SEL_UNROLL];
                 load_pass(pred, lo + lane, hi, p);
@@ -359,6 +370,8 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
                     continue;
                 }
             }
+            if (lane == 0) idx_out[k * N] = -2;  // left to the per-lane lists
+            continue;
         }
         uint64_t top[K];
 #pragma unroll
@@ -406,8 +419,15 @@ static void launch_topn(const float *pred, const int64_t *offsets, int64_t n_k, 
                         int N, int64_t *idx_out, float *val_out, hipStream_t s)
 {
     const int64_t blocks = std::min<int64_t>((n_k + AM_WAVES - 1) / AM_WAVES, 1 << 20);
-    hipLaunchKernelGGL(topn_preds_kernel<K>, dim3((unsigned)blocks), dim3(AM_WAVES * 64), 0, s,
-                       pred, offsets, n_k, n_v, N, idx_out, val_out);
+    if constexpr (K >= 8) {
+        hipLaunchKernelGGL((topn_preds_kernel<K, TOPN_FAST>), dim3((unsigned)blocks),
+                           dim3(AM_WAVES * 64), 0, s, pred, offsets, n_k, n_v, N, idx_out, val_out);
+        hipLaunchKernelGGL((topn_preds_kernel<K, TOPN_MARKED>), dim3((unsigned)blocks),
+                           dim3(AM_WAVES * 64), 0, s, pred, offsets, n_k, n_v, N, idx_out, val_out);
+    } else {
+        hipLaunchKernelGGL((topn_preds_kernel<K, TOPN_ALL>), dim3((unsigned)blocks),
+                           dim3(AM_WAVES * 64), 0, s, pred, offsets, n_k, n_v, N, idx_out, val_out);
+    }
 }
 
 int launch_topn_preds(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v,
