@@ -28,7 +28,7 @@ static void prof_clear_locked()
 // tile M as large as LDS allows (activations [M][W] plus the input tile),
 // 8 waves (two per SIMD, 256 registers each) except the 1024-wide fp8 tile
 // (one wave per SIMD and its 512 registers), and NS passes over each wave's
-// neurons for the 1024-wide tiles. Shape 1 halves the rows with 8 waves.
+// neurons for the 1024-wide tiles and the 512-wide bf16 and fp8 tiles. Shape 1 halves the rows with 8 waves.
 // Shape 2 halves the rows (or quarters them for 1024 bf16 and 512 fp32
 // neurons) and the waves, so two workgroups share each CU by LDS and by
 // registers: one's input stage, epilogues and barriers overlap the other's
@@ -46,7 +46,12 @@ template <int P, int W> struct TileShape<P, W, 0> {
                                  ? (W <= 256 ? 128 : (W == 512 ? 64 : 32))
                                  : (P == PREC_BF16 ? (W <= 512 ? 128 : 64) : 128);
     static constexpr int NW = (W == 1024 && P == PREC_FP8) ? 4 : 8;
-    static constexpr int NS = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1)) : 1;
+    // two passes at 512 wide in bf16 and fp8 (a wave's 128 x 64 accumulators
+    // in one pass spill: 36 B per lane in bf16, 296 in fp8), except for the
+    // training forward, whose copy-out registers spill more with two
+    static constexpr int NS = W == 1024 ? (P == PREC_FP8 ? 4 : (P == PREC_BF16 ? 2 : 1))
+                                        : ((W == 512 && (P == PREC_BF16 || P == PREC_FP8)) ? 2 : 1);
+    static constexpr int NS_TRAIN = W == 1024 ? NS : 1;
 };
 template <int P, int W> struct TileShape<P, W, 1> {
     static constexpr bool PP = false;
@@ -84,9 +89,17 @@ constexpr int N_TILE_SHAPES = 4;
 
 // (a grouped pass runs shape 3's rows and waves on mlp_tiles_kernel: the
 // same bits as the ping-pong kernel)
+// Passes over a wave's neurons as a kernel with this sink runs the shape
+// (only shape 0 runs the training forward).
+template <class S, int SINK> constexpr int shape_passes()
+{
+    if constexpr (SINK == SINK_TRAIN) return S::NS_TRAIN;
+    else return S::NS;
+}
+
 template <class S, int P, int W, int SRC, int SINK, bool PP = S::PP && SINK != SINK_GROUP>
 struct TileKernel {
-    static constexpr auto kern = mlp_tiles_kernel<P, W, S::M, S::NW, S::NS, SRC, SINK>;
+    static constexpr auto kern = mlp_tiles_kernel<P, W, S::M, S::NW, shape_passes<S, SINK>(), SRC, SINK>;
 };
 template <class S, int P, int W, int SRC, int SINK> struct TileKernel<S, P, W, SRC, SINK, true> {
     static constexpr auto kern = mlp_pp_kernel<P, W, S::M, S::NW, SRC, SINK>;
@@ -113,7 +126,7 @@ struct TileLaunch {
     using S = TileShape<P, W, V>;
     static constexpr int M = S::M;
     static constexpr int NW = S::NW;
-    static constexpr int NS = S::NS;
+    static constexpr int NS = shape_passes<S, SINK>();
     using C = TileCfg<P, W, M, NW, NS,
                       SRC == SRC_DESC && SINK != SINK_GROUP && tile_vdesc_prefetch<P, W, M, NW>(),
                       SINK != SINK_GROUP && SINK != SINK_TRAIN && !S::PP &&
