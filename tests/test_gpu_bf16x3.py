@@ -51,7 +51,11 @@ def _margin(pred, off):
 @pytest.mark.parametrize("widths", [(32, 64, 128, 64, 32, 1), (32, 256, 256, 256, 1),
                                     (32, 512, 512, 512, 512, 1), (32, 64, 64, 1)])
 def test_bf16x3_rank_against_oracle(widths):
-    kd, vd, off = workload.make_descriptors(120, 1, 900, 31, depth=3, invalid_frac=0.05)
+    # three kernels without variants, 5% invalid variants
+    counts = np.random.default_rng(30).integers(1, 901, size=120)
+    counts[[3, 50, 119]] = 0
+    kd, vd, off = workload.make_descriptors(120, 1, 900, 31, depth=3, invalid_frac=0.05,
+                                            counts=counts)
     vd[5, 0] = (vd[5, 0] + 1) % 120          # a variant filed under the wrong kernel
     m, p, mu, sd = _model(widths, 41, kd, vd)
     best_ref, pred_ref = oracle.rank(kd, vd, off, widths, p, mu, sd)
@@ -61,6 +65,8 @@ def test_bf16x3_rank_against_oracle(widths):
     ok = ~np.isnan(pred_ref)
     err = rel_err(pred[ok], pred_ref[ok])
     assert best.tolist() == segment_argmin(pred, off).tolist()
+    empty = np.diff(off) == 0
+    assert np.all(best[empty] == -1) and np.array_equal(best[empty], best_ref[empty])
     gap = _margin(pred_ref, off) / np.maximum(np.abs(np.nan_to_num(
         pred_ref[np.maximum(best_ref, 0)])), 1.0)
     clear = gap > 2 * X3_MAX
