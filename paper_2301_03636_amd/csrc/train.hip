@@ -212,19 +212,41 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
 // waves of the first column tile also sum their g^T rows: the bias
 // gradient's partials (one per split, reduced in the same fixed order).
 // 72 KB of LDS per workgroup: two workgroups per CU.
+//
+// One launch can hold the products of several layers (a small batch, where
+// each layer is a few workgroups and separate launches would each wait for
+// the previous one): job j owns workgroups [wg0_j, wg0_{j+1}).
+struct WgradJob {
+    const void *A, *B;       // g^T rows (na of them) and h^T rows (nb), batch-contiguous
+    int na, nb, tiles_n, tiles_k, splits, wg0;
+    int64_t kchunk;          // batch rows per split
+    float *partial, *partial_b, *direct;
+    int dout, din;
+};
+struct WgradJobs {
+    int n;
+    int64_t ld, n_rows;
+    WgradJob job[MAX_LAYERS];
+};
+
 template <int P>
-__global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__restrict__ A, int na,
-                                                    const typename CT<P>::T *__restrict__ B, int nb,
-                                                    int64_t ld, int64_t kchunk, int tiles_n,
-                                                    int tiles_k, int splits,
-                                                    float *__restrict__ partial,
-                                                    float *__restrict__ partial_b,
-                                                    float *__restrict__ direct, int dout, int din,
-                                                    int64_t n_rows)
+__global__ __launch_bounds__(256) void wgrad_kernel(const WgradJobs jobs)
 {
     using G = Geo<P>;
     using V = typename G::Vec;
     using T = typename CT<P>::T;
+    int jsel = 0;  // the job of this workgroup (uniform)
+    for (int q = 1; q < jobs.n; ++q)
+        if ((int)blockIdx.x >= jobs.job[q].wg0) jsel = q;
+    const WgradJob &J = jobs.job[jsel];
+    const T *__restrict__ A = static_cast<const T *>(J.A);
+    const T *__restrict__ B = static_cast<const T *>(J.B);
+    const int na = J.na, nb = J.nb, tiles_n = J.tiles_n, tiles_k = J.tiles_k, splits = J.splits;
+    const int64_t ld = jobs.ld, kchunk = J.kchunk, n_rows = jobs.n_rows;
+    float *__restrict__ partial = J.partial;
+    float *__restrict__ partial_b = J.partial_b;
+    float *__restrict__ direct = J.direct;
+    const int dout = J.dout, din = J.din;
     typedef int v4i_ __attribute__((ext_vector_type(4)));
     constexpr int KV = G::KV, CH = 8 * KV;
     constexpr int ROWB = CH * (int)sizeof(T);      // bytes of a row per chunk (128)
@@ -244,7 +266,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const typename CT<P>::T *__r
     // the same rows from its own L2.
     int tile, split;
     {
-        const int wg = blockIdx.x, tiles = tiles_n * tiles_k;
+        const int wg = (int)blockIdx.x - J.wg0, tiles = tiles_n * tiles_k;
         if (splits % 8 == 0) {
             const int xcd = wg & 7, slot = wg >> 3;
             split = xcd * (splits >> 3) + slot / tiles;
@@ -998,40 +1020,72 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         ADV_LAUNCHED("head_reduce_kernel");
     }
     // weight and bias gradients per hidden layer
+    // one job per layer; when no layer splits its batch (small batches) every
+    // layer goes into one launch, else each layer is a launch of its own
+    // followed by its reduction
+    WgradJobs all{};
+    all.ld = ld;
+    all.n_rows = n;
+    bool one_launch = true;
     for (int l = 0; l < L; ++l) {
         const int na = tw, nb = l == 0 ? NFEAT : tw;
-        const int out = m->widths[l + 1], in = m->widths[l];
-        const int splits = splits_for(na, nb, ld);
-        const int64_t kchunk = ld / splits;
-        const unsigned char *Ab = reinterpret_cast<const unsigned char *>(w->gt) + (size_t)l * tw * ld * eb;
-        const unsigned char *Bb = l == 0 ? xs : hs + (size_t)(l - 1) * tw * ld * eb;
-        const int tn = (na + 127) / 128, tk = (nb + 127) / 128;
-        const dim3 grid((unsigned)(tn * tk * splits));
-        float *partial_b = w->partial + w->partial_floats;
+        WgradJob &J = all.job[l];
+        J.splits = splits_for(na, nb, ld);
+        J.kchunk = ld / J.splits;
+        J.A = reinterpret_cast<const unsigned char *>(w->gt) + (size_t)l * tw * ld * eb;
+        J.B = l == 0 ? xs : hs + (size_t)(l - 1) * tw * ld * eb;
+        J.na = na;
+        J.nb = nb;
+        J.tiles_n = (na + 127) / 128;
+        J.tiles_k = (nb + 127) / 128;
+        J.partial = w->partial;
+        J.partial_b = w->partial + w->partial_floats;
         // weights then biases of the layer (the bias gradient is the sum of
         // g^T's rows over the batch; rows past n are zero)
-        float *gw = grads + m->layer_off[l];
-        float *direct = splits == 1 ? gw : nullptr;
+        J.direct = J.splits == 1 ? grads + m->layer_off[l] : nullptr;
+        J.dout = m->widths[l + 1];
+        J.din = m->widths[l];
+        one_launch = one_launch && J.splits == 1;
+    }
+    auto launch = [&](const WgradJobs &jobs, int wgs) {
         if (m->precision == PREC_FP32)
-            hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, grid, dim3(256), WGRAD_LDS_BYTES, s,
-                               reinterpret_cast<const float *>(Ab), na,
-                               reinterpret_cast<const float *>(Bb), nb, ld, kchunk, tn, tk, splits,
-                               w->partial, partial_b, direct, out, in, n);
+            hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, dim3((unsigned)wgs), dim3(256),
+                               WGRAD_LDS_BYTES, s, jobs);
         else
-            hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, grid, dim3(256), WGRAD_LDS_BYTES, s,
-                               reinterpret_cast<const __bf16 *>(Ab), na,
-                               reinterpret_cast<const __bf16 *>(Bb), nb, ld, kchunk, tn, tk, splits,
-                               w->partial, partial_b, direct, out, in, n);
+            hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, dim3((unsigned)wgs), dim3(256),
+                               WGRAD_LDS_BYTES, s, jobs);
         ADV_LAUNCHED("wgrad_kernel");
-        if (direct) continue;
+    };
+    if (one_launch) {
+        int wgs = 0;
+        for (int l = 0; l < L; ++l) {
+            all.job[l].wg0 = wgs;
+            wgs += all.job[l].tiles_n * all.job[l].tiles_k;
+        }
+        all.n = L;
+        launch(all, wgs);
+        return ADVISOR_OK;
+    }
+    for (int l = 0; l < L; ++l) {
+        WgradJobs one{};
+        one.ld = ld;
+        one.n_rows = n;
+        one.n = 1;
+        one.job[0] = all.job[l];
+        one.job[0].wg0 = 0;
+        const WgradJob &J = one.job[0];
+        launch(one, J.tiles_n * J.tiles_k * J.splits);
+        if (J.direct) continue;
+        const int out = J.dout, in = J.din, na = J.na, nb = J.nb, splits = J.splits;
+        float *gw = grads + m->layer_off[l];
         const int64_t ne = (int64_t)out * in + out;
         if (in % 4 == 0 && nb % 4 == 0 && ((uintptr_t)gw & 15) == 0) {
             const int64_t ne4 = (int64_t)out * in / 4 + out;
             hipLaunchKernelGGL(wgrad_reduce4_kernel, dim3((unsigned)((ne4 + 255) / 256)), dim3(256), 0,
-                               s, w->partial, partial_b, splits, na, nb, out, in, gw);
+                               s, w->partial, J.partial_b, splits, na, nb, out, in, gw);
         } else {
             hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
-                               w->partial, partial_b, splits, na, nb, out, in, gw);
+                               w->partial, J.partial_b, splits, na, nb, out, in, gw);
         }
         ADV_LAUNCHED("wgrad_reduce_kernel");
     }
