@@ -213,9 +213,11 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
 // gradient's partials (one per split, reduced in the same fixed order).
 // 72 KB of LDS per workgroup: two workgroups per CU.
 //
-// One launch can hold the products of several layers (a small batch, where
-// each layer is a few workgroups and separate launches would each wait for
-// the previous one): job j owns workgroups [wg0_j, wg0_{j+1}).
+// One launch holds every layer's product (job j owns workgroups
+// [wg0_j, wg0_{j+1}), the last few of each range padding that exit at
+// once): a small batch's layers are a few workgroups each, which separate
+// launches would run one after another, and a large batch's layers overlap
+// each other's first and last waves of workgroups.
 struct WgradJob {
     const void *A, *B;       // g^T rows (na of them) and h^T rows (nb), batch-contiguous
     int na, nb, tiles_n, tiles_k, splits, wg0;
@@ -267,6 +269,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const WgradJobs jobs)
     int tile, split;
     {
         const int wg = (int)blockIdx.x - J.wg0, tiles = tiles_n * tiles_k;
+        if (wg >= tiles * splits) return;  // padding up to the next job's multiple of 8
         if (splits % 8 == 0) {
             const int xcd = wg & 7, slot = wg >> 3;
             split = xcd * (splits >> 3) + slot / tiles;
@@ -756,14 +759,15 @@ static int ensure_ws(advisor_model *m, int64_t n, bool with_saved)
         for (int l = 1; l < m->n_hidden; ++l) ADV_HIP(hipMalloc(&w->wt[l], (size_t)tw * tw * eb));
         ADV_HIP(hipMalloc(&w->grads, sizeof(float) * m->n_params));
         ADV_HIP(hipMalloc(&w->red, sizeof(double) * (2 * RB + 8)));  // + scalars
+        // every layer's weight partials (all layers' products run in one
+        // launch), then every layer's 64 splits x tile width bias partials
         size_t pf = 0;
         for (int l = 0; l < m->n_hidden; ++l) {
             const int na = tw, nb = l == 0 ? NFEAT : tw;
-            pf = std::max(pf, (size_t)64 * na * nb);
+            pf += (size_t)64 * na * nb;
         }
         w->partial_floats = pf;
-        // weight partials, then 64 splits x tile width bias partials
-        ADV_HIP(hipMalloc(&w->partial, sizeof(float) * (pf + (size_t)64 * tw)));
+        ADV_HIP(hipMalloc(&w->partial, sizeof(float) * (pf + (size_t)64 * tw * m->n_hidden)));
     }
     const int64_t ld = ld_for(n);
     if (ld > w->ld || (with_saved && !w->saved)) {
@@ -1020,13 +1024,15 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         ADV_LAUNCHED("head_reduce_kernel");
     }
     // weight and bias gradients per hidden layer
-    // one job per layer; when no layer splits its batch (small batches) every
-    // layer goes into one launch, else each layer is a launch of its own
-    // followed by its reduction
+    // one job per layer, all in one launch (each with its own partials, whose
+    // splits are then summed per layer in a fixed order); a job's first
+    // workgroup is a multiple of 8, so its splits keep their XCD placement
     WgradJobs all{};
     all.ld = ld;
     all.n_rows = n;
-    bool one_launch = true;
+    all.n = L;
+    size_t pw = 0, pb = 0;
+    int wgs = 0;
     for (int l = 0; l < L; ++l) {
         const int na = tw, nb = l == 0 ? NFEAT : tw;
         WgradJob &J = all.job[l];
@@ -1038,43 +1044,27 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         J.nb = nb;
         J.tiles_n = (na + 127) / 128;
         J.tiles_k = (nb + 127) / 128;
-        J.partial = w->partial;
-        J.partial_b = w->partial + w->partial_floats;
+        J.partial = w->partial + pw;
+        J.partial_b = w->partial + w->partial_floats + pb;
+        pw += (size_t)J.splits * na * nb;
+        pb += (size_t)J.splits * na;
+        J.wg0 = wgs;
+        wgs += (J.tiles_n * J.tiles_k * J.splits + 7) / 8 * 8;
         // weights then biases of the layer (the bias gradient is the sum of
         // g^T's rows over the batch; rows past n are zero)
         J.direct = J.splits == 1 ? grads + m->layer_off[l] : nullptr;
         J.dout = m->widths[l + 1];
         J.din = m->widths[l];
-        one_launch = one_launch && J.splits == 1;
     }
-    auto launch = [&](const WgradJobs &jobs, int wgs) {
-        if (m->precision == PREC_FP32)
-            hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, dim3((unsigned)wgs), dim3(256),
-                               WGRAD_LDS_BYTES, s, jobs);
-        else
-            hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, dim3((unsigned)wgs), dim3(256),
-                               WGRAD_LDS_BYTES, s, jobs);
-        ADV_LAUNCHED("wgrad_kernel");
-    };
-    if (one_launch) {
-        int wgs = 0;
-        for (int l = 0; l < L; ++l) {
-            all.job[l].wg0 = wgs;
-            wgs += all.job[l].tiles_n * all.job[l].tiles_k;
-        }
-        all.n = L;
-        launch(all, wgs);
-        return ADVISOR_OK;
-    }
+    if (m->precision == PREC_FP32)
+        hipLaunchKernelGGL(wgrad_kernel<PREC_FP32>, dim3((unsigned)wgs), dim3(256), WGRAD_LDS_BYTES,
+                           s, all);
+    else
+        hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, dim3((unsigned)wgs), dim3(256), WGRAD_LDS_BYTES,
+                           s, all);
+    ADV_LAUNCHED("wgrad_kernel");
     for (int l = 0; l < L; ++l) {
-        WgradJobs one{};
-        one.ld = ld;
-        one.n_rows = n;
-        one.n = 1;
-        one.job[0] = all.job[l];
-        one.job[0].wg0 = 0;
-        const WgradJob &J = one.job[0];
-        launch(one, J.tiles_n * J.tiles_k * J.splits);
+        const WgradJob &J = all.job[l];
         if (J.direct) continue;
         const int out = J.dout, in = J.din, na = J.na, nb = J.nb, splits = J.splits;
         float *gw = grads + m->layer_off[l];
@@ -1082,10 +1072,10 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         if (in % 4 == 0 && nb % 4 == 0 && ((uintptr_t)gw & 15) == 0) {
             const int64_t ne4 = (int64_t)out * in / 4 + out;
             hipLaunchKernelGGL(wgrad_reduce4_kernel, dim3((unsigned)((ne4 + 255) / 256)), dim3(256), 0,
-                               s, w->partial, J.partial_b, splits, na, nb, out, in, gw);
+                               s, J.partial, J.partial_b, splits, na, nb, out, in, gw);
         } else {
             hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
-                               w->partial, J.partial_b, splits, na, nb, out, in, gw);
+                               J.partial, J.partial_b, splits, na, nb, out, in, gw);
         }
         ADV_LAUNCHED("wgrad_reduce_kernel");
     }
