@@ -198,7 +198,7 @@ __global__ __launch_bounds__(NWAVES * 64) void bwd_tiles_kernel(BwdArgs a)
 // ---------------------------------------------------------------------------
 // Weight gradient dW[n][k] = sum_b g^T[n][b] h^T[k][b] (both operands with
 // the batch contiguous), split over the batch into `splits` ranges whose fp32
-// partial tiles are summed in a fixed order by wgrad_reduce_kernel. A
+// partial tiles are summed in a fixed order by wgrad_reduce_jobs_kernel. A
 // workgroup of 4 waves owns a 128 x 128 output tile, each wave 64 x 64.
 //
 // The batch is consumed in chunks of CH = 8 KV rows (one 128-byte line of
@@ -435,11 +435,11 @@ constexpr size_t WGRAD_LDS_BYTES = 2 * 2 * 128 * (128 + 16);
 
 // grads[off + n * in + k] = sum over splits of partial[s][n][k] (n < out,
 // k < in), then grads[off + out * in + n] = sum over splits of partial_b[s][n]
-__global__ void wgrad_reduce_kernel(const float *__restrict__ partial,
-                                    const float *__restrict__ partial_b, int splits, int na,
-                                    int nb, int out, int in, float *__restrict__ grads)
+__device__ __forceinline__ void wgrad_reduce_one(int64_t idx, const float *__restrict__ partial,
+                                                 const float *__restrict__ partial_b, int splits,
+                                                 int na, int nb, int out, int in,
+                                                 float *__restrict__ grads)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nw = (int64_t)out * in;
     if (idx >= nw + out) return;
     float s = 0.0f;
@@ -459,11 +459,11 @@ __global__ void wgrad_reduce_kernel(const float *__restrict__ partial,
 
 // The same sums four consecutive weights at a time (16-byte loads and
 // stores) where the layer's row lengths allow it (in and nb multiples of 4).
-__global__ void wgrad_reduce4_kernel(const float *__restrict__ partial,
-                                     const float *__restrict__ partial_b, int splits, int na,
-                                     int nb, int out, int in, float *__restrict__ grads)
+__device__ __forceinline__ void wgrad_reduce_four(int64_t idx4, const float *__restrict__ partial,
+                                                  const float *__restrict__ partial_b, int splits,
+                                                  int na, int nb, int out, int in,
+                                                  float *__restrict__ grads)
 {
-    const int64_t idx4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nw4 = (int64_t)out * in / 4;
     if (idx4 < nw4) {
         const int64_t idx = idx4 * 4;
@@ -485,6 +485,32 @@ __global__ void wgrad_reduce4_kernel(const float *__restrict__ partial,
         for (int q = 0; q < splits; ++q) s += partial_b[(int64_t)q * na + nn];
         grads[nw4 * 4 + nn] = s;
     }
+}
+
+// The reductions of every layer that split its batch, in one launch: job j
+// owns blocks [block0_j, block0_{j+1}) of 256 threads, each thread one output
+// (or four consecutive weights when `four`).
+struct ReduceJob {
+    const float *partial, *partial_b;
+    float *grads;
+    int splits, na, nb, out, in, four, block0;
+};
+struct ReduceJobs {
+    int n;
+    ReduceJob job[MAX_LAYERS];
+};
+
+__global__ __launch_bounds__(256) void wgrad_reduce_jobs_kernel(const ReduceJobs jobs)
+{
+    int jsel = 0;
+    for (int q = 1; q < jobs.n; ++q)
+        if ((int)blockIdx.x >= jobs.job[q].block0) jsel = q;
+    const ReduceJob &J = jobs.job[jsel];
+    const int64_t i = (int64_t)((int)blockIdx.x - J.block0) * blockDim.x + threadIdx.x;
+    if (J.four)
+        wgrad_reduce_four(i, J.partial, J.partial_b, J.splits, J.na, J.nb, J.out, J.in, J.grads);
+    else
+        wgrad_reduce_one(i, J.partial, J.partial_b, J.splits, J.na, J.nb, J.out, J.in, J.grads);
 }
 
 // Output-layer gradient from the backward seed's partials, one workgroup
@@ -1063,21 +1089,29 @@ static int backward_core(advisor_model *m, const float *dy, const void *saved, i
         hipLaunchKernelGGL(wgrad_kernel<PREC_BF16>, dim3((unsigned)wgs), dim3(256), WGRAD_LDS_BYTES,
                            s, all);
     ADV_LAUNCHED("wgrad_kernel");
+    // the split layers' fixed-order reductions, in one launch
+    ReduceJobs red{};
+    int blocks = 0;
     for (int l = 0; l < L; ++l) {
         const WgradJob &J = all.job[l];
         if (J.direct) continue;
-        const int out = J.dout, in = J.din, na = J.na, nb = J.nb, splits = J.splits;
-        float *gw = grads + m->layer_off[l];
-        const int64_t ne = (int64_t)out * in + out;
-        if (in % 4 == 0 && nb % 4 == 0 && ((uintptr_t)gw & 15) == 0) {
-            const int64_t ne4 = (int64_t)out * in / 4 + out;
-            hipLaunchKernelGGL(wgrad_reduce4_kernel, dim3((unsigned)((ne4 + 255) / 256)), dim3(256), 0,
-                               s, J.partial, J.partial_b, splits, na, nb, out, in, gw);
-        } else {
-            hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
-                               J.partial, J.partial_b, splits, na, nb, out, in, gw);
-        }
-        ADV_LAUNCHED("wgrad_reduce_kernel");
+        ReduceJob &R = red.job[red.n++];
+        R.partial = J.partial;
+        R.partial_b = J.partial_b;
+        R.grads = grads + m->layer_off[l];
+        R.splits = J.splits;
+        R.na = J.na;
+        R.nb = J.nb;
+        R.out = J.dout;
+        R.in = J.din;
+        R.four = (R.in % 4 == 0 && R.nb % 4 == 0 && ((uintptr_t)R.grads & 15) == 0) ? 1 : 0;
+        const int64_t ne = R.four ? (int64_t)R.out * R.in / 4 + R.out : (int64_t)R.out * R.in + R.out;
+        R.block0 = blocks;
+        blocks += (int)((ne + 255) / 256);
+    }
+    if (red.n > 0) {
+        hipLaunchKernelGGL(wgrad_reduce_jobs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, red);
+        ADV_LAUNCHED("wgrad_reduce_jobs_kernel");
     }
     return ADVISOR_OK;
 }
