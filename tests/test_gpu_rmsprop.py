@@ -299,6 +299,57 @@ def test_multi_model_plan_matches_separate_steps():
     plan.close()
 
 
+def test_paper_recipe_seven_models_batch16_eager():
+    """Section 5.3's recipe for seven targets (one model per cluster of the
+    paper's experiments, each on 2000 synthetic runtimes of 200 kernels of
+    its own), trained together with eager library steps: per minibatch of 16
+    rows every model takes its RMSprop step (lr 0.01 divided by 10 every 30
+    epochs, weight decay 1e-4, RMSE loss), 150 epochs each, 105,000 steps in
+    all. Every model's validation NRMSE ends below the paper's 0.1 bar. The
+    same recipe through one captured plan of the seven steps is the skipped
+    test below."""
+    widths = (32, 64, 128, 64, 32, 1)
+    T, N, bs, epochs = 7, 2000, 16, 150
+    n_train = int(0.8 * N)
+    models, trainers, data = [], [], []
+    for t in range(T):
+        kd, vd, off = workload.make_descriptors(200, 8, 40, 480 + 10 * t)
+        f, inv = oracle.featurize(kd, vd)
+        f = f[inv == 0]
+        f = f[np.random.default_rng(482 + 10 * t).permutation(f.shape[0])[:N]]
+        y = cost.target(f, workload.noise(f.shape[0], 483 + 10 * t))
+        mu, sd = oracle.zscore_fit(f[:n_train])
+        m = adv.Model(widths, "fp32")
+        m.set_params(workload.glorot_init(widths, 481 + 10 * t), mu, sd)
+        models.append(m)
+        trainers.append(adv.RMSpropTrainer(m))
+        data.append((to_dev(f[:n_train]), to_dev(y[:n_train]), f[n_train:], y[n_train:]))
+    rng = np.random.default_rng(489)
+    first, last = None, [None] * T
+    for epoch in range(epochs):
+        for tr in trainers:
+            tr.set_epoch(epoch)
+        # each model's epoch order, gathered once: its batches are row slices
+        order = [to_dev(rng.permutation(n_train)) for _ in range(T)]
+        Fe = [data[t][0][order[t]] for t in range(T)]
+        Ye = [data[t][1][order[t]] for t in range(T)]
+        for s in range(0, n_train - bs + 1, bs):
+            for t in range(T):
+                last[t], _ = trainers[t].step(Fe[t][s:s + bs], Ye[t][s:s + bs])
+        if first is None:
+            first = [host(v)[0] for v in last]
+        if epoch % 30 == 29:
+            say("recipe, seven models, batch 16: epoch %d" % epoch)
+    for t in range(T):
+        pred = host(models[t].predict(to_dev(data[t][2]))).astype(np.float64)
+        nr = oracle.nrmse(pred, data[t][3])
+        say("model %d: batch RMSE %.3f -> %.3f, validation NRMSE %.4f"
+            % (t, first[t], host(last[t])[0], nr))
+        assert nr < 0.1
+    for m in models:
+        m.close()
+
+
 @pytest.mark.skip(reason="crashed the host inside hipGraphLaunch twice (a segmentation fault "
                          "during thousands of unsynchronized replays of the seven-model plan, "
                          "then in the full suite after the destroy fix); kept off the GPU until "
