@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "wave_select.h"
 
 namespace adv {
 
@@ -75,40 +76,86 @@ CascadeLayout cascade_layout(int64_t n_v, int64_t n_k, const int *keep, int n_st
 constexpr int RF_WAVES = 4;
 constexpr int RF_UNROLL = 16;
 
-// order-preserving key of (prediction, row): smaller prediction first, then
-// lower row; -0 equals +0
-__device__ __forceinline__ uint64_t rf_key(float p, uint32_t row)
-{
-    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
-    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return ((uint64_t)u << 32) | row;
-}
-
 // One wave per kernel segment of a workload's predictions: the K smallest
-// keys of its non-NaN predictions (each lane keeps a sorted list of its own K
-// best, then K rounds of a wave-wide minimum pop the overall best), written
-// as candidate variant indices in ascending order, padded with -1. A row's
+// keys (prediction, row; pred_key) of its non-NaN predictions, written as
+// candidate variant indices in ascending order, padded with -1. Lists of 8
+// or more over a segment of at most 64 * RF_UNROLL rows take the threshold
+// path (threshold_select: a bound on the K-th smallest key from one wave
+// sort, then at most 64 candidates gathered and sorted, and the best K
+// sorted again by row); other segments, and threshold paths with more than
+// 64 candidates, keep a sorted list of each lane's own K best, then K rounds
+// of a wave-wide minimum pop the overall best. As in the top-N list, lists
+// of 8 or more take two launches: the first (TK_FAST, few registers) holds
+// only the threshold path and marks each kernel it leaves undone with -2 in
+// its first candidate slot; the second (TK_MARKED) runs the per-lane lists
+// on the marked kernels. Shorter lists take one launch (TK_ALL). A row's
 // variant index is map[row] for a compact workload (map = the previous
 // stage's candidates, ascending within each kernel, so row order is variant
 // order and ties still go to the lowest variant index), else the row itself.
 // The candidates' descriptor rows are gathered from the original vdesc with
 // kernel id k (padding rows get kernel id -1: never eligible).
-template <int K>
+enum { TK_ALL = 0, TK_FAST = 1, TK_MARKED = 2 };
+
+template <int K, int MODE>
 __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
     const float *__restrict__ pred, const int64_t *__restrict__ offsets,
     const int64_t *__restrict__ map, const int64_t *__restrict__ vdesc, int64_t n_k,
     int64_t n_rows, int64_t *__restrict__ cand, int64_t *__restrict__ vdesc_c,
     int64_t *__restrict__ off_c)
 {
+    __shared__ uint64_t cand_lds[RF_WAVES][64];
     const int lane = threadIdx.x & 63;
-    const int64_t k = (int64_t)blockIdx.x * RF_WAVES + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t k = (int64_t)blockIdx.x * RF_WAVES + wave;
     if (k > n_k) return;
+    if constexpr (MODE == TK_MARKED) {
+        if (k == n_k || cand[k * K] != -2) return;  // done by the threshold path
+    }
     if (k == n_k) {  // the last offset
         if (lane == 0) off_c[n_k] = n_k * K;
         return;
     }
     const int64_t lo = max((int64_t)0, min(offsets[k], n_rows));
     const int64_t hi = max(lo, min(offsets[k + 1], n_rows));
+    // candidate `slot` of this kernel: the variant of `row` (INT64_MAX: none)
+    // and its descriptor row, with kernel id k (-1 for padding)
+    auto emit = [&](int64_t row, int slot) {
+        const int64_t dst_row = k * K + slot;
+        int64_t var = -1;
+        if (row != INT64_MAX) var = map ? map[row] : row;
+        cand[dst_row] = var;
+        const int64_t *src = vdesc + (var >= 0 ? var : 0) * VD;
+        int64_t *dst = vdesc_c + dst_row * VD;
+#pragma unroll
+        for (int c = 0; c < VD; ++c) dst[c] = var >= 0 ? (c == 0 ? k : src[c]) : (c == 0 ? -1 : 0);
+    };
+    if constexpr (MODE == TK_FAST) {
+        if (hi - lo <= 64 * RF_UNROLL) {  // the same for every lane
+            uint64_t x[RF_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RF_UNROLL; ++u) {
+                const int64_t i = lo + lane + 64 * u;
+                const float pv = i < hi ? pred[i] : __builtin_nanf("");
+                x[u] = __builtin_isnan(pv) ? ~0ull : pred_key(pv, (uint32_t)i);
+            }
+            uint64_t v;
+            if (threshold_select(x, K, lane, cand_lds[wave], v)) {
+                // rows are below 2^32 - 1 (the variant count is below 2^32),
+                // so the all-ones row of padding sorts last; lanes 0..K-1
+                // end in ascending row order
+                const uint32_t r32 = lane < K && v != ~0ull ? (uint32_t)v : ~0u;
+                const uint32_t row = bitonic_from<2, K>(r32, lane);
+                if (lane < K) emit(row == ~0u ? INT64_MAX : (int64_t)row, lane);
+                if (lane == 0) off_c[k] = k * K;
+                return;
+            }
+        }
+        if (lane == 0) {
+            cand[k * K] = -2;  // left to the per-lane lists
+            off_c[k] = k * K;
+        }
+        return;
+    }
     uint64_t top[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) top[q] = ~0ull;
@@ -125,7 +172,7 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
 #pragma unroll
         for (int u = 0; u < RF_UNROLL; ++u) {
             if (__builtin_isnan(pv[u])) continue;
-            uint64_t x = rf_key(pv[u], (uint32_t)(base + 64 * u));
+            uint64_t x = pred_key(pv[u], (uint32_t)(base + 64 * u));
             if (x >= top[K - 1]) continue;
             // insertion into the sorted list (compile-time indices only)
 #pragma unroll
@@ -168,14 +215,7 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
         int slot = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) slot += (crow[r] < mine || (crow[r] == mine && r < lane)) ? 1 : 0;
-        const int64_t dst_row = k * K + slot;
-        int64_t var = -1;
-        if (mine != INT64_MAX) var = map ? map[mine] : mine;
-        cand[dst_row] = var;
-        const int64_t *src = vdesc + (var >= 0 ? var : 0) * VD;
-        int64_t *dst = vdesc_c + dst_row * VD;
-#pragma unroll
-        for (int c = 0; c < VD; ++c) dst[c] = var >= 0 ? (c == 0 ? k : src[c]) : (c == 0 ? -1 : 0);
+        emit(mine, slot);
     }
     if (lane == 0) off_c[k] = k * K;
 }
@@ -197,16 +237,24 @@ static int launch_topk(int K, const float *pred, const int64_t *offsets, const i
                        int64_t *vdesc_c, int64_t *off_c, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((n_k + 1 + RF_WAVES - 1) / RF_WAVES);
-#define ADV_TK(KK)                                                                        \
-    case KK:                                                                              \
-        hipLaunchKernelGGL(topk_gather_kernel<KK>, dim3(blocks), dim3(RF_WAVES * 64), 0, s, \
-                           pred, offsets, map, vdesc, n_k, n_rows, cand, vdesc_c, off_c);  \
+#define ADV_TK1(KK, MODE)                                                                        \
+    hipLaunchKernelGGL((topk_gather_kernel<KK, MODE>), dim3(blocks), dim3(RF_WAVES * 64), 0, s, \
+                       pred, offsets, map, vdesc, n_k, n_rows, cand, vdesc_c, off_c);
+#define ADV_TK(KK)                       \
+    case KK:                             \
+        if constexpr (KK >= 8) {         \
+            ADV_TK1(KK, TK_FAST)         \
+            ADV_TK1(KK, TK_MARKED)       \
+        } else {                         \
+            ADV_TK1(KK, TK_ALL)          \
+        }                                \
         break;
     switch (K) {
         ADV_TK(1) ADV_TK(2) ADV_TK(4) ADV_TK(8) ADV_TK(16) ADV_TK(32)
     default: return fail(ADVISOR_EINVAL, "candidates per kernel must be 1, 2, 4, 8, 16 or 32");
     }
 #undef ADV_TK
+#undef ADV_TK1
     ADV_LAUNCHED("topk_gather_kernel");
     return ADVISOR_OK;
 }

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "features.h"
+#include "wave_select.h"
 
 namespace adv {
 
@@ -124,52 +125,8 @@ __global__ void zscore_final_kernel(const double *__restrict__ part_sum,
 }
 
 // ---------------------------------------------------------------------------
-// Segmented argmin on predictions: one wave per kernel segment. The key of a
-// variant orders (prediction, index) lexicographically as one unsigned
-// 64-bit integer: the prediction's bits mapped to an order-preserving
-// unsigned form (after folding -0 into +0) in the high half, the index in the
-// low half. The minimum key is the lowest prediction, lowest index on ties.
-__device__ __forceinline__ uint64_t pred_key(float p, uint32_t idx)
-{
-    uint32_t u = __float_as_uint(p == 0.0f ? 0.0f : p);
-    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    return ((uint64_t)u << 32) | idx;
-}
-
-// One step of a min-reduction over lanes through a DPP lane permutation
-// inside each row of 16 lanes (the 64-bit key moves as two 32-bit halves).
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_min_u64(uint64_t v)
-{
-    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
-    const uint64_t o = ((uint64_t)ohi << 32) | olo;
-    return o < v ? o : v;
-}
-
-__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int lane)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Minimum over the 64 lanes of a wave, returned to every lane (all lanes must
-// be active): swaps of neighbours and of lane pairs inside each quad, then
-// the mirror images inside each half-row and row leave every lane of a row
-// with the row's minimum; the four rows' minima are read out and compared.
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
-{
-    v = dpp_min_u64<0xB1>(v);   // quad_perm [1,0,3,2]
-    v = dpp_min_u64<0x4E>(v);   // quad_perm [2,3,0,1]
-    v = dpp_min_u64<0x141>(v);  // row_half_mirror
-    v = dpp_min_u64<0x140>(v);  // row_mirror
-    const uint64_t a = read_lane_u64(v, 0), b = read_lane_u64(v, 16);
-    const uint64_t c = read_lane_u64(v, 32), d = read_lane_u64(v, 48);
-    const uint64_t ab = a < b ? a : b, cd = c < d ? c : d;
-    return ab < cd ? ab : cd;
-}
+// Segmented argmin on predictions: one wave per kernel segment, keys and
+// wave-wide exchanges from wave_select.h.
 
 // Loads in flight per lane in the selection kernels' scans: a segment of up
 // to 64 * SEL_UNROLL = 1024 variants is read in one round trip (the loads of
@@ -220,64 +177,6 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
     }
 }
 
-// The key of lane (lane xor J). Inside a row of 16 lanes the exchange is a
-// DPP move (xor 1 and 2: quad permutations; xor 4: the mirror image inside
-// each 8-lane half-row, then each quad reversed; xor 8: a rotation of the row
-// by 8); across rows it goes through the LDS crossbar (ds_bpermute).
-template <int J>
-__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t x)
-{
-    const int v = (int)x;
-    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false);
-    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false);
-    else if constexpr (J == 4) {
-        const int m = __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
-        return (uint32_t)__builtin_amdgcn_update_dpp(m, m, 0x1B, 0xf, 0xf, false);  // quad [3,2,1,0]
-    } else if constexpr (J == 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false);  // row_ror:8
-    } else {
-        return (uint32_t)__shfl_xor(v, J, 64);
-    }
-}
-
-// One compare-exchange step of a bitonic sort over the wave: runs of K lanes
-// alternate ascending and descending, partners are J lanes apart; the lower
-// lane of a pair keeps the smaller key in an ascending run and the larger
-// in a descending one.
-template <int K, int J>
-__device__ __forceinline__ uint64_t bitonic_step(uint64_t v, int lane)
-{
-    const uint32_t olo = xor_lane_u32<J>((uint32_t)v);
-    const uint32_t ohi = xor_lane_u32<J>((uint32_t)(v >> 32));
-    const uint64_t o = ((uint64_t)ohi << 32) | olo;
-    const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
-    v = ((o < v) == keep_min) ? o : v;
-    if constexpr (J > 1) return bitonic_step<K, J / 2>(v, lane);
-    else return v;
-}
-
-template <int K>
-__device__ __forceinline__ uint64_t bitonic_from(uint64_t v, int lane)
-{
-    v = bitonic_step<K, K / 2>(v, lane);
-    if constexpr (K < 64) return bitonic_from<2 * K>(v, lane);
-    else return v;
-}
-
-// Ascending bitonic sort of one 64-bit key per lane over the 64 lanes of a
-// wave (lane r ends with the r-th smallest key): 21 compare-exchange steps,
-// 18 of them DPP moves inside rows of 16 lanes. Every lane must be active.
-__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v, int lane)
-{
-    return bitonic_from<2>(v, lane);
-}
-
-// The prediction a key was made from (pred_key inverted; -0 comes back as +0).
-__device__ __forceinline__ float key_pred(uint64_t key)
-{
-    const uint32_t u = (uint32_t)(key >> 32);
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
 
 // The top-N list of the prediction flow (section 3: the predicted runtimes
 // are sorted and the N best variants kept). One wave per kernel segment, in a
@@ -291,18 +190,13 @@ __device__ __forceinline__ float key_pred(uint64_t key)
 // take one launch (TOPN_ALL) of the per-lane lists.
 //
 // A segment of at most 64 * SEL_UNROLL variants (one load pass) takes the
-// threshold path: every lane's minimum key goes into one wave
-// sort, whose N-th smallest value t bounds the segment's N-th smallest key
-// from above (the N lane minima at or below t are N eligible variants);
-// only keys <= t can rank, and when there are at most 64 of them they are
-// gathered through LDS (each lane's at its rank among the wave's
-// candidates, counted per load slot with a ballot) and one more wave sort
-// puts them in order. Every other segment (longer ones, more than 64
-// candidates): each lane keeps the K smallest keys it has seen (a
-// sorted list held in registers, compile-time indices only, entered only by
-// keys that beat its current K-th), then N rounds of a wave-wide minimum pop
-// the segment's best keys in ascending order (keys are unique, so exactly one
-// lane pops each).
+// threshold path (threshold_select: a bound on the N-th smallest key from
+// one wave sort, then at most 64 candidates gathered and sorted). Every
+// other segment (longer ones, more than 64 candidates): each lane keeps the
+// K smallest keys it has seen (a sorted list held in registers, compile-time
+// indices only, entered only by keys that beat its current K-th), then N
+// rounds of a wave-wide minimum pop the segment's best keys in ascending
+// order (keys are unique, so exactly one lane pops each).
 enum { TOPN_ALL = 0, TOPN_FAST = 1, TOPN_MARKED = 2 };
 
 template <int K, int MODE>
@@ -325,36 +219,12 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
                 float p[SEL_UNROLL];
                 load_pass(pred, lo + lane, hi, p);
                 uint64_t x[SEL_UNROLL];
-                uint64_t m = ~0ull;
 #pragma unroll
-                for (int u = 0; u < SEL_UNROLL; ++u) {
+                for (int u = 0; u < SEL_UNROLL; ++u)
                     x[u] = __builtin_isnan(p[u]) ? ~0ull
                                                  : pred_key(p[u], (uint32_t)(lo + lane + 64 * u));
-                    m = x[u] < m ? x[u] : m;
-                }
-                const uint64_t t = read_lane_u64(wave_sort_u64(m, lane), N - 1);
-                // no eligible key is ~0 (its high half would be a NaN's)
-                uint64_t mask[SEL_UNROLL];
-                uint32_t total = 0;
-#pragma unroll
-                for (int u = 0; u < SEL_UNROLL; ++u) {
-                    mask[u] = __ballot(x[u] <= t && x[u] != ~0ull);
-                    total += (uint32_t)__popcll(mask[u]);
-                }
-                if (total <= 64) {
-                    uint64_t *slot = cand_lds[wave];
-                    uint32_t at = 0;
-#pragma unroll
-                    for (int u = 0; u < SEL_UNROLL; ++u) {
-                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(mask[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask[u], 0u));
-                        if ((mask[u] >> lane) & 1ull) slot[at + below] = x[u];
-                        at += (uint32_t)__popcll(mask[u]);
-                    }
-                    // this wave's LDS writes are done before its reads below
-                    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-                    uint64_t v = (uint32_t)lane < total ? slot[lane] : ~0ull;
-                    v = wave_sort_u64(v, lane);
+                uint64_t v;
+                if (threshold_select(x, N, lane, cand_lds[wave], v)) {
                     if (lane < N) {
                         const int64_t s_ = k * N + lane;
                         const bool some = v != ~0ull;

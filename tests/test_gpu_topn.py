@@ -79,7 +79,10 @@ def test_topn_preds_one_pass_segments(n):
     pass boundary, and segments built so that more than 64 variants lie at
     or below the threshold (the lane-list path takes over): nine lanes full
     of small values and a tenth whose smallest is larger than all of them,
-    and fewer eligible lanes than N with many eligible variants each."""
+    and fewer eligible lanes than N with many eligible variants each. Flat
+    and coarsely rounded segments put many more than 64 variants on the
+    N-th smallest prediction itself, where the bound falls back from the
+    prediction to the whole key (prediction, then index)."""
     rng = np.random.default_rng(80 + n)
     lens = [1, 2, 63, 64, 65, 577, 1023, 1024, 1025, 2048]
     lens += [int(x) for x in rng.integers(1, 1025, size=300)]
@@ -94,6 +97,12 @@ def test_topn_preds_one_pass_segments(n):
     segs.append(few)
     ties = np.round(rng.standard_normal(1000), 1).astype(np.float32)  # many equal values
     segs.append(ties)
+    flat = np.full(1024, 0.5, dtype=np.float32)
+    flat[rng.choice(1024, 5, replace=False)] = -1.0
+    segs.append(flat)
+    segs.append(np.full(700, 2.0, dtype=np.float32))
+    for L in (200, 700, 900, 1024):
+        segs.append((np.round(rng.standard_normal(L) * 4) / 4).astype(np.float32))
     pred = np.concatenate(segs)
     pred[rng.random(pred.size) < 0.02] = np.nan
     off = np.concatenate([[0], np.cumsum([x.size for x in segs])]).astype(np.int64)
