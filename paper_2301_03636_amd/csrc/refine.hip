@@ -84,11 +84,12 @@ constexpr int RF_UNROLL = 16;
 // sort, then at most 64 candidates gathered and sorted, and the best K
 // sorted again by row); other segments, and threshold paths with more than
 // 64 candidates, keep a sorted list of each lane's own K best, then K rounds
-// of a wave-wide minimum pop the overall best. As in the top-N list, lists
-// of 8 or more take two launches: the first (TK_FAST, few registers) holds
-// only the threshold path and marks each kernel it leaves undone with -2 in
-// its first candidate slot; the second (TK_MARKED) runs the per-lane lists
-// on the marked kernels. Shorter lists take one launch (TK_ALL). A row's
+// of a wave-wide minimum pop the overall best. Lists of 8 or more take two
+// launches: the first (TK_FAST, few registers) holds only the threshold path
+// and marks each kernel it leaves undone with -2 in its first candidate
+// slot; the second (TK_MARKED) runs the per-lane lists on the marked
+// kernels. Shorter lists take one launch (TK_ALL) of the lists, which was
+// measured faster for them. A row's
 // variant index is map[row] for a compact workload (map = the previous
 // stage's candidates, ascending within each kernel, so row order is variant
 // order and ties still go to the lowest variant index), else the row itself.
@@ -130,6 +131,8 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
         for (int c = 0; c < VD; ++c) dst[c] = var >= 0 ? (c == 0 ? k : src[c]) : (c == 0 ? -1 : 0);
     };
     if constexpr (MODE == TK_FAST) {
+        // 16-byte copies of descriptor rows where both ends allow them
+        const bool wide = ((reinterpret_cast<uintptr_t>(vdesc) | reinterpret_cast<uintptr_t>(vdesc_c)) & 15) == 0;
         if (hi - lo <= 64 * RF_UNROLL) {  // the same for every lane
             uint64_t x[RF_UNROLL];
 #pragma unroll
@@ -145,7 +148,42 @@ __global__ __launch_bounds__(RF_WAVES * 64) void topk_gather_kernel(
                 // end in ascending row order
                 const uint32_t r32 = lane < K && v != ~0ull ? (uint32_t)v : ~0u;
                 const uint32_t row = bitonic_from<2, K>(r32, lane);
-                if (lane < K) emit(row == ~0u ? INT64_MAX : (int64_t)row, lane);
+                int64_t var = -1;
+                if (lane < K && row != ~0u) var = map ? map[row] : (int64_t)row;
+                if (lane < K) cand[k * K + lane] = var;
+                // the K descriptor rows are one contiguous block of the
+                // output: LPC lanes copy each row, CPL columns apiece
+                constexpr int LPC = 64 / K < VD ? 64 / K : VD, CPL = VD / LPC;
+                static_assert(VD % LPC == 0, "a row splits evenly over its lanes");
+                const int c = min(lane / LPC, K - 1), part = lane % LPC;
+                const bool copies = lane < K * LPC;
+                const uint32_t vlo = (uint32_t)__shfl((int)(uint32_t)var, c, 64);
+                const uint32_t vhi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)var >> 32), c, 64);
+                const int64_t vc = (int64_t)(((uint64_t)vhi << 32) | vlo);
+                const int64_t *src = vdesc + (vc >= 0 ? vc : 0) * VD + part * CPL;
+                int64_t *dst = vdesc_c + (k * K + c) * VD + part * CPL;
+                int64_t col[CPL];
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    const int cc = part * CPL + q;
+                    col[q] = cc == 0 ? (vc >= 0 ? k : -1) : 0;
+                }
+                typedef long long v2ll_ __attribute__((ext_vector_type(2)));
+                if constexpr (CPL % 2 == 0) {
+                    if (wide && copies) {
+#pragma unroll
+                        for (int q = 0; q < CPL; q += 2) {
+                            v2ll_ w = vc >= 0 ? *reinterpret_cast<const v2ll_ *>(src + q) : v2ll_{0, 0};
+                            if (part * CPL + q == 0) w[0] = col[0];
+                            *reinterpret_cast<v2ll_ *>(dst + q) = w;
+                        }
+                    }
+                }
+                if ((CPL % 2 != 0 || !wide) && copies) {
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q)
+                        dst[q] = vc >= 0 && part * CPL + q != 0 ? src[q] : col[q];
+                }
                 if (lane == 0) off_c[k] = k * K;
                 return;
             }
