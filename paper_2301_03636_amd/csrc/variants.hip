@@ -115,56 +115,109 @@ __global__ void vg_zero_kernel(int64_t *p) { *p = 0; }
 // placement = r / (2 n_sched) in the order x = 0 (c = 1..n), then x = 1..n-1
 // with (d, c) row-major over 1..x by 1..n-x. Rows past the kernel's own
 // count (offsets not from the count pass) are written as -1.
+//
+// The decode depends only on (n, r) and the schedule mask, so each workgroup
+// first decodes every row of every loop count (VG_TABLE entries) into LDS,
+// four bits per field; a row then costs one LDS read. Each lane writes
+// whole rows (48 bytes: three 16-byte stores where the output is 16-byte
+// aligned, so the wave's three stores fill 3 KB of the output together). A
+// wave takes VG_KPW consecutive kernels at a time: their offsets and loop
+// counts come in one load, one per lane, so a wave pays one memory round
+// trip for several kernels' rows.
+constexpr int VG_KPW = 8;
+
+__device__ __forceinline__ int64_t read_lane_i64(int64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+constexpr int VG_TABLE = 6 + 18 + 42 + 84;  // n^3 + 5n rows for n = 1..4
+
+__device__ __forceinline__ int vg_table_base(int n)  // first entry of loop count n
+{
+    return n == 1 ? 0 : (n == 2 ? 6 : (n == 3 ? 24 : 66));
+}
+
 __global__ __launch_bounds__(VG_THREADS) void vg_rows_kernel(
     const int64_t *__restrict__ n_loops, const int64_t *__restrict__ offsets, int64_t n_k,
     int64_t n_v, int sched_mask, int n_sched, int64_t *__restrict__ out)
 {
+    static_assert(ADVISOR_VARIANT_COLS == 6 && ADVISOR_MAX_LOOPS == 4, "table layout");
+    __shared__ uint32_t table[VG_TABLE];
+    for (int t = threadIdx.x; t < VG_TABLE; t += VG_THREADS) {
+        const int nn = t < 6 ? 1 : (t < 24 ? 2 : (t < 66 ? 3 : 4));
+        const int r = t - vg_table_base(nn);
+        uint32_t e = 0xffffffffu;  // rows past this mask's count: never read
+        if (r < vg_count(nn, n_sched)) {
+            const int data = r & 1;
+            const int q = r >> 1;
+            const int si = q % n_sched;
+            int p = q / n_sched;
+            int sch = 0;
+            for (int b = 0, seen = 0; b < 3; ++b)
+                if ((sched_mask >> b) & 1) {
+                    if (seen == si) sch = b;
+                    ++seen;
+                }
+            int x = 0, d = 0, c = 0;
+            if (p < nn) {
+                c = p + 1;
+            } else {
+                p -= nn;
+                for (x = 1; x < nn; ++x) {
+                    const int m = x * (nn - x);
+                    if (p < m) break;
+                    p -= m;
+                }
+                d = p / (nn - x) + 1;
+                c = p % (nn - x) + 1;
+            }
+            e = (uint32_t)x | ((uint32_t)d << 4) | ((uint32_t)c << 8) | ((uint32_t)sch << 12) |
+                ((uint32_t)data << 16);
+        }
+        table[t] = e;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * VG_WAVES;
-    for (int64_t k = (int64_t)blockIdx.x * VG_WAVES + (threadIdx.x >> 6); k < n_k; k += nwaves) {
-        const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
-        const int64_t hi = max(lo, min(offsets[k + 1], n_v));
-        const int64_t n = n_loops[k];
-        const int64_t cnt = vg_count(n, n_sched);
-        const int64_t seg0 = offsets[k];
-        for (int64_t w = lo * ADVISOR_VARIANT_COLS + lane; w < hi * ADVISOR_VARIANT_COLS; w += 64) {
-            const int64_t row = w / ADVISOR_VARIANT_COLS;
-            const int col = (int)(w - row * ADVISOR_VARIANT_COLS);
-            const int64_t r64 = row - seg0;
-            int64_t val = -1;
-            if (r64 >= 0 && r64 < cnt) {
-                // a kernel has at most 84 rows and 1 <= n <= 4 here: 32-bit decode
-                const int r = (int)r64, nn = (int)n;
-                const int data = r & 1;
-                const int q = r >> 1;
-                const int si = q % n_sched;
-                int p = q / n_sched;
-                int sch = 0;
-                for (int b = 0, seen = 0; b < 3; ++b)
-                    if ((sched_mask >> b) & 1) {
-                        if (seen == si) sch = b;
-                        ++seen;
-                    }
-                int x = 0, d = 0, c = 0;
-                if (p < nn) {
-                    c = p + 1;
-                } else {
-                    p -= nn;
-                    for (x = 1; x < nn; ++x) {
-                        const int m = x * (nn - x);
-                        if (p < m) break;
-                        p -= m;
-                    }
-                    d = p / (nn - x) + 1;
-                    c = p % (nn - x) + 1;
-                }
-                const int64_t vals[ADVISOR_VARIANT_COLS] = {k, x, d, c, sch, data};
-                val = vals[0];
+    const bool wide = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    typedef long long v2ll_ __attribute__((ext_vector_type(2)));
+    const int64_t wave0 = (int64_t)blockIdx.x * VG_WAVES + (threadIdx.x >> 6);
+    for (int64_t k0 = wave0 * VG_KPW; k0 < n_k; k0 += nwaves * VG_KPW) {
+        // lane j holds offsets[k0 + j] (j <= VG_KPW) and n_loops[k0 + j]
+        const int64_t kl = k0 + lane;
+        const int64_t offl = lane <= VG_KPW && kl <= n_k ? offsets[kl] : 0;
+        const int64_t nl = lane < VG_KPW && kl < n_k ? n_loops[kl] : 0;
+        const int nb = (int)min((int64_t)VG_KPW, n_k - k0);
+        for (int j = 0; j < nb; ++j) {
+            const int64_t k = k0 + j;
+            const int64_t seg0 = read_lane_i64(offl, j);
+            const int64_t lo = max((int64_t)0, min(seg0, n_v));
+            const int64_t hi = max(lo, min(read_lane_i64(offl, j + 1), n_v));
+            const int64_t n = read_lane_i64(nl, j);
+            const int64_t cnt = vg_count(n, n_sched);
+            const int base = cnt > 0 ? vg_table_base((int)n) : 0;
+            for (int64_t row = lo + lane; row < hi; row += 64) {
+                const int64_t r64 = row - seg0;
+                int64_t v[ADVISOR_VARIANT_COLS] = {-1, -1, -1, -1, -1, -1};
+                if (r64 >= 0 && r64 < cnt) {
+                    // at most 84 rows per kernel: a 32-bit index into the table
+                    const uint32_t e = table[base + (int)r64];
+                    v[0] = k;
 #pragma unroll
-                for (int j = 1; j < ADVISOR_VARIANT_COLS; ++j)
-                    if (col == j) val = vals[j];
+                    for (int c = 1; c < ADVISOR_VARIANT_COLS; ++c) v[c] = (int64_t)((e >> (4 * (c - 1))) & 15u);
+                }
+                int64_t *o = out + row * ADVISOR_VARIANT_COLS;
+                if (wide) {
+#pragma unroll
+                    for (int c = 0; c < ADVISOR_VARIANT_COLS; c += 2)
+                        *reinterpret_cast<v2ll_ *>(o + c) = v2ll_{v[c], v[c + 1]};
+                } else {
+#pragma unroll
+                    for (int c = 0; c < ADVISOR_VARIANT_COLS; ++c) o[c] = v[c];
+                }
             }
-            out[w] = val;
         }
     }
 }
@@ -280,7 +333,8 @@ extern "C" int advisor_enumerate_variants(const int64_t *n_loops, const int64_t 
     if (!offsets || !variants_out) return fail(ADVISOR_EINVAL, "advisor_enumerate_variants: null pointer");
     hipStream_t s = as_stream(stream);
     const int n_sched = __builtin_popcount((unsigned)sched_mask);
-    const int64_t blocks = std::min<int64_t>((n_kernels + VG_WAVES - 1) / VG_WAVES, 1 << 20);
+    const int64_t blocks =
+        std::min<int64_t>((n_kernels + VG_WAVES * VG_KPW - 1) / (VG_WAVES * VG_KPW), 1 << 20);
     hipLaunchKernelGGL(vg_rows_kernel, dim3((unsigned)blocks), dim3(VG_THREADS), 0, s, n_loops,
                        offsets, n_kernels, n_variants, sched_mask, n_sched, variants_out);
     ADV_LAUNCHED("vg_rows_kernel");
