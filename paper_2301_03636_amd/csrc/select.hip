@@ -178,6 +178,83 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
 }
 
 
+// Long segments (on average AM_LONG variants or more per kernel, where one
+// wave per segment leaves most of the chip idle): the variants are cut into
+// chunks of AM_CHUNK, one wave each. A wave finds the segment holding its
+// chunk's first variant (the last k with offsets[k] <= start: rounds of 64
+// offsets sampled across the remaining range, one load and a ballot each),
+// walks the segments its chunk overlaps, and folds each one's minimum key
+// into keys[k] with a 64-bit atomic minimum (keys start at ~0; the key holds
+// the index, so the result does not depend on the order of the atomics).
+// Every index is clamped, so offsets that break the contract (not
+// non-decreasing) give wrong picks but no access out of bounds.
+constexpr int64_t AM_CHUNK = 4096;
+constexpr int64_t AM_LONG = 16384;
+
+__global__ __launch_bounds__(AM_WAVES * 64) void argmin_chunks_kernel(
+    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, unsigned long long *__restrict__ keys)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t c0 = ((int64_t)blockIdx.x * AM_WAVES + wave) * AM_CHUNK;
+    if (c0 >= n_v) return;
+    const int64_t c1 = min(c0 + AM_CHUNK, n_v);
+    // the last k in [a, b] with offsets[k] <= c0 (offsets[0] = 0 <= c0)
+    int64_t a = 0, b = n_k - 1;
+    while (b > a) {
+        const int64_t span = b - a + 1;
+        const int64_t kj = span <= 64 ? a + lane : a + (int64_t)lane * span / 64;
+        const bool ok = kj <= b && offsets[kj] <= c0;
+        const uint64_t m = __ballot(ok);
+        if (m == 0) break;  // only for offsets[a] > c0: not a valid offsets array
+        const int j = 63 - __builtin_clzll(m);
+        const int64_t ka = span <= 64 ? a + j : a + (int64_t)j * span / 64;
+        if (span <= 64) {
+            a = ka;
+            break;
+        }
+        const int64_t kb = j == 63 ? b : a + (int64_t)(j + 1) * span / 64 - 1;
+        a = ka;
+        b = max(ka, kb);
+    }
+    int64_t pos = c0;
+    for (int64_t k = a; k < n_k && pos < c1; ++k) {
+        const int64_t hi = min(max(offsets[k + 1], pos), c1);
+        uint64_t key = ~0ull;
+        for (int64_t base = pos + lane; base < hi; base += 64 * SEL_UNROLL) {
+            float p[SEL_UNROLL];
+            load_pass(pred, base, hi, p);
+#pragma unroll
+            for (int u = 0; u < SEL_UNROLL; ++u) {
+                if (!__builtin_isnan(p[u])) {
+                    const uint64_t q = pred_key(p[u], (uint32_t)(base + 64 * u));
+                    key = q < key ? q : key;
+                }
+            }
+        }
+        key = wave_min_u64(key);
+        if (lane == 0 && key != ~0ull) atomicMin(keys + k, (unsigned long long)key);
+        pos = hi;
+    }
+}
+
+__global__ void argmin_keys_init_kernel(unsigned long long *keys, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = ~0ull;
+}
+
+// key -> variant index (its low 32 bits), -1 where no variant was eligible
+__global__ void argmin_keys_final_kernel(int64_t *best, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint64_t k = (uint64_t)best[i];
+        best[i] = k == ~0ull ? -1 : (int64_t)(k & 0xffffffffull);
+    }
+}
+
 // The top-N list of the prediction flow (section 3: the predicted runtimes
 // are sorted and the N best variants kept). One wave per kernel segment, in a
 // grid-stride loop over kernels. Lane r writes rank r: the variant index and
@@ -432,9 +509,22 @@ extern "C" int advisor_rank_preds(const float *pred, const int64_t *offsets, int
     if (debug_offsets(as_stream(stream))) {
         if (int rc = advisor_validate_offsets(offsets, n_kernels, n_variants, nullptr, stream)) return rc;
     }
+    hipStream_t s = as_stream(stream);
+    if (n_variants >= AM_LONG * n_kernels) {
+        // long segments: chunks of variants, per-kernel keys in best_out
+        unsigned long long *keys = reinterpret_cast<unsigned long long *>(best_out);
+        const unsigned kb = (unsigned)((n_kernels + 255) / 256);
+        hipLaunchKernelGGL(argmin_keys_init_kernel, dim3(kb), dim3(256), 0, s, keys, n_kernels);
+        const int64_t waves = (n_variants + AM_CHUNK - 1) / AM_CHUNK;
+        hipLaunchKernelGGL(argmin_chunks_kernel, dim3((unsigned)((waves + AM_WAVES - 1) / AM_WAVES)),
+                           dim3(AM_WAVES * 64), 0, s, pred, offsets, n_kernels, n_variants, keys);
+        hipLaunchKernelGGL(argmin_keys_final_kernel, dim3(kb), dim3(256), 0, s, best_out, n_kernels);
+        ADV_LAUNCHED("argmin_chunks_kernel");
+        return ADVISOR_OK;
+    }
     const int64_t blocks = std::min<int64_t>((n_kernels + AM_WAVES - 1) / AM_WAVES, 1 << 20);
     hipLaunchKernelGGL(argmin_preds_kernel, dim3((unsigned)blocks), dim3(AM_WAVES * 64), 0,
-                       as_stream(stream), pred, offsets, n_kernels, n_variants, best_out);
+                       s, pred, offsets, n_kernels, n_variants, best_out);
     ADV_LAUNCHED("argmin_preds_kernel");
     return ADVISOR_OK;
 }

@@ -112,6 +112,30 @@ def test_rank_preds_long_segments():
     assert best.tolist() == oracle.argmin(pred.astype(np.float64), off).tolist()
 
 
+def test_rank_preds_chunked_long_segments():
+    """Kernels of 16384 or more variants on average take the chunked form
+    (waves over fixed chunks of variants, per-kernel atomic minima of the
+    keys): segment ends on and off the chunk boundaries, empty and all-NaN
+    segments, short segments among long ones, and equal values spread over
+    many chunks (the lowest index must still win), against the oracle."""
+    rng = np.random.default_rng(6)
+    n = 1_500_000
+    pred = np.round(rng.standard_normal(n), 1).astype(np.float32)  # many ties
+    pred[rng.random(n) < 0.01] = np.nan
+    cuts = [0, 5, 5, 16384, 16385, 32768, 200000, 200000, 200003, 700000, 1_000_000]
+    pred[200000:200003] = np.nan                       # an all-NaN segment
+    pred[900000] = -7.0                                # one clear winner
+    pred[[400000, 650000]] = -9.0                      # a tie across chunks
+    pred[-1] = -0.0
+    off = np.array(cuts + [n], dtype=np.int64)
+    assert n >= 16384 * (off.size - 1)
+    say("argmin chunked: %d kernels, %d variants" % (off.size - 1, n))
+    best = host(adv.advisor_rank_preds(to_dev(pred), to_dev(off)))
+    assert best.tolist() == oracle.argmin(pred.astype(np.float64), off).tolist()
+    assert best[1] == -1 and best[6] == -1 and best[7] == -1  # empty, empty, all NaN
+    assert best[8] == 400000 and best[9] == 900000
+
+
 @pytest.mark.parametrize("widths", [(32, 64, 64, 1), (32, 256, 256, 256, 1), (32, 8, 1),
                                     (32, 48, 24, 40, 1), (32, 512, 512, 1),
                                     (32, 1024, 1024, 1)])
