@@ -178,29 +178,52 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_preds_kernel(
 }
 
 
-// Long segments (on average AM_LONG variants or more per kernel, where one
-// wave per segment leaves most of the chip idle): the variants are cut into
-// chunks of AM_CHUNK, one wave each. A wave finds the segment holding its
-// chunk's first variant (the last k with offsets[k] <= start: rounds of 64
-// offsets sampled across the remaining range, one load and a ballot each),
-// walks the segments its chunk overlaps, and folds each one's minimum key
-// into keys[k] with a 64-bit atomic minimum (keys start at ~0; the key holds
-// the index, so the result does not depend on the order of the atomics).
-// Every index is clamped, so offsets that break the contract (not
-// non-decreasing) give wrong picks but no access out of bounds.
-constexpr int64_t AM_CHUNK = 4096;
-constexpr int64_t AM_LONG = 16384;
-
-__global__ __launch_bounds__(AM_WAVES * 64) void argmin_chunks_kernel(
-    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
-    int64_t n_v, unsigned long long *__restrict__ keys)
+// A lane's sorted list of the K smallest keys it has seen (compile-time
+// indices only): a key enters only if it beats the current K-th.
+template <int K>
+__device__ __forceinline__ void list_insert(uint64_t (&top)[K], uint64_t x)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t c0 = ((int64_t)blockIdx.x * AM_WAVES + wave) * AM_CHUNK;
-    if (c0 >= n_v) return;
-    const int64_t c1 = min(c0 + AM_CHUNK, n_v);
-    // the last k in [a, b] with offsets[k] <= c0 (offsets[0] = 0 <= c0)
+    if (x >= top[K - 1]) return;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const uint64_t t = top[q];
+        const bool less = x < t;
+        top[q] = less ? x : t;
+        x = less ? t : x;
+    }
+}
+
+// N rounds of a wave-wide minimum over the lists' heads pop the wave's N
+// smallest keys in ascending order (keys are unique, so exactly one lane
+// pops each); lane r gets the r-th, ~0 past the last key. N <= K, the same
+// in every lane; every lane must be active.
+template <int K>
+__device__ __forceinline__ uint64_t list_pop(uint64_t (&top)[K], int N, int lane)
+{
+    uint64_t mine = ~0ull;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        if (r >= N) break;
+        const uint64_t v = wave_min_u64(top[0]);
+        if (v == ~0ull) break;  // fewer than N keys
+        if (lane == r) mine = v;
+        if (top[0] == v) {
+#pragma unroll
+            for (int q = 0; q + 1 < K; ++q) top[q] = top[q + 1];
+            top[K - 1] = ~0ull;
+        }
+    }
+    return mine;
+}
+
+// The last k in [0, n_k) with offsets[k] <= c0 (offsets non-decreasing,
+// offsets[0] = 0 <= c0): rounds of 64 offsets sampled across the remaining
+// range, one load and a ballot each. Uniform over the wave; every lane must
+// be active. With offsets that break the contract the result is some k in
+// range.
+__device__ __forceinline__ int64_t segment_of(const int64_t *__restrict__ offsets, int64_t n_k,
+                                              int64_t c0, int lane)
+{
     int64_t a = 0, b = n_k - 1;
     while (b > a) {
         const int64_t span = b - a + 1;
@@ -218,6 +241,30 @@ __global__ __launch_bounds__(AM_WAVES * 64) void argmin_chunks_kernel(
         a = ka;
         b = max(ka, kb);
     }
+    return a;
+}
+
+// Long segments (on average AM_LONG variants or more per kernel, where one
+// wave per segment leaves most of the chip idle): the variants are cut into
+// chunks of AM_CHUNK, one wave each. A wave finds the segment holding its
+// chunk's first variant (segment_of), walks the segments its chunk overlaps, and folds each one's minimum key
+// into keys[k] with a 64-bit atomic minimum (keys start at ~0; the key holds
+// the index, so the result does not depend on the order of the atomics).
+// Every index is clamped, so offsets that break the contract (not
+// non-decreasing) give wrong picks but no access out of bounds.
+constexpr int64_t AM_CHUNK = 4096;
+constexpr int64_t AM_LONG = 16384;
+
+__global__ __launch_bounds__(AM_WAVES * 64) void argmin_chunks_kernel(
+    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, unsigned long long *__restrict__ keys)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t c0 = ((int64_t)blockIdx.x * AM_WAVES + wave) * AM_CHUNK;
+    if (c0 >= n_v) return;
+    const int64_t c1 = min(c0 + AM_CHUNK, n_v);
+    const int64_t a = segment_of(offsets, n_k, c0, lane);
     int64_t pos = c0;
     for (int64_t k = a; k < n_k && pos < c1; ++k) {
         const int64_t hi = min(max(offsets[k + 1], pos), c1);
@@ -327,32 +374,80 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
             float p[SEL_UNROLL];
             load_pass(pred, base, hi, p);
 #pragma unroll
-            for (int u = 0; u < SEL_UNROLL; ++u) {
-                if (__builtin_isnan(p[u])) continue;
-                uint64_t x = pred_key(p[u], (uint32_t)(base + 64 * u));
-                if (x >= top[K - 1]) continue;
-#pragma unroll
-                for (int q = 0; q < K; ++q) {
-                    const uint64_t t = top[q];
-                    const bool less = x < t;
-                    top[q] = less ? x : t;
-                    x = less ? t : x;
-                }
-            }
+            for (int u = 0; u < SEL_UNROLL; ++u)
+                if (!__builtin_isnan(p[u])) list_insert(top, pred_key(p[u], (uint32_t)(base + 64 * u)));
         }
-        int64_t mine = -1;
-#pragma unroll
-        for (int r = 0; r < K; ++r) {
-            if (r >= N) break;  // N is the same for every lane
-            const uint64_t v = wave_min_u64(top[0]);
-            if (v == ~0ull) break;  // the segment has fewer than N eligible variants
-            if (lane == r) mine = (int64_t)(v & 0xffffffffull);
-            if (top[0] == v) {
-#pragma unroll
-                for (int q = 0; q + 1 < K; ++q) top[q] = top[q + 1];
-                top[K - 1] = ~0ull;
-            }
+        const uint64_t v = list_pop(top, N, lane);
+        const int64_t mine = v == ~0ull ? -1 : (int64_t)(v & 0xffffffffull);
+        if (lane < N) {
+            const int64_t slot = k * N + lane;
+            idx_out[slot] = mine;
+            if (val_out) val_out[slot] = mine >= 0 ? pred[mine] : __builtin_nanf("");
         }
+    }
+}
+
+// Top-N on long segments (AM_LONG variants or more per kernel on average):
+// chunks of AM_CHUNK variants, one wave each, find their first segment as
+// the chunked argmin does; for every segment k a chunk c overlaps, the
+// overlap's N best keys (per-lane lists, then N pops) go to list c + k of a
+// scratch array of (chunks + n_k) lists of N keys (a later segment only
+// overlaps later chunks, so the lists of different overlaps never share a
+// slot, and segment k's chunks own the consecutive lists c_first + k ..
+// c_last + k). A second launch, one wave per segment, takes the N best keys
+// of its lists the same way and writes the segment's top-N list.
+template <int K>
+__global__ __launch_bounds__(AM_WAVES * 64) void topn_chunks_kernel(
+    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, int N, uint64_t *__restrict__ lists)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t c = (int64_t)blockIdx.x * AM_WAVES + wave;
+    const int64_t c0 = c * AM_CHUNK;
+    if (c0 >= n_v) return;
+    const int64_t c1 = min(c0 + AM_CHUNK, n_v);
+    int64_t pos = c0;
+    for (int64_t k = segment_of(offsets, n_k, c0, lane); k < n_k && pos < c1; ++k) {
+        const int64_t hi = min(max(offsets[k + 1], pos), c1);
+        if (hi == pos) continue;
+        uint64_t top[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) top[q] = ~0ull;
+        for (int64_t base = pos + lane; base < hi; base += 64 * SEL_UNROLL) {
+            float p[SEL_UNROLL];
+            load_pass(pred, base, hi, p);
+#pragma unroll
+            for (int u = 0; u < SEL_UNROLL; ++u)
+                if (!__builtin_isnan(p[u])) list_insert(top, pred_key(p[u], (uint32_t)(base + 64 * u)));
+        }
+        const uint64_t v = list_pop(top, N, lane);
+        if (lane < N) lists[(c + k) * N + lane] = v;
+        pos = hi;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(AM_WAVES * 64) void topn_merge_kernel(
+    const float *__restrict__ pred, const int64_t *__restrict__ offsets, int64_t n_k,
+    int64_t n_v, int N, const uint64_t *__restrict__ lists, int64_t *__restrict__ idx_out,
+    float *__restrict__ val_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves_total = (int64_t)gridDim.x * AM_WAVES;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int64_t k = (int64_t)blockIdx.x * AM_WAVES + wave; k < n_k; k += nwaves_total) {
+        const int64_t lo = max((int64_t)0, min(offsets[k], n_v));
+        const int64_t hi = max(lo, min(offsets[k + 1], n_v));
+        uint64_t top[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) top[q] = ~0ull;
+        if (hi > lo) {
+            const int64_t first = (lo / AM_CHUNK + k) * N, last = ((hi - 1) / AM_CHUNK + k + 1) * N;
+            for (int64_t i = first + lane; i < last; i += 64) list_insert(top, lists[i]);
+        }
+        const uint64_t v = list_pop(top, N, lane);
+        const int64_t mine = v == ~0ull ? -1 : (int64_t)(v & 0xffffffffull);
         if (lane < N) {
             const int64_t slot = k * N + lane;
             idx_out[slot] = mine;
@@ -363,8 +458,17 @@ __global__ __launch_bounds__(AM_WAVES * 64) void topn_preds_kernel(
 
 template <int K>
 static void launch_topn(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v,
-                        int N, int64_t *idx_out, float *val_out, hipStream_t s)
+                        int N, int64_t *idx_out, float *val_out, uint64_t *lists, hipStream_t s)
 {
+    if (lists) {
+        const int64_t chunks = (n_v + AM_CHUNK - 1) / AM_CHUNK;
+        hipLaunchKernelGGL((topn_chunks_kernel<K>), dim3((unsigned)((chunks + AM_WAVES - 1) / AM_WAVES)),
+                           dim3(AM_WAVES * 64), 0, s, pred, offsets, n_k, n_v, N, lists);
+        const int64_t blocks = std::min<int64_t>((n_k + AM_WAVES - 1) / AM_WAVES, 1 << 20);
+        hipLaunchKernelGGL((topn_merge_kernel<K>), dim3((unsigned)blocks), dim3(AM_WAVES * 64), 0, s,
+                           pred, offsets, n_k, n_v, N, (const uint64_t *)lists, idx_out, val_out);
+        return;
+    }
     const int64_t blocks = std::min<int64_t>((n_k + AM_WAVES - 1) / AM_WAVES, 1 << 20);
     if constexpr (K >= 8) {
         hipLaunchKernelGGL((topn_preds_kernel<K, TOPN_FAST>), dim3((unsigned)blocks),
@@ -377,16 +481,26 @@ static void launch_topn(const float *pred, const int64_t *offsets, int64_t n_k, 
     }
 }
 
+// Long segments on average take the chunked form, with its lists in a
+// stream-ordered scratch allocation freed after the merge.
 int launch_topn_preds(const float *pred, const int64_t *offsets, int64_t n_k, int64_t n_v,
                       int N, int64_t *idx_out, float *val_out, hipStream_t s)
 {
-    if (N <= 1) launch_topn<1>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
-    else if (N <= 2) launch_topn<2>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
-    else if (N <= 4) launch_topn<4>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
-    else if (N <= 8) launch_topn<8>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
-    else if (N <= 16) launch_topn<16>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
-    else launch_topn<32>(pred, offsets, n_k, n_v, N, idx_out, val_out, s);
-    ADV_LAUNCHED("topn_preds_kernel");
+    uint64_t *lists = nullptr;
+    if (n_v >= AM_LONG * n_k) {
+        const int64_t chunks = (n_v + AM_CHUNK - 1) / AM_CHUNK;
+        ADV_HIP(hipMallocAsync((void **)&lists, sizeof(uint64_t) * (size_t)(chunks + n_k) * N, s));
+    }
+    if (N <= 1) launch_topn<1>(pred, offsets, n_k, n_v, N, idx_out, val_out, lists, s);
+    else if (N <= 2) launch_topn<2>(pred, offsets, n_k, n_v, N, idx_out, val_out, lists, s);
+    else if (N <= 4) launch_topn<4>(pred, offsets, n_k, n_v, N, idx_out, val_out, lists, s);
+    else if (N <= 8) launch_topn<8>(pred, offsets, n_k, n_v, N, idx_out, val_out, lists, s);
+    else if (N <= 16) launch_topn<16>(pred, offsets, n_k, n_v, N, idx_out, val_out, lists, s);
+    else launch_topn<32>(pred, offsets, n_k, n_v, N, idx_out, val_out, lists, s);
+    const hipError_t le = hipGetLastError();
+    const hipError_t fe = lists ? hipFreeAsync(lists, s) : hipSuccess;
+    if (le != hipSuccess) return hip_fail(le, "topn_preds_kernel");
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
     return ADVISOR_OK;
 }
 

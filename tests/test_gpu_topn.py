@@ -112,6 +112,30 @@ def test_topn_preds_one_pass_segments(n):
     _check_values(idx, val, pred)
 
 
+@pytest.mark.parametrize("n", [1, 3, 10, 17, 32])
+def test_topn_preds_chunked_long_segments(n):
+    """Kernels of 16384 or more variants on average take the chunked form
+    (per-chunk lists, then a merge per kernel): segment ends on and off the
+    chunk boundaries, empty, all-NaN and short segments among long ones,
+    coarse values with ties spread over many chunks, against the oracle."""
+    rng = np.random.default_rng(90 + n)
+    nv = 1_200_000
+    pred = np.round(rng.standard_normal(nv), 1).astype(np.float32)
+    pred[rng.random(nv) < 0.01] = np.nan
+    cuts = [0, 7, 7, 4096, 4100, 8192, 150000, 150000, 150020, 600001, 600040, 1_000_000]
+    pred[150000:150020] = np.nan                      # an all-NaN segment
+    pred[[300000, 450000, 590000]] = -9.0             # ties across chunks
+    off = np.array(cuts + [nv], dtype=np.int64)
+    assert nv >= 16384 * (off.size - 1)
+    say("topn chunked N=%d n_k=%d" % (n, off.size - 1))
+    idx, val = _gpu_topn(pred, off, n)
+    assert np.array_equal(idx, oracle.topn(pred.astype(np.float64), off, n))
+    _check_values(idx, val, pred)
+    assert np.all(idx[[1, 6, 7]] == -1)
+    if n >= 3:
+        assert idx[8, :3].tolist() == [300000, 450000, 590000]
+
+
 def test_topn_preds_summit_worked_example():
     """The 84 printed Summit predictions of the Wilson Dslash variants: the
     predicted top ten, numbered 1..84 in order of measured runtime, with
