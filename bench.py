@@ -170,8 +170,19 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
     variants: 128 B per kernel) and writes 256 B of features and a 1-byte
     flag; the argmin reads a 4-byte prediction per variant and 8 B of
     offsets and writes 8 B of `best` per kernel; the top-10 list reads the
-    same and writes 10 x (8 B index + 4 B prediction) per kernel."""
+    same and writes 10 x (8 B index + 4 B prediction) per kernel. The two
+    selections also run on the same predictions cut into 64 long segments
+    (the chunked forms)."""
     nv, nk = vdd.shape[0], offd.shape[0] - 1
+    # the same predictions cut into 64 long segments (seeded cuts), which
+    # take the chunked argmin and top-N
+    g_cut = np.random.default_rng(91)
+    cuts_l = np.sort(g_cut.integers(1, nv, size=63))
+    off_l = torch.from_numpy(np.concatenate([[0], cuts_l, [nv]]).astype(np.int64)).to(vdd.device)
+    nk_l = 64
+    best_l = torch.empty(nk_l, dtype=torch.int64, device=vdd.device)
+    tidx_l = torch.empty((nk_l, 10), dtype=torch.int64, device=vdd.device)
+    tval_l = torch.empty((nk_l, 10), dtype=torch.float32, device=vdd.device)
     feat = torch.empty((nv, 32), dtype=torch.int64, device=vdd.device)
     inv = torch.empty(nv, dtype=torch.uint8, device=vdd.device)
     pred = torch.empty(nv, dtype=torch.float32, device=vdd.device).normal_()
@@ -186,7 +197,12 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
              nv * 4 + nk * 16 + 8),
             ("topn10_preds", lambda: adv.advisor_topn_preds(pred, offd, 10, idx_out=tidx,
                                                             val_out=tval),
-             nv * 4 + nk * (8 + 10 * 12) + 8)):
+             nv * 4 + nk * (8 + 10 * 12) + 8),
+            ("rank_preds_64_long_segments", lambda: adv.advisor_rank_preds(pred, off_l, best_out=best_l),
+             nv * 4 + nk_l * 16 + 8),
+            ("topn10_preds_64_long_segments",
+             lambda: adv.advisor_topn_preds(pred, off_l, 10, idx_out=tidx_l, val_out=tval_l),
+             nv * 4 + nk_l * (8 + 10 * 12) + 8)):
         for _ in range(2):
             fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -199,7 +215,7 @@ def stage_kernels(adv, torch, kdd, vdd, offd, steps):
         gbs = nbytes / (ms / 1e3) / 1e9
         out[name] = {"ms": ms, "bytes": nbytes, "achieved_gbs": gbs, "peak_gbs": PEAK_HBM_GBS,
                      "frac": gbs / PEAK_HBM_GBS}
-    del feat, inv, pred, best, tidx, tval
+    del feat, inv, pred, best, tidx, tval, off_l, best_l, tidx_l, tval_l
     # the method's integer steps on synthetic inputs of their own: variant
     # generation for 262,144 kernels of 1-4 loops (8 B of loop count read per
     # kernel, 8 B of offsets and 48 B per variant row written), and the data
