@@ -363,12 +363,14 @@ __device__ __forceinline__ void mma_group(const typename Geo<PL>::Vec *__restric
 #pragma unroll
         for (int i = 0; i < NBW; ++i) ring[U][i] = abase[((int64_t)i * KGROUPS + kg + PF) * 64];
     }
-    if constexpr (PL == PREC_BF16) {
-        // bf16: single-buffered B operands. Those of m-block j for group
-        // kg + 1 are read into bcur[j] as soon as group kg's multiplies by it
-        // are issued, which frees the registers of a second buffer (measured:
-        // 4-15% faster bf16 tiles; fp32 and fp8 tiles are as fast or faster
-        // with the double buffer below)
+    if constexpr (PL == PREC_BF16 || (PL == PREC_FP8 && MBW >= 4)) {
+        // bf16, and fp8 with four or more m-blocks: single-buffered B
+        // operands. Those of m-block j for group kg + 1 are read into bcur[j]
+        // as soon as group kg's multiplies by it are issued, which frees the
+        // registers of a second buffer (measured: 4-15% faster bf16 tiles;
+        // the 128-row fp8 512-wide tile stops spilling, 7.74 -> 7.62 ms;
+        // fp32 and the other fp8 tiles are as fast or faster with the double
+        // buffer below)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < MBW; ++j) {
